@@ -1,0 +1,224 @@
+/*
+ * simrank.h — C ABI of the MI355X (gfx950) single-source SimRank library.
+ *
+ * What it computes (Luo & Zhu, "Massively Parallel Single-Source SimRanks in
+ * o(log n) Rounds", arXiv 2304.04015):
+ *   - Problem (Section 2.2 and Algorithm 1's input/output): given a directed
+ *     graph G, a source s, decay c, error eps and failure probability delta,
+ *     return s_hat(s, u) for every node u with |s(s,u) - s_hat(s,u)| <= eps.
+ *   - Estimator (Lemma 2 and the Monte Carlo paragraph of Section 2.2): pair
+ *     the j-th sqrt(c)-walk from s with the j-th sqrt(c)-walk from u on the
+ *     reversed graph, j < R; s_hat(s,u) = (number of pairs that meet) / R.
+ *     Two walks meet when they are on the same node at the same step i >= 0;
+ *     a pair counts once however often its walks coincide (Section 4.4).
+ *   - Walks are truncated at L steps (Algorithm 1 truncates at log_{1/sqrt c} n;
+ *     Appendix B.4 extends the cap); R follows from Hoeffding's inequality
+ *     (Section 3; Appendix B.3/B.4).
+ *   - Stitched mode: long walks are formed from short per-node walk segments
+ *     joined by pointer doubling, the one-GPU counterpart of the few-round walk
+ *     sampler of Theorem 2 / Section 4.1.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low
+ * word, seed high word) and counter = (node, walk, step, domain); domain 0 =
+ * step of a walk, 1 = step of a pool segment, 2 = pool slot entered after the
+ * private head, 3 = successor slot of a segment.  At step t (1-based) a walk
+ * draws x; it stops if x0 >= T = floor(sqrt(c) * 2^32) or its node has no
+ * in-neighbour, else moves to in-neighbour number floor(x1 * deg / 2^32) of the
+ * in-edge row (row order as passed to simrank_load_graph).  Results are a pure
+ * function of (graph, query) and never depend on launch shape or timing.
+ *
+ * Conventions for every call:
+ *   - Return 0 (SIMRANK_OK) or a SIMRANK_E* code; on error nothing is written
+ *     to caller outputs and simrank_last_error() describes the failure.
+ *   - "host" pointers are ordinary CPU memory, read or written synchronously;
+ *     "device" pointers are HIP device memory on the graph's device.
+ *   - A graph (and its index, once built) is immutable and may be queried from
+ *     several threads at once; a workspace is used by one call at a time.
+ */
+#ifndef SIMRANK_H
+#define SIMRANK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIMRANK_OK 0
+#define SIMRANK_EINVAL 1   /* bad argument: NULL, range, malformed CSR, eps <= c^(L+1) ... */
+#define SIMRANK_ENOMEM 2   /* device or host allocation failed, or admission refused */
+#define SIMRANK_EDEVICE 3  /* a HIP call failed */
+#define SIMRANK_ESTATE 4   /* call not valid in the object's state (e.g. no index built) */
+
+#define SIMRANK_MODE_PLAIN 0     /* every walk generated step by step */
+#define SIMRANK_MODE_STITCHED 1  /* private head + tail read from the segment index */
+
+typedef struct simrank_graph simrank_graph;         /* opaque; device resident */
+typedef struct simrank_workspace simrank_workspace; /* opaque; per-call scratch */
+
+/* One single-source query (Algorithm 1 input: G, s, c, delta, eps). */
+typedef struct simrank_query {
+    int32_t s;           /* source node, 0 <= s < n */
+    int32_t graph;       /* simrank_batch only: index into its graph array */
+    double c;            /* decay factor, 0 < c < 1 */
+    double eps;          /* absolute error target, c^(L+1) < eps < 1 */
+    double delta;        /* failure probability, 0 < delta < 1 */
+    uint64_t seed;       /* Philox key of the query's walks */
+    int32_t walk_cap;    /* L, the truncation length; 0 selects 64; at most 255 */
+    int32_t R_override;  /* walks per node; 0 selects the Hoeffding count */
+    int32_t mode;        /* SIMRANK_MODE_PLAIN or SIMRANK_MODE_STITCHED */
+    int32_t union_bound; /* 0: delta per node; 1: delta for all n nodes at once */
+} simrank_query;
+
+/* Derived per-query constants. */
+typedef struct simrank_params {
+    int32_t R;   /* walks per node: ceil(ln(2/delta) / (2 (eps - c^(L+1))^2)),
+                    with 2n/delta in place of 2/delta when union_bound is set */
+    int32_t L;   /* walk cap */
+    uint32_t T;  /* continue threshold floor(sqrt(c) 2^32), at most 2^32 - 1 */
+    int32_t reserved;
+} simrank_params;
+
+/* Work and timing of one call (filled by the synchronous calls). */
+typedef struct simrank_stats {
+    uint64_t pairs;        /* (v, j) pairs with v != s the query covers: (n - 1) * R */
+    uint64_t pairs_walked; /* pairs whose walk had to be generated (v has in-edges,
+                              the source walk j has at least one step) */
+    uint64_t moves;        /* walk steps taken along in-edges by the meet kernel */
+    uint64_t draws;        /* Philox draws made by the meet kernel */
+    uint64_t meets;        /* pairs that met (sum of counts minus R for s) */
+    uint64_t tail_steps;   /* stitched mode: steps read from the segment index */
+    uint64_t source_moves; /* steps of the R source walks */
+    double ms;             /* device time of the call, from HIP events */
+    double meet_ms;        /* device time of the fused walk + meet kernel alone */
+    int32_t R, L;
+    uint32_t T;
+    int32_t reserved;
+} simrank_stats;
+
+/* Stitched-walk index parameters. */
+typedef struct simrank_index_params {
+    int32_t seg_log2;    /* k: segments have 2^k steps; 0 <= k <= 6; default 3 */
+    int32_t reserved;
+    double kappa;        /* pool size P(y) = ceil(kappa * dbar(y)), dbar(y) = number
+                            of in-edge rows that list y; 0 < kappa < 1e6 */
+    double c;            /* decay of the segments' walks; stitched queries must use it */
+    uint64_t seed;       /* Philox key of the segments and successor picks */
+} simrank_index_params;
+
+typedef struct simrank_index_summary {
+    int64_t segments;    /* sum over y of P(y) */
+    int64_t bytes;       /* device bytes held by the index */
+    int32_t seg_log2;
+    int32_t levels;      /* doubling rounds run: log2(ceil(max cap / 2^k)) */
+    double build_ms;     /* device time of the last build */
+    uint64_t build_moves;/* steps taken while building the segments */
+} simrank_index_summary;
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Copies the in-edge CSR of G to the current HIP device and builds the
+ * library's gather layout.  Row v, in_src[in_off[v] .. in_off[v+1]), lists the
+ * in-neighbours of v, I(v) (Eq. 1; Algorithm 1 "reverse the edges").
+ * in_off: host int32[n+1], in_off[0] = 0, non-decreasing, in_off[n] = m.
+ * in_src: host int32[m], each in [0, n).  Duplicates are allowed and then
+ * weigh the neighbour pick.  1 <= n, 0 <= m < 2^31 - n.  The caller keeps
+ * ownership of its arrays.  *g_out receives a handle owned by the library
+ * until simrank_free_graph.  EINVAL on a malformed CSR. */
+int simrank_load_graph(int32_t n, int64_t m, const int32_t *in_off, const int32_t *in_src,
+                       simrank_graph **g_out);
+
+/* Frees the graph, its index and its device memory.  NULL is a no-op. */
+int simrank_free_graph(simrank_graph *g);
+
+/* n, m, number of nodes with at least one in-neighbour, device bytes held. */
+int simrank_graph_info(const simrank_graph *g, int32_t *n, int64_t *m, int32_t *n_active,
+                       int64_t *device_bytes);
+
+/* ------------------------------------------------------------ parameters */
+
+/* Fills *out from q (walk cap default, R from Hoeffding, T).  EINVAL when an
+ * argument is out of range, when eps <= c^(L+1) (the truncation bias
+ * S - S_L <= c^(L+1) would use up the error budget), or when R > 2^24. */
+int simrank_derive_params(const simrank_query *q, int32_t n, simrank_params *out);
+
+/* --------------------------------------------------------------- queries */
+
+/* Plain query with seed 0, cap 64, per-node delta.  out: host double[n],
+ * out[u] = s_hat(s, u), out[s] = 1.  Synchronous. */
+int simrank_single_source(const simrank_graph *g, int32_t s, double c, double eps, double delta,
+                          double *out);
+
+/* Full query.  out_host: host double[n] or NULL; counts_host: host uint32[n]
+ * or NULL (counts[u] = meeting pairs, counts[s] = R); st_opt may be NULL.
+ * Synchronous; allocates and frees its own workspace. */
+int simrank_single_source_ex(const simrank_graph *g, const simrank_query *q, double *out_host,
+                             uint32_t *counts_host, simrank_stats *st_opt);
+
+/* Workspace for asynchronous queries on one graph: scratch for source walks
+ * (R x L) and counters, sized for queries with R <= max_R and L <= max_L. */
+int simrank_workspace_create(const simrank_graph *g, int32_t max_R, int32_t max_L,
+                             simrank_workspace **ws_out);
+int simrank_workspace_free(simrank_workspace *ws);
+
+/* Enqueues a whole query on `stream` (a hipStream_t; NULL = default stream)
+ * and returns without waiting.  out_dev: device double[n] or NULL;
+ * counts_dev: device uint32[n], required (caller-owned, overwritten).  No
+ * allocation, no host synchronisation.  The workspace must not be reused until
+ * the stream has passed this call. */
+int simrank_single_source_async(const simrank_graph *g, const simrank_query *q,
+                                simrank_workspace *ws, double *out_dev, uint32_t *counts_dev,
+                                void *stream);
+
+/* Waits for the workspace's last call and fills *st (moves, draws, meets...;
+ * ms = device time between the call's first and last kernel). */
+int simrank_workspace_stats(simrank_workspace *ws, simrank_stats *st);
+
+/* Materialises walks (v[i], j[i]) for i < count under query q (seed, c, cap,
+ * mode): paths host int32[count][L+1] with -1 after the walk's end, lens host
+ * int32[count] (moves made).  For parity checks and inspection. */
+int simrank_walks(const simrank_graph *g, const simrank_query *q, const int32_t *v,
+                  const uint32_t *j, int64_t count, int32_t *paths, int32_t *lens);
+
+/* ----------------------------------------------------------------- index */
+
+/* Builds the stitched-walk index on the graph (replacing any earlier one):
+ * per-node segment pools, one 2^k-step walk per slot keyed (y, i, t, 1),
+ * successor picks keyed (y, i, 0, 3), and long walks of up to 64 steps by
+ * pointer doubling.  Synchronous.  ENOMEM if it does not fit. */
+int simrank_build_index(simrank_graph *g, const simrank_index_params *p);
+int simrank_index_info(const simrank_graph *g, simrank_index_summary *out);
+
+/* Reads index entries for inspection.  For each slot sigma[i] (0 <= sigma[i] <
+ * segments): nodes host int32[count][2^k] receives the segment's positions
+ * 1..len as node ids (-1 padded), lens host int32[count] its number of moves,
+ * succ host int64[count] its successor slot (-1 if none), and chain_opt (host
+ * int64[count][64 / 2^k], may be NULL) the slots of the long walk that starts
+ * at sigma[i]: sigma[i], succ(sigma[i]), succ^2(sigma[i]), ..., -1 padded. */
+int simrank_index_read(const simrank_graph *g, const int64_t *sigma, int64_t count,
+                       int32_t *nodes, int32_t *lens, int64_t *succ, int64_t *chain_opt);
+
+/* ----------------------------------------------------------------- batch */
+
+/* Runs nq queries over ngraphs graphs (qs[i].graph selects the graph) in one
+ * persistent launch per phase.  outs[i]: host double[n of its graph] or NULL;
+ * counts_opt[i] (may be NULL, or entries NULL): host uint32[n].  Each query's
+ * result equals what simrank_single_source_ex returns for it alone. */
+int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs, const simrank_query *qs,
+                  int32_t nq, double *const *outs, uint32_t *const *counts_opt,
+                  simrank_stats *st_opt);
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *simrank_last_error(void);
+
+/* Library version string. */
+const char *simrank_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMRANK_H */

@@ -1,0 +1,146 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "simrank.h"
+
+namespace srk {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+int fail(int code, const std::string &msg);
+
+#define SRK_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::srk::fail(SIMRANK_EDEVICE, std::string(#expr) + ": " +                \
+                                                    hipGetErrorString(e_));                \
+    } while (0)
+
+// --------------------------------------------------------------- constants
+constexpr uint32_t NIL = 0xffffffffu;   // no successor / no segment
+constexpr int MAX_CAP = 255;            // walk cap limit (lengths fit a byte)
+constexpr int MAX_STITCH_CAP = 64;      // stitched walks: long walks span 64 steps
+constexpr int64_t MAX_R = 1 << 24;
+
+// Meet-kernel tiling of the compacted source walks (see query.hip).
+constexpr int TILE_J = 1024;            // source walks per tile, at most
+constexpr int TILE_NODES = 4096;        // LDS node slots per tile
+constexpr int MEET_BLOCK = 512;         // threads per block of the meet kernel
+constexpr int MEET_VB = 256;            // nodes v per work unit
+
+// ------------------------------------------------------------ device graph
+// Gather layout of the reversed graph.  Every node v owns the edge slots
+// [o(v), o(v) + max(deg(v), 1)) of E; E[o(v) + k] describes the k-th
+// in-neighbour u of v by (o(u), deg(u)), so one 8-byte gather moves a walk and
+// already yields the row of the node it lands on.  o() is strictly increasing,
+// so it identifies nodes; nodes without in-neighbours own one unused slot.
+struct Index;
+
+struct Graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    int64_t m_slots = 0;          // sum over v of max(deg(v), 1)
+    int32_t n_active = 0;         // nodes with deg >= 1
+    int32_t max_deg = 0;
+    uint2 *nodes = nullptr;       // [n]     (o(v), deg(v))
+    uint2 *E = nullptr;           // [m_slots]
+    uint32_t *node_of = nullptr;  // [m_slots] node id owning slot o (valid at o(v))
+    int32_t *active = nullptr;    // [n_active] nodes with deg >= 1, ascending
+    hipStream_t stream = nullptr; // stream of the synchronous calls
+    Index *index = nullptr;
+    int64_t bytes = 0;
+};
+
+// Stitched-walk index (see index.hip).
+struct Index {
+    int32_t seg_log2 = 3;
+    int32_t seg_len = 8;          // 2^k
+    int32_t width = 8;            // long-walk width in segments: 64 / 2^k
+    int32_t levels = 3;           // doubling rounds: log2(width)
+    double kappa = 1.0;
+    double c = 0.6;               // decay of the segments' walks
+    uint32_t T = 0;               // their continue threshold
+    uint64_t seed = 0;
+    int64_t segments = 0;
+    int64_t *pool_off = nullptr;  // [n+1]
+    uint32_t *seg = nullptr;      // [segments][seg_len] o() of positions 1..len, NIL after
+    uint8_t *seg_lens = nullptr;  // [segments]
+    uint32_t *succ = nullptr;     // [segments] successor slot or NIL
+    uint32_t *chain = nullptr;    // [segments][width] slots of the long walk from sigma
+    int64_t bytes = 0;
+    double build_ms = 0;
+    uint64_t build_moves = 0;
+};
+
+// Per-query scratch.
+struct Workspace {
+    const Graph *g = nullptr;
+    int32_t max_R = 0, max_L = 0;
+    uint32_t *sw = nullptr;        // [max_R][max_L] source walk positions 1..L (o values)
+    uint8_t *slen = nullptr;       // [max_R]
+    uint32_t *jj = nullptr;        // [max_R] walk index of compact entry k
+    uint32_t *joff = nullptr;      // [max_R + 1] start of entry k in swc
+    uint32_t *swc = nullptr;       // [max_R * max_L] compact positions
+    uint32_t *tiles = nullptr;     // [max tiles + 1] first compact entry of each tile
+    uint32_t *meta = nullptr;      // [8]: R1, total nodes, n_tiles, unit cursor, ...
+    unsigned long long *counters = nullptr;  // [8] stats
+    int32_t max_tiles = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;     // around the whole query
+    hipEvent_t evm0 = nullptr, evm1 = nullptr;   // around the meet kernel
+    hipStream_t last_stream = nullptr;
+    simrank_params last_params{};
+    int32_t last_n = 0;
+    bool pending = false;
+};
+
+enum Counter : int {
+    C_MOVES = 0, C_DRAWS = 1, C_MEETS = 2, C_TAIL = 3, C_PAIRS = 4, C_SRC_MOVES = 5,
+    C_UNITS = 6, C_SPARE = 7
+};
+
+// ----------------------------------------------------------------- helpers
+int device_alloc(void **p, size_t bytes, int64_t *acct);
+void device_free(void *p);
+
+// Device-wide scans (scan.hip).  Exclusive sum of `in` (n values) into `out`
+// (n values); returns the total in *total_dev (device scalar).  Temp storage
+// is allocated and released by the call.
+int scan_exclusive_u32_to_i64(const uint32_t *in, int64_t n, int64_t *out, int64_t *total_dev,
+                              hipStream_t st);
+int scan_exclusive_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total_dev,
+                       hipStream_t st);
+// Inclusive running maximum of u32 values, in place.
+int scan_inclusive_max_u32(uint32_t *data, int64_t n, hipStream_t st);
+
+// Queries (query.hip).
+int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mode);
+int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                  Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st);
+int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws);
+void workspace_release(Workspace *ws);
+
+// Index (index.hip).
+void index_free(Index *ix);
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > 0x7fffffff) b = 0x7fffffff;
+    return (unsigned)b;
+}
+
+uint32_t continue_threshold(double c);
+
+}  // namespace srk
+
+// The opaque handles of the C ABI are the internal objects.
+struct simrank_graph : srk::Graph {};
+struct simrank_workspace : srk::Workspace {};

@@ -1,0 +1,356 @@
+// Stitched-walk index: per-node pools of short walk segments, joined into
+// long walks by pointer doubling — the single-GPU counterpart of building
+// long walks from short ones in few rounds (Theorem 2, Section 4.1).
+//
+//   P(y)      = ceil(kappa * dbar(y)), dbar(y) = number of in-edge rows that
+//               list y (walks arrive at y along those edges); pools are
+//               sampled with replacement, so they never run out
+//   slot sigma = pool_off[y] + i, i < P(y): a sqrt(c)-walk of at most 2^k
+//               steps from y keyed (y, i, t, 1) under the index seed
+//   succ(sigma) = pool_off[z] + pick(draw(y, i, 0, 3).x0, P(z)) if the
+//               segment made all 2^k moves and ended at z, else none
+//   chain[sigma][m] = succ^m(sigma) for m < width = 64 / 2^k, built in
+//               log2(width) doubling rounds: round r copies the first 2^r
+//               entries of chain[J_r(sigma)] behind those of sigma, with
+//               J_0 = succ and J_{r+1} = J_r o J_r.
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace srk {
+namespace {
+
+__global__ void k_fill_u32i(uint32_t *__restrict__ p, int64_t n, uint32_t val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+// dbar(y): one thread per edge slot; dummy slots of nodes without in-edges
+// carry o = NIL.
+__global__ void k_dbar(const uint2 *__restrict__ E, const uint32_t *__restrict__ node_of,
+                       int64_t m_slots, uint32_t *__restrict__ dbar) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m_slots) return;
+    const uint32_t o = E[e].x;
+    if (o != NIL) atomicAdd(&dbar[node_of[o]], 1u);
+}
+
+__global__ void k_pool_sizes(const uint32_t *__restrict__ dbar, int32_t n, double kappa,
+                             int64_t *__restrict__ P, uint32_t *__restrict__ too_big) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    const double p = ceil(kappa * (double)dbar[y]);
+    if (p >= 4294967295.0) {
+        *too_big = 1u;
+        P[y] = 0;
+    } else {
+        P[y] = (int64_t)p;
+    }
+}
+
+__global__ void k_owner_scatter(const int64_t *__restrict__ pool_off, const int64_t *__restrict__ P,
+                                int32_t n, uint32_t *__restrict__ owner) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    if (P[y] > 0) owner[pool_off[y]] = (uint32_t)y;
+}
+
+struct SegArgs {
+    const uint2 *nodes;
+    const uint2 *E;
+    const uint32_t *node_of;
+    const int64_t *pool_off;
+    const uint32_t *owner;
+    uint32_t *seg;
+    uint8_t *seg_lens;
+    uint32_t *succ;
+    uint32_t *chain;
+    unsigned long long *moves;
+    PhiloxKey key;
+    uint32_t T;
+    int32_t seg_len, width;
+    int64_t segments;
+};
+
+__global__ __launch_bounds__(256) void k_segments(SegArgs a) {
+    const int64_t sigma = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t len = 0;
+    if (sigma < a.segments) {
+        const uint32_t y = a.owner[sigma];
+        const uint32_t i = (uint32_t)(sigma - a.pool_off[y]);
+        uint32_t *row = a.seg + (size_t)sigma * a.seg_len;
+        uint2 cur = a.nodes[y];
+        for (int32_t t = 1; t <= a.seg_len; ++t) {
+            const uint4 x = philox4x32_10(y, i, (uint32_t)t, DOM_SEGMENT, a.key);
+            if (x.x >= a.T || cur.y == 0) break;
+            cur = a.E[cur.x + pick32(x.y, cur.y)];
+            row[t - 1] = cur.x;
+            len = (uint32_t)t;
+        }
+        for (int32_t t = (int32_t)len; t < a.seg_len; ++t) row[t] = NIL;
+        a.seg_lens[sigma] = (uint8_t)len;
+        uint32_t nx = NIL;
+        if ((int32_t)len == a.seg_len) {
+            const uint32_t z = a.node_of[cur.x];
+            const int64_t b = a.pool_off[z];
+            const int64_t P = a.pool_off[z + 1] - b;
+            const uint4 x = philox4x32_10(y, i, 0u, DOM_SUCC, a.key);
+            nx = (uint32_t)(b + (int64_t)pick64(x.x, (uint64_t)P));
+        }
+        a.succ[sigma] = nx;
+        a.chain[(size_t)sigma * a.width] = (uint32_t)sigma;
+    }
+    unsigned long long m = len;
+    for (int d = 32; d > 0; d >>= 1) m += __shfl_xor(m, d, 64);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(a.moves, m);
+}
+
+// Round r of pointer doubling: chain[s][h + i] = chain[J[s]][i] for i < h = 2^r,
+// Jn[s] = J[J[s]].  Reads touch columns < h and writes columns >= h, so the
+// round can update chain in place.
+__global__ __launch_bounds__(256) void k_double(uint32_t *__restrict__ chain,
+                                                const uint32_t *__restrict__ J,
+                                                uint32_t *__restrict__ Jn, int64_t segments,
+                                                int32_t width, int32_t h) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= segments) return;
+    const uint32_t a = J[s];
+    uint32_t *dst = chain + (size_t)s * width + h;
+    if (a == NIL) {
+        for (int32_t i = 0; i < h; ++i) dst[i] = NIL;
+        if (Jn) Jn[s] = NIL;
+    } else {
+        const uint32_t *src = chain + (size_t)a * width;
+        for (int32_t i = 0; i < h; ++i) dst[i] = src[i];
+        if (Jn) Jn[s] = J[a];
+    }
+}
+
+struct ReadArgs {
+    const Index *ix;
+    const uint32_t *node_of;
+    const int64_t *sigma;
+    int64_t count;
+    int32_t *nodes;
+    int32_t *lens;
+    int64_t *succ;
+    int64_t *chain;
+};
+
+__global__ void k_index_read(const uint32_t *__restrict__ node_of, const uint32_t *__restrict__ seg,
+                             const uint8_t *__restrict__ seg_lens, const uint32_t *__restrict__ succ,
+                             const uint32_t *__restrict__ chain, int32_t seg_len, int32_t width,
+                             const int64_t *__restrict__ sig, int64_t count,
+                             int32_t *__restrict__ out_nodes, int32_t *__restrict__ out_lens,
+                             int64_t *__restrict__ out_succ, int64_t *__restrict__ out_chain) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t s = sig[i];
+    const int32_t l = seg_lens[s];
+    out_lens[i] = l;
+    for (int32_t t = 0; t < seg_len; ++t)
+        out_nodes[i * seg_len + t] = t < l ? (int32_t)node_of[seg[s * seg_len + t]] : -1;
+    const uint32_t nx = succ[s];
+    out_succ[i] = nx == NIL ? -1 : (int64_t)nx;
+    if (out_chain)
+        for (int32_t m = 0; m < width; ++m) {
+            const uint32_t c = chain[s * width + m];
+            out_chain[i * width + m] = c == NIL ? -1 : (int64_t)c;
+        }
+}
+
+}  // namespace
+
+void index_free(Index *ix) {
+    if (!ix) return;
+    device_free(ix->pool_off);
+    device_free(ix->seg);
+    device_free(ix->seg_lens);
+    device_free(ix->succ);
+    device_free(ix->chain);
+    *ix = Index{};
+}
+
+}  // namespace srk
+
+using namespace srk;
+
+
+extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params *p) {
+    clear_error();
+    if (!g || !p) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (p->seg_log2 < 0 || p->seg_log2 > 6) return fail(SIMRANK_EINVAL, "seg_log2 must lie in [0, 6]");
+    if (!(p->kappa > 0.0) || !(p->kappa < 1e6)) return fail(SIMRANK_EINVAL, "kappa must lie in (0, 1e6)");
+    if (!(p->c > 0.0 && p->c < 1.0)) return fail(SIMRANK_EINVAL, "c must lie in (0, 1)");
+    SRK_HIP(hipSetDevice(g->device));
+    hipStream_t st = g->stream;
+    SRK_HIP(hipStreamSynchronize(st));
+    if (g->index) {
+        index_free(g->index);
+        delete g->index;
+        g->index = nullptr;
+    }
+    Index *ix = new Index();
+    ix->seg_log2 = p->seg_log2;
+    ix->seg_len = 1 << p->seg_log2;
+    ix->width = MAX_STITCH_CAP / ix->seg_len;
+    ix->levels = 0;
+    while ((1 << ix->levels) < ix->width) ++ix->levels;
+    ix->kappa = p->kappa;
+    ix->c = p->c;
+    ix->T = continue_threshold(p->c);
+    ix->seed = p->seed;
+    const int32_t n = g->n;
+    int rc = SIMRANK_OK;
+    uint32_t *dbar = nullptr, *owner = nullptr, *Ja = nullptr, *Jb = nullptr, *flag = nullptr;
+    int64_t *P = nullptr, *tot = nullptr;
+    unsigned long long *moves = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        device_free(dbar); device_free(owner); device_free(Ja); device_free(Jb);
+        device_free(flag); device_free(P); device_free(tot); device_free(moves);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    auto bail = [&](int code) {
+        cleanup();
+        index_free(ix);
+        delete ix;
+        return code;
+    };
+#define IX_TRY(x)                         \
+    do {                                  \
+        rc = (x);                         \
+        if (rc != SIMRANK_OK) return bail(rc); \
+    } while (0)
+#define IX_HIP(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess)                                                             \
+            return bail(fail(SIMRANK_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+    IX_HIP(hipEventCreate(&e0));
+    IX_HIP(hipEventCreate(&e1));
+    IX_TRY(device_alloc((void **)&dbar, 4 * (size_t)n, nullptr));
+    IX_TRY(device_alloc((void **)&P, 8 * (size_t)n, nullptr));
+    IX_TRY(device_alloc((void **)&tot, 8 * 2, nullptr));
+    IX_TRY(device_alloc((void **)&flag, 4, nullptr));
+    IX_TRY(device_alloc((void **)&moves, 8, nullptr));
+    IX_TRY(device_alloc((void **)&ix->pool_off, 8 * ((size_t)n + 1), &ix->bytes));
+    IX_HIP(hipEventRecord(e0, st));
+    k_fill_u32i<<<1024, 256, 0, st>>>(dbar, n, 0u);
+    k_fill_u32i<<<1, 64, 0, st>>>(flag, 1, 0u);
+    k_fill_u32i<<<1, 64, 0, st>>>((uint32_t *)moves, 2, 0u);
+    k_dbar<<<grid_for(g->m_slots, 256), 256, 0, st>>>(g->E, g->node_of, g->m_slots, dbar);
+    k_pool_sizes<<<grid_for(n, 256), 256, 0, st>>>(dbar, n, p->kappa, P, flag);
+    IX_TRY(scan_exclusive_i64(P, n, ix->pool_off, tot, st));
+    IX_HIP(hipMemcpyAsync(ix->pool_off + n, tot, 8, hipMemcpyDeviceToDevice, st));
+    int64_t total = 0;
+    uint32_t too_big = 0;
+    IX_HIP(hipMemcpyAsync(&total, tot, 8, hipMemcpyDeviceToHost, st));
+    IX_HIP(hipMemcpyAsync(&too_big, flag, 4, hipMemcpyDeviceToHost, st));
+    IX_HIP(hipStreamSynchronize(st));
+    if (too_big || total >= (int64_t)NIL)
+        return bail(fail(SIMRANK_EINVAL, "pool sizes exceed 2^32 - 1 segments"));
+    ix->segments = total;
+    const int64_t S = total > 0 ? total : 1;
+    IX_TRY(device_alloc((void **)&ix->seg, 4 * (size_t)S * ix->seg_len, &ix->bytes));
+    IX_TRY(device_alloc((void **)&ix->seg_lens, (size_t)S, &ix->bytes));
+    IX_TRY(device_alloc((void **)&ix->succ, 4 * (size_t)S, &ix->bytes));
+    IX_TRY(device_alloc((void **)&ix->chain, 4 * (size_t)S * ix->width, &ix->bytes));
+    IX_TRY(device_alloc((void **)&owner, 4 * (size_t)S, nullptr));
+    if (ix->levels > 1) {
+        IX_TRY(device_alloc((void **)&Ja, 4 * (size_t)S, nullptr));
+        IX_TRY(device_alloc((void **)&Jb, 4 * (size_t)S, nullptr));
+    }
+    if (total > 0) {
+        k_fill_u32i<<<2048, 256, 0, st>>>(owner, total, 0u);
+        k_owner_scatter<<<grid_for(n, 256), 256, 0, st>>>(ix->pool_off, P, n, owner);
+        IX_TRY(scan_inclusive_max_u32(owner, total, st));
+        SegArgs sa{g->nodes, g->E, g->node_of, ix->pool_off, owner, ix->seg, ix->seg_lens,
+                   ix->succ, ix->chain, moves, make_key(p->seed), ix->T, ix->seg_len, ix->width,
+                   total};
+        k_segments<<<grid_for(total, 256), 256, 0, st>>>(sa);
+        const uint32_t *J = ix->succ;
+        for (int32_t r = 0; r < ix->levels; ++r) {
+            uint32_t *Jn = (r + 1 < ix->levels) ? ((r & 1) ? Jb : Ja) : nullptr;
+            k_double<<<grid_for(total, 256), 256, 0, st>>>(ix->chain, J, Jn, total, ix->width,
+                                                           1 << r);
+            J = Jn;
+        }
+        IX_HIP(hipGetLastError());
+    }
+    IX_HIP(hipEventRecord(e1, st));
+    unsigned long long mv = 0;
+    IX_HIP(hipMemcpyAsync(&mv, moves, 8, hipMemcpyDeviceToHost, st));
+    IX_HIP(hipStreamSynchronize(st));
+    float ms = 0.f;
+    IX_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ix->build_ms = ms;
+    ix->build_moves = mv;
+    cleanup();
+    g->index = ix;
+    return SIMRANK_OK;
+#undef IX_TRY
+#undef IX_HIP
+}
+
+extern "C" int simrank_index_info(const simrank_graph *g, simrank_index_summary *out) {
+    clear_error();
+    if (!g || !out) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (!g->index) return fail(SIMRANK_ESTATE, "no index built");
+    const Index *ix = g->index;
+    out->segments = ix->segments;
+    out->bytes = ix->bytes;
+    out->seg_log2 = ix->seg_log2;
+    out->levels = ix->levels;
+    out->build_ms = ix->build_ms;
+    out->build_moves = ix->build_moves;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_index_read(const simrank_graph *g, const int64_t *sigma, int64_t count,
+                                  int32_t *nodes, int32_t *lens, int64_t *succ,
+                                  int64_t *chain_opt) {
+    clear_error();
+    if (!g || (count > 0 && (!sigma || !nodes || !lens || !succ)))
+        return fail(SIMRANK_EINVAL, "NULL argument");
+    if (!g->index) return fail(SIMRANK_ESTATE, "no index built");
+    const Index *ix = g->index;
+    for (int64_t i = 0; i < count; ++i)
+        if (sigma[i] < 0 || sigma[i] >= ix->segments)
+            return fail(SIMRANK_EINVAL, "slot out of range");
+    if (count <= 0) return SIMRANK_OK;
+    SRK_HIP(hipSetDevice(g->device));
+    hipStream_t st = g->stream;
+    int64_t *dsig = nullptr, *dsucc = nullptr, *dchain = nullptr;
+    int32_t *dnodes = nullptr, *dlens = nullptr;
+    int rc = device_alloc((void **)&dsig, 8 * (size_t)count, nullptr);
+    if (!rc) rc = device_alloc((void **)&dsucc, 8 * (size_t)count, nullptr);
+    if (!rc) rc = device_alloc((void **)&dnodes, 4 * (size_t)count * ix->seg_len, nullptr);
+    if (!rc) rc = device_alloc((void **)&dlens, 4 * (size_t)count, nullptr);
+    if (!rc && chain_opt) rc = device_alloc((void **)&dchain, 8 * (size_t)count * ix->width, nullptr);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(dsig, sigma, 8 * (size_t)count, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            k_index_read<<<grid_for(count, 256), 256, 0, st>>>(
+                g->node_of, ix->seg, ix->seg_lens, ix->succ, ix->chain, ix->seg_len, ix->width,
+                dsig, count, dnodes, dlens, dsucc, dchain);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nodes, dnodes, 4 * (size_t)count * ix->seg_len,
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(lens, dlens, 4 * (size_t)count, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(succ, dsucc, 8 * (size_t)count, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && chain_opt)
+            e = hipMemcpyAsync(chain_opt, dchain, 8 * (size_t)count * ix->width,
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    device_free(dsig); device_free(dsucc); device_free(dnodes); device_free(dlens);
+    device_free(dchain);
+    return rc;
+}

@@ -1,0 +1,824 @@
+// Single-source query: source walks, their compaction into LDS tiles, the
+// fused walk + meet + count kernel, and the estimate.
+//
+// Method (Section 2.2; Lemma 2; Section 3.2 pairing): walk j of the source s
+// is paired with walk j of every node v, j < R; the pair meets if the two
+// walks are on the same node at the same step; s_hat(s, v) = meets / R.
+//
+// The meet kernel generates walk (v, j) only as far as it can still meet walk
+// (s, j): it stops at the first meeting step (a pair counts once, Section 4.4),
+// when walk (v, j) stops, and when walk (s, j) has no later position.  This
+// reads exactly the positions the meet test compares, so the counts equal
+// those of full walks, while a pair costs about sum_t c^t = c / (1 - c) moves.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace srk {
+namespace {
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_query_init(uint32_t *__restrict__ cnt, int32_t n, uint32_t *__restrict__ meta,
+                             unsigned long long *__restrict__ counters) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 8) {
+        meta[i] = 0u;
+        counters[i] = 0ull;
+    }
+    for (int64_t v = i; v < n; v += (int64_t)gridDim.x * blockDim.x) cnt[v] = 0u;
+}
+
+// s_hat(s, v) = cnt[v] / R; the pair (s, s) meets at step 0 for every j.
+__global__ void k_estimate(uint32_t *__restrict__ cnt, double *__restrict__ out, int32_t n,
+                           int32_t R, int32_t s) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (v == s) cnt[v] = (uint32_t)R;
+    if (out) out[v] = (v == s) ? 1.0 : (double)cnt[v] / (double)R;
+}
+
+// --------------------------------------------------------- stitched tails
+
+struct IndexView {
+    const uint32_t *node_of;
+    const int64_t *pool_off;
+    const uint32_t *seg;
+    const uint8_t *seg_lens;
+    const uint32_t *chain;
+    int32_t seg_len, width;
+};
+
+// Slot entered by walk (v, j) whose private head ended at node y
+// (counter (v, j, 0, 2)).
+__device__ __forceinline__ uint32_t entry_slot(const IndexView &ix, PhiloxKey key, uint32_t v,
+                                               uint32_t j, uint32_t y) {
+    const int64_t b = ix.pool_off[y];
+    const int64_t P = ix.pool_off[y + 1] - b;
+    const uint4 x = philox4x32_10(v, j, 0u, DOM_ENTRY, key);
+    return (uint32_t)(b + (int64_t)pick64(x.x, (uint64_t)P));
+}
+
+// ------------------------------------------------------------ source walks
+
+struct SrcArgs {
+    const uint2 *nodes;
+    const uint2 *E;
+    IndexView ix;
+    uint32_t *sw;        // [R][L]
+    uint8_t *slen;       // [R]
+    unsigned long long *counters;
+    PhiloxKey key;
+    uint32_t T;
+    int32_t R, L, s;
+};
+
+// Walk (s, j) for j < R: positions 1..len as o() values.
+template <bool STITCHED>
+__global__ __launch_bounds__(256) void k_source_walks(SrcArgs a) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t moves = 0, tail = 0;
+    if (j < a.R) {
+        uint32_t *row = a.sw + (size_t)j * a.L;
+        uint2 cur = a.nodes[a.s];
+        const int32_t head = STITCHED ? min(a.ix.seg_len, a.L) : a.L;
+        int32_t len = 0;
+        for (int32_t t = 1; t <= head; ++t) {
+            const uint4 x = philox4x32_10((uint32_t)a.s, (uint32_t)j, (uint32_t)t, DOM_WALK, a.key);
+            if (x.x >= a.T || cur.y == 0) break;
+            cur = a.E[cur.x + pick32(x.y, cur.y)];
+            row[t - 1] = cur.x;
+            len = t;
+        }
+        moves = (uint32_t)len;
+        if (STITCHED && len == a.ix.seg_len && len < a.L) {
+            const uint32_t y = a.ix.node_of[cur.x];
+            const uint32_t sigma = entry_slot(a.ix, a.key, (uint32_t)a.s, (uint32_t)j, y);
+            for (int32_t mm = 0; mm < a.ix.width && len < a.L; ++mm) {
+                const uint32_t sg = a.ix.chain[(size_t)sigma * a.ix.width + mm];
+                if (sg == NIL) break;
+                const int32_t sl = a.ix.seg_lens[sg];
+                for (int32_t u = 0; u < sl && len < a.L; ++u) {
+                    row[len] = a.ix.seg[(size_t)sg * a.ix.seg_len + u];
+                    ++len;
+                    ++tail;
+                }
+                if (sl < a.ix.seg_len) break;
+            }
+        }
+        a.slen[j] = (uint8_t)len;
+    }
+    // wave totals
+    unsigned long long m64 = moves, t64 = tail;
+    for (int d = 32; d > 0; d >>= 1) {
+        m64 += __shfl_xor(m64, d, 64);
+        t64 += __shfl_xor(t64, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (m64) atomicAdd(&a.counters[C_SRC_MOVES], m64);
+        if (t64) atomicAdd(&a.counters[C_SRC_MOVES], t64);
+    }
+}
+
+// ------------------------------------------------------------ compaction
+// One block.  Keeps the walks with at least one step (a walk of length 0 can
+// only meet at step 0, i.e. only the source itself), packs their positions
+// back to back (swc), and cuts the packed list into tiles that fit the meet
+// kernel's LDS: a tile boundary falls wherever the entry index crosses a
+// multiple of TILE_J or the packed offset crosses a multiple of NW =
+// TILE_NODES - L, so a tile holds at most TILE_J walks and at most
+// NW - 1 + L <= TILE_NODES positions.
+
+template <typename T>
+__device__ T block_excl_sum(T x, T *total) {
+    __shared__ T part[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    T inc = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) part[wave] = inc;
+    __syncthreads();
+    T before = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) before += part[w];
+        tot += part[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+__global__ __launch_bounds__(1024) void k_compact(const uint8_t *__restrict__ slen,
+                                                  const uint32_t *__restrict__ sw, int32_t R,
+                                                  int32_t L, uint32_t *__restrict__ jj,
+                                                  uint32_t *__restrict__ joff,
+                                                  uint32_t *__restrict__ swc,
+                                                  uint32_t *__restrict__ tiles,
+                                                  uint32_t *__restrict__ meta, uint32_t NW) {
+    const int32_t per = (R + blockDim.x - 1) / blockDim.x;
+    const int32_t j0 = min(R, (int32_t)threadIdx.x * per), j1 = min(R, j0 + per);
+    uint32_t cnt = 0, nodes = 0;
+    for (int32_t j = j0; j < j1; ++j) {
+        const uint32_t l = slen[j];
+        cnt += l > 0;
+        nodes += l;
+    }
+    uint32_t R1, total;
+    const uint32_t kb = block_excl_sum(cnt, &R1);
+    const uint32_t nb = block_excl_sum(nodes, &total);
+    uint32_t k = kb, off = nb;
+    for (int32_t j = j0; j < j1; ++j) {
+        const uint32_t l = slen[j];
+        if (!l) continue;
+        jj[k] = (uint32_t)j;
+        joff[k] = off;
+        const uint32_t *src = sw + (size_t)j * L;
+        for (uint32_t t = 0; t < l; ++t) swc[off + t] = src[t];
+        ++k;
+        off += l;
+    }
+    if (threadIdx.x == 0) joff[R1] = total;
+    __syncthreads();
+    // tile boundaries over this thread's entries [kb, kb + cnt)
+    uint32_t nbound = 0;
+    for (uint32_t e = kb; e < kb + cnt; ++e)
+        nbound += (e == 0) || (e % TILE_J == 0) || (joff[e] / NW != joff[e - 1] / NW);
+    uint32_t n_tiles;
+    uint32_t tb = block_excl_sum(nbound, &n_tiles);
+    for (uint32_t e = kb; e < kb + cnt; ++e)
+        if ((e == 0) || (e % TILE_J == 0) || (joff[e] / NW != joff[e - 1] / NW)) tiles[tb++] = e;
+    if (threadIdx.x == 0) {
+        tiles[n_tiles] = R1;
+        meta[0] = R1;
+        meta[1] = total;
+        meta[2] = n_tiles;
+        meta[3] = 0u;   // work-unit cursor of the meet kernel
+    }
+}
+
+// ------------------------------------------------------------ meet kernel
+//
+// Persistent blocks take work units (tile of source walks x chunk of MEET_VB
+// nodes) from a device cursor.  A block stages its tile (walk ids, packed
+// positions) in LDS once and keeps it while consecutive units share the tile.
+// Inside a unit each wave takes one node v at a time from an LDS cursor and
+// spreads the tile's K pairs (v, j) over its 64 lanes; a lane that finishes a
+// pair (stop, meet, or end of walk (s, j)) is refilled with the next pair
+// before the next step, so all lanes keep stepping until the unit runs dry.
+// A step: one Philox draw, a multiply-high neighbour pick, one 8-byte gather
+// of E, one LDS compare.  Meets go to an LDS counter per node, flushed to the
+// global counts once per unit.
+
+struct MeetArgs {
+    const uint2 *nodes;
+    const uint2 *E;
+    const int32_t *active;
+    const uint32_t *jj;
+    const uint32_t *joff;
+    const uint32_t *swc;
+    const uint32_t *tiles;
+    uint32_t *meta;
+    uint32_t *cnt;
+    unsigned long long *counters;
+    IndexView ix;
+    PhiloxKey key;
+    uint32_t T;
+    int32_t s;
+    int32_t n_active;
+    int32_t n_chunks;
+};
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <bool STITCHED>
+__global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
+    __shared__ uint32_t s_nodes[TILE_NODES];
+    __shared__ uint32_t s_j[TILE_J];
+    __shared__ uint16_t s_off[TILE_J + 1];
+    __shared__ uint32_t s_cnt[MEET_VB];
+    __shared__ uint32_t s_unit, s_vnext;
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_tiles = a.meta[2];
+    const uint32_t n_units = n_tiles * (uint32_t)a.n_chunks;
+    uint32_t cur_tile = 0xffffffffu;
+    uint32_t K = 0;
+    uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_tail = 0, st_pairs = 0;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(&a.meta[3], 1u);
+        __syncthreads();
+        const uint32_t unit = s_unit;
+        if (unit >= n_units) break;
+        const uint32_t tile = unit / (uint32_t)a.n_chunks;
+        const uint32_t chunk = unit - tile * (uint32_t)a.n_chunks;
+        if (tile != cur_tile) {
+            const uint32_t k0 = a.tiles[tile], k1 = a.tiles[tile + 1];
+            const uint32_t nb = a.joff[k0], ne = a.joff[k1];
+            K = k1 - k0;
+            for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+                s_j[i] = a.jj[k0 + i];
+                s_off[i] = (uint16_t)(a.joff[k0 + i] - nb);
+            }
+            if (threadIdx.x == 0) s_off[K] = (uint16_t)(ne - nb);
+            for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = a.swc[nb + i];
+            cur_tile = tile;
+        }
+        for (uint32_t i = threadIdx.x; i < MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
+        if (threadIdx.x == 0) s_vnext = 0u;
+        __syncthreads();
+
+        const int32_t vbase = (int32_t)chunk * MEET_VB;
+        const uint32_t nv = (uint32_t)min(MEET_VB, a.n_active - vbase);
+
+        // wave-uniform cursor: current node (local index cv, id, row) and next pair index ck
+        uint32_t cv, cv_id = 0;
+        uint2 cv_row = make_uint2(0u, 0u);
+        auto fetch_v = [&]() {
+            for (;;) {
+                uint32_t x = 0;
+                if (lane == 0) x = atomicAdd(&s_vnext, 1u);
+                cv = __builtin_amdgcn_readfirstlane(x);
+                if (cv >= nv) return;
+                cv_id = (uint32_t)a.active[vbase + (int32_t)cv];
+                if ((int32_t)cv_id == a.s) continue;   // the source's own pairs are not walked
+                cv_row = a.nodes[cv_id];
+                return;
+            }
+        };
+        fetch_v();
+        uint32_t ck = 0;
+
+        bool busy = false;
+        uint32_t my_vl = 0, my_v = 0, my_j = 0, my_base = 0, my_len = 0, t = 0, o = 0, d = 0;
+        // stitched tail state: tail >= 1 once the private head is complete
+        uint32_t tail_sigma = 0, tail_m = 0, tail_u = 0, tail_seg = 0, tail_sl = 0;
+        bool in_tail = false;
+
+        for (;;) {
+            uint64_t need = __ballot(!busy);
+            while (need != 0ull && cv < nv) {
+                const uint32_t avail = K - ck;
+                const uint32_t want = (uint32_t)__popcll(need);
+                const uint32_t take = avail < want ? avail : want;
+                const uint32_t rank = lane_rank(need);
+                const bool mine = ((need >> lane) & 1ull) && rank < take;
+                if (mine) {
+                    const uint32_t kk = ck + rank;
+                    my_vl = cv;
+                    my_v = cv_id;
+                    my_j = s_j[kk];
+                    my_base = s_off[kk];
+                    my_len = (uint32_t)s_off[kk + 1] - my_base;
+                    o = cv_row.x;
+                    d = cv_row.y;
+                    t = 0;
+                    busy = true;
+                    in_tail = false;
+                    ++st_pairs;
+                }
+                need &= ~__ballot(mine);
+                ck += take;
+                if (ck == K) {
+                    fetch_v();
+                    ck = 0;
+                }
+            }
+            if (__ballot(busy) == 0ull) break;
+            if (!busy) continue;
+
+            if (!STITCHED || !in_tail) {
+                ++t;
+                const uint4 x = philox4x32_10(my_v, my_j, t, DOM_WALK, a.key);
+                ++st_draws;
+                if (x.x >= a.T) {
+                    busy = false;
+                } else {
+                    const uint2 e = a.E[o + pick32(x.y, d)];
+                    ++st_moves;
+                    o = e.x;
+                    d = e.y;
+                    if (o == s_nodes[my_base + t - 1]) {
+                        atomicAdd(&s_cnt[my_vl], 1u);
+                        ++st_meets;
+                        busy = false;
+                    } else if (t == my_len || d == 0u) {
+                        busy = false;
+                    } else if (STITCHED && t == (uint32_t)a.ix.seg_len) {
+                        const uint32_t y = a.ix.node_of[o];
+                        tail_sigma = entry_slot(a.ix, a.key, my_v, my_j, y);
+                        tail_m = 0;
+                        tail_u = 0;
+                        tail_seg = tail_sigma;
+                        tail_sl = a.ix.seg_lens[tail_seg];
+                        in_tail = true;
+                        if (tail_sl == 0u) busy = false;
+                    }
+                }
+            } else {
+                // one step read from the index: position u of segment tail_seg
+                ++t;
+                ++st_tail;
+                o = a.ix.seg[(size_t)tail_seg * a.ix.seg_len + tail_u];
+                ++tail_u;
+                if (o == s_nodes[my_base + t - 1]) {
+                    atomicAdd(&s_cnt[my_vl], 1u);
+                    ++st_meets;
+                    busy = false;
+                } else if (t == my_len) {
+                    busy = false;
+                } else if (tail_u == tail_sl) {
+                    if (tail_sl < (uint32_t)a.ix.seg_len || tail_m + 1 >= (uint32_t)a.ix.width) {
+                        busy = false;
+                    } else {
+                        ++tail_m;
+                        tail_seg = a.ix.chain[(size_t)tail_sigma * a.ix.width + tail_m];
+                        tail_u = 0;
+                        if (tail_seg == NIL) {
+                            busy = false;
+                        } else {
+                            tail_sl = a.ix.seg_lens[tail_seg];
+                            if (tail_sl == 0u) busy = false;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
+            const uint32_t c = s_cnt[i];
+            if (c) atomicAdd(&a.cnt[a.active[vbase + (int32_t)i]], c);
+        }
+    }
+
+    unsigned long long v0 = st_moves, v1 = st_draws, v2 = st_meets, v3 = st_tail, v4 = st_pairs;
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        v0 += __shfl_xor(v0, dd, 64);
+        v1 += __shfl_xor(v1, dd, 64);
+        v2 += __shfl_xor(v2, dd, 64);
+        v3 += __shfl_xor(v3, dd, 64);
+        v4 += __shfl_xor(v4, dd, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&a.counters[C_MOVES], v0);
+        atomicAdd(&a.counters[C_DRAWS], v1);
+        atomicAdd(&a.counters[C_MEETS], v2);
+        atomicAdd(&a.counters[C_TAIL], v3);
+        atomicAdd(&a.counters[C_PAIRS], v4);
+    }
+}
+
+// ------------------------------------------------------ walk materialisation
+
+struct WalkArgs {
+    const uint2 *nodes;
+    const uint2 *E;
+    IndexView ix;
+    const int32_t *vs;
+    const uint32_t *js;
+    int64_t count;
+    int32_t *paths;   // [count][L+1]
+    int32_t *lens;
+    PhiloxKey key;
+    uint32_t T;
+    int32_t L;
+};
+
+template <bool STITCHED>
+__global__ __launch_bounds__(256) void k_walks(WalkArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    int32_t *row = a.paths + (size_t)i * (a.L + 1);
+    const uint32_t v = (uint32_t)a.vs[i], j = a.js[i];
+    row[0] = (int32_t)v;
+    uint2 cur = a.nodes[v];
+    const int32_t head = STITCHED ? min(a.ix.seg_len, a.L) : a.L;
+    int32_t len = 0;
+    for (int32_t t = 1; t <= head; ++t) {
+        const uint4 x = philox4x32_10(v, j, (uint32_t)t, DOM_WALK, a.key);
+        if (x.x >= a.T || cur.y == 0) break;
+        cur = a.E[cur.x + pick32(x.y, cur.y)];
+        row[t] = (int32_t)a.ix.node_of[cur.x];
+        len = t;
+    }
+    if (STITCHED && len == a.ix.seg_len && len < a.L) {
+        const uint32_t sigma = entry_slot(a.ix, a.key, v, j, (uint32_t)row[len]);
+        for (int32_t mm = 0; mm < a.ix.width && len < a.L; ++mm) {
+            const uint32_t sg = a.ix.chain[(size_t)sigma * a.ix.width + mm];
+            if (sg == NIL) break;
+            const int32_t sl = a.ix.seg_lens[sg];
+            for (int32_t u = 0; u < sl && len < a.L; ++u) {
+                ++len;
+                row[len] = (int32_t)a.ix.node_of[a.ix.seg[(size_t)sg * a.ix.seg_len + u]];
+            }
+            if (sl < a.ix.seg_len) break;
+        }
+    }
+    for (int32_t t = len + 1; t <= a.L; ++t) row[t] = -1;
+    a.lens[i] = len;
+}
+
+IndexView index_view(const Graph *g) {
+    IndexView v{};
+    v.node_of = g->node_of;
+    if (g->index) {
+        v.pool_off = g->index->pool_off;
+        v.seg = g->index->seg;
+        v.seg_lens = g->index->seg_lens;
+        v.chain = g->index->chain;
+        v.seg_len = g->index->seg_len;
+        v.width = g->index->width;
+    }
+    return v;
+}
+
+int meet_grid_blocks() {
+    static int blocks = 0;
+    if (blocks == 0) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<false>, MEET_BLOCK, 0);
+        if (cus <= 0) cus = 256;
+        if (per <= 0) per = 1;
+        blocks = cus * per;
+    }
+    return blocks;
+}
+
+int32_t max_tiles_for(int32_t R, int32_t L) {
+    const int64_t NW = TILE_NODES - L;
+    return (int32_t)(2 + R / TILE_J + ((int64_t)R * L) / NW);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mode) {
+    if (!q) return fail(SIMRANK_EINVAL, "query is NULL");
+    if (!(q->c > 0.0 && q->c < 1.0)) return fail(SIMRANK_EINVAL, "c must lie in (0, 1)");
+    if (!(q->delta > 0.0 && q->delta < 1.0)) return fail(SIMRANK_EINVAL, "delta must lie in (0, 1)");
+    if (!(q->eps > 0.0 && q->eps < 1.0)) return fail(SIMRANK_EINVAL, "eps must lie in (0, 1)");
+    if (q->mode != SIMRANK_MODE_PLAIN && q->mode != SIMRANK_MODE_STITCHED)
+        return fail(SIMRANK_EINVAL, "unknown mode");
+    const int32_t L = q->walk_cap == 0 ? 64 : q->walk_cap;
+    if (L < 1 || L > MAX_CAP) return fail(SIMRANK_EINVAL, "walk_cap must lie in [1, 255]");
+    if (q->mode == SIMRANK_MODE_STITCHED && L > MAX_STITCH_CAP)
+        return fail(SIMRANK_EINVAL, "stitched walks are capped at 64 steps");
+    if (q->R_override < 0) return fail(SIMRANK_EINVAL, "R_override must be >= 0");
+    int64_t R;
+    if (q->R_override > 0) {
+        R = q->R_override;
+    } else {
+        // Hoeffding: 2 exp(-2 R lambda^2) <= delta (per node) or delta / n
+        // (union over n nodes); lambda = eps minus the truncation bias c^(L+1).
+        const double lam = q->eps - pow(q->c, (double)(L + 1));
+        if (!(lam > 0.0)) return fail(SIMRANK_EINVAL, "eps must exceed c^(L+1)");
+        const double num = q->union_bound ? log(2.0 * (double)n / q->delta) : log(2.0 / q->delta);
+        const double r = ceil(num / (2.0 * lam * lam));
+        if (!(r <= (double)MAX_R)) return fail(SIMRANK_EINVAL, "R exceeds 2^24");
+        R = (int64_t)r;
+    }
+    if (R > MAX_R) return fail(SIMRANK_EINVAL, "R exceeds 2^24");
+    out->R = (int32_t)R;
+    out->L = L;
+    out->T = continue_threshold(q->c);
+    out->reserved = 0;
+    if (mode) *mode = q->mode;
+    return SIMRANK_OK;
+}
+
+int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws) {
+    if (max_R < 1 || max_R > MAX_R) return fail(SIMRANK_EINVAL, "max_R must lie in [1, 2^24]");
+    if (max_L < 1 || max_L > MAX_CAP) return fail(SIMRANK_EINVAL, "max_L must lie in [1, 255]");
+    ws->g = g;
+    ws->max_R = max_R;
+    ws->max_L = max_L;
+    ws->max_tiles = max_tiles_for(max_R, max_L);
+    const size_t RL = (size_t)max_R * (size_t)max_L;
+    int rc;
+    if ((rc = device_alloc((void **)&ws->sw, 4 * RL, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->slen, (size_t)max_R, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->jj, 4 * (size_t)max_R, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->joff, 4 * ((size_t)max_R + 1), nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->swc, 4 * RL, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->tiles, 4 * ((size_t)ws->max_tiles + 1), nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->meta, 4 * 8, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->counters, 8 * 8, nullptr))) return rc;
+    SRK_HIP(hipEventCreate(&ws->ev0));
+    SRK_HIP(hipEventCreate(&ws->ev1));
+    SRK_HIP(hipEventCreate(&ws->evm0));
+    SRK_HIP(hipEventCreate(&ws->evm1));
+    return SIMRANK_OK;
+}
+
+void workspace_release(Workspace *ws) {
+    if (!ws) return;
+    device_free(ws->sw);
+    device_free(ws->slen);
+    device_free(ws->jj);
+    device_free(ws->joff);
+    device_free(ws->swc);
+    device_free(ws->tiles);
+    device_free(ws->meta);
+    device_free(ws->counters);
+    if (ws->ev0) (void)hipEventDestroy(ws->ev0);
+    if (ws->ev1) (void)hipEventDestroy(ws->ev1);
+    if (ws->evm0) (void)hipEventDestroy(ws->evm0);
+    if (ws->evm1) (void)hipEventDestroy(ws->evm1);
+    *ws = Workspace{};
+}
+
+int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                  Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st) {
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (p.R > ws->max_R || p.L > ws->max_L)
+        return fail(SIMRANK_EINVAL, "query needs R or L beyond the workspace's size");
+    if (!counts_dev) return fail(SIMRANK_EINVAL, "counts buffer is NULL");
+    const bool stitched = mode == SIMRANK_MODE_STITCHED;
+    if (stitched && !g->index) return fail(SIMRANK_ESTATE, "stitched query without an index");
+    if (stitched && g->index->T != p.T)
+        return fail(SIMRANK_EINVAL, "stitched query's c differs from the index's c");
+    // the meet kernel counts work units (tile x node chunk) in 32 bits
+    const int64_t units_bound = (int64_t)max_tiles_for(p.R, p.L) *
+                                ((g->n_active + MEET_VB - 1) / MEET_VB);
+    if (units_bound >= (int64_t)0xffffffffu - (1 << 20))
+        return fail(SIMRANK_EINVAL, "R * L * n too large for one launch");
+    const PhiloxKey key = make_key(q->seed);
+    const IndexView ix = index_view(g);
+
+    SRK_HIP(hipEventRecord(ws->ev0, st));
+    k_query_init<<<grid_for(std::max<int64_t>(g->n, 8), 256), 256, 0, st>>>(counts_dev, g->n,
+                                                                           ws->meta, ws->counters);
+    SrcArgs sa{g->nodes, g->E, ix, ws->sw, ws->slen, ws->counters, key, p.T, p.R, p.L, q->s};
+    if (stitched)
+        k_source_walks<true><<<grid_for(p.R, 256), 256, 0, st>>>(sa);
+    else
+        k_source_walks<false><<<grid_for(p.R, 256), 256, 0, st>>>(sa);
+    k_compact<<<1, 1024, 0, st>>>(ws->slen, ws->sw, p.R, p.L, ws->jj, ws->joff, ws->swc,
+                                  ws->tiles, ws->meta, (uint32_t)(TILE_NODES - p.L));
+    const int32_t n_chunks = (g->n_active + MEET_VB - 1) / MEET_VB;
+    SRK_HIP(hipEventRecord(ws->evm0, st));
+    if (n_chunks > 0) {
+        MeetArgs ma{g->nodes, g->E, g->active, ws->jj, ws->joff, ws->swc, ws->tiles, ws->meta,
+                    counts_dev, ws->counters, ix, key, p.T, q->s, g->n_active, n_chunks};
+        const int64_t max_units = (int64_t)max_tiles_for(p.R, p.L) * n_chunks;
+        const int blocks = (int)std::min<int64_t>(max_units, meet_grid_blocks());
+        if (stitched)
+            k_meet<true><<<blocks, MEET_BLOCK, 0, st>>>(ma);
+        else
+            k_meet<false><<<blocks, MEET_BLOCK, 0, st>>>(ma);
+    }
+    SRK_HIP(hipEventRecord(ws->evm1, st));
+    k_estimate<<<grid_for(g->n, 256), 256, 0, st>>>(counts_dev, out_dev, g->n, p.R, q->s);
+    SRK_HIP(hipGetLastError());
+    SRK_HIP(hipEventRecord(ws->ev1, st));
+    ws->last_stream = st;
+    ws->last_params = p;
+    ws->last_n = g->n;
+    ws->pending = true;
+    return SIMRANK_OK;
+}
+
+static int read_stats(Workspace *ws, simrank_stats *st) {
+    SRK_HIP(hipEventSynchronize(ws->ev1));
+    unsigned long long c[8];
+    SRK_HIP(hipMemcpy(c, ws->counters, sizeof(c), hipMemcpyDeviceToHost));
+    float ms = 0.f, mms = 0.f;
+    SRK_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+    SRK_HIP(hipEventElapsedTime(&mms, ws->evm0, ws->evm1));
+    if (st) {
+        *st = simrank_stats{};
+        st->pairs = (uint64_t)(ws->last_n - 1) * (uint64_t)ws->last_params.R;
+        st->pairs_walked = c[C_PAIRS];
+        st->moves = c[C_MOVES];
+        st->draws = c[C_DRAWS];
+        st->meets = c[C_MEETS];
+        st->tail_steps = c[C_TAIL];
+        st->source_moves = c[C_SRC_MOVES];
+        st->ms = ms;
+        st->meet_ms = mms;
+        st->R = ws->last_params.R;
+        st->L = ws->last_params.L;
+        st->T = ws->last_params.T;
+    }
+    ws->pending = false;
+    return SIMRANK_OK;
+}
+
+}  // namespace srk
+
+using namespace srk;
+
+
+extern "C" int simrank_derive_params(const simrank_query *q, int32_t n, simrank_params *out) {
+    clear_error();
+    if (!out) return fail(SIMRANK_EINVAL, "out is NULL");
+    if (n < 1) return fail(SIMRANK_EINVAL, "n must be >= 1");
+    simrank_params p;
+    const int rc = query_params(q, n, &p, nullptr);
+    if (rc == SIMRANK_OK) *out = p;
+    return rc;
+}
+
+extern "C" int simrank_workspace_create(const simrank_graph *g, int32_t max_R, int32_t max_L,
+                                        simrank_workspace **ws_out) {
+    clear_error();
+    if (!g || !ws_out) return fail(SIMRANK_EINVAL, "NULL argument");
+    *ws_out = nullptr;
+    SRK_HIP(hipSetDevice(g->device));
+    simrank_workspace *ws = new simrank_workspace();
+    const int rc = workspace_init(g, max_R, max_L, ws);
+    if (rc != SIMRANK_OK) {
+        workspace_release(ws);
+        delete ws;
+        return rc;
+    }
+    *ws_out = ws;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_workspace_free(simrank_workspace *ws) {
+    clear_error();
+    if (!ws) return SIMRANK_OK;
+    if (ws->pending && ws->last_stream) (void)hipStreamSynchronize(ws->last_stream);
+    workspace_release(ws);
+    delete ws;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_single_source_async(const simrank_graph *g, const simrank_query *q,
+                                           simrank_workspace *ws, double *out_dev,
+                                           uint32_t *counts_dev, void *stream) {
+    clear_error();
+    if (!g || !q || !ws) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (ws->g != g) return fail(SIMRANK_EINVAL, "workspace belongs to another graph");
+    simrank_params p;
+    int mode;
+    int rc = query_params(q, g->n, &p, &mode);
+    if (rc) return rc;
+    SRK_HIP(hipSetDevice(g->device));
+    return enqueue_query(g, q, p, mode, ws, out_dev, counts_dev, (hipStream_t)stream);
+}
+
+extern "C" int simrank_workspace_stats(simrank_workspace *ws, simrank_stats *st) {
+    clear_error();
+    if (!ws) return fail(SIMRANK_EINVAL, "workspace is NULL");
+    if (!ws->pending) return fail(SIMRANK_ESTATE, "no call recorded on this workspace");
+    return read_stats(ws, st);
+}
+
+extern "C" int simrank_single_source_ex(const simrank_graph *g, const simrank_query *q,
+                                        double *out_host, uint32_t *counts_host,
+                                        simrank_stats *st_opt) {
+    clear_error();
+    if (!g || !q) return fail(SIMRANK_EINVAL, "NULL argument");
+    simrank_params p;
+    int mode;
+    int rc = query_params(q, g->n, &p, &mode);
+    if (rc) return rc;
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (mode == SIMRANK_MODE_STITCHED && !g->index)
+        return fail(SIMRANK_ESTATE, "stitched query without an index");
+    if (mode == SIMRANK_MODE_STITCHED && g->index->T != p.T)
+        return fail(SIMRANK_EINVAL, "stitched query's c differs from the index's c");
+    SRK_HIP(hipSetDevice(g->device));
+    Workspace ws;
+    double *out_dev = nullptr;
+    uint32_t *cnt_dev = nullptr;
+    rc = workspace_init(g, p.R, p.L, &ws);
+    if (!rc) rc = device_alloc((void **)&cnt_dev, 4 * (size_t)g->n, nullptr);
+    if (!rc && out_host) rc = device_alloc((void **)&out_dev, 8 * (size_t)g->n, nullptr);
+    if (!rc) rc = enqueue_query(g, q, p, mode, &ws, out_dev, cnt_dev, g->stream);
+    if (!rc) rc = read_stats(&ws, st_opt);
+    if (!rc && out_host) {
+        hipError_t e = hipMemcpy(out_host, out_dev, 8 * (size_t)g->n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    if (!rc && counts_host) {
+        hipError_t e = hipMemcpy(counts_host, cnt_dev, 4 * (size_t)g->n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    device_free(out_dev);
+    device_free(cnt_dev);
+    workspace_release(&ws);
+    return rc;
+}
+
+extern "C" int simrank_single_source(const simrank_graph *g, int32_t s, double c, double eps,
+                                     double delta, double *out) {
+    if (!out) {
+        clear_error();
+        return fail(SIMRANK_EINVAL, "out is NULL");
+    }
+    simrank_query q{};
+    q.s = s;
+    q.c = c;
+    q.eps = eps;
+    q.delta = delta;
+    q.seed = 0;
+    q.walk_cap = 64;
+    q.mode = SIMRANK_MODE_PLAIN;
+    return simrank_single_source_ex(g, &q, out, nullptr, nullptr);
+}
+
+extern "C" int simrank_walks(const simrank_graph *g, const simrank_query *q, const int32_t *v,
+                             const uint32_t *j, int64_t count, int32_t *paths, int32_t *lens) {
+    clear_error();
+    if (!g || !q || (count > 0 && (!v || !j || !paths || !lens)))
+        return fail(SIMRANK_EINVAL, "NULL argument");
+    if (count < 0) return fail(SIMRANK_EINVAL, "count < 0");
+    simrank_params p;
+    int mode;
+    int rc = query_params(q, g->n, &p, &mode);
+    if (rc) return rc;
+    for (int64_t i = 0; i < count; ++i)
+        if (v[i] < 0 || v[i] >= g->n) return fail(SIMRANK_EINVAL, "walk start out of range");
+    const bool stitched = mode == SIMRANK_MODE_STITCHED;
+    if (stitched && !g->index) return fail(SIMRANK_ESTATE, "stitched walks without an index");
+    if (stitched && g->index->T != p.T)
+        return fail(SIMRANK_EINVAL, "stitched walks' c differs from the index's c");
+    if (count == 0) return SIMRANK_OK;
+    SRK_HIP(hipSetDevice(g->device));
+    int32_t *dv = nullptr, *dpaths = nullptr, *dlens = nullptr;
+    uint32_t *dj = nullptr;
+    const size_t rowb = 4 * (size_t)(p.L + 1);
+    rc = device_alloc((void **)&dv, 4 * (size_t)count, nullptr);
+    if (!rc) rc = device_alloc((void **)&dj, 4 * (size_t)count, nullptr);
+    if (!rc) rc = device_alloc((void **)&dpaths, rowb * (size_t)count, nullptr);
+    if (!rc) rc = device_alloc((void **)&dlens, 4 * (size_t)count, nullptr);
+    hipStream_t st = g->stream;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(dv, v, 4 * (size_t)count, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dj, j, 4 * (size_t)count, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            WalkArgs wa{g->nodes, g->E, index_view(g), dv, dj, count, dpaths, dlens,
+                        make_key(q->seed), p.T, p.L};
+            if (stitched)
+                k_walks<true><<<grid_for(count, 256), 256, 0, st>>>(wa);
+            else
+                k_walks<false><<<grid_for(count, 256), 256, 0, st>>>(wa);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(paths, dpaths, rowb * (size_t)count, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lens, dlens, 4 * (size_t)count, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    device_free(dv);
+    device_free(dj);
+    device_free(dpaths);
+    device_free(dlens);
+    return rc;
+}

@@ -1,0 +1,308 @@
+"""Python binding of libsimrank.so (the C ABI in include/simrank.h).
+
+Argument marshalling only: every step of a query runs in the library's HIP
+kernels.  There is no CPU fallback: if the library cannot be loaded, every
+call raises.  Function names are those of the C ABI.  Device buffers for the
+asynchronous call are any objects with a device address (torch tensors are
+accepted directly); PyTorch is used only for that memory and for streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsimrank.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "simrank.h")
+
+SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
+MODE_PLAIN, MODE_STITCHED = 0, 1
+_ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE"}
+
+
+class SimRankError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"simrank error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class simrank_query(C.Structure):
+    _fields_ = [("s", C.c_int32), ("graph", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
+                ("delta", C.c_double), ("seed", C.c_uint64), ("walk_cap", C.c_int32),
+                ("R_override", C.c_int32), ("mode", C.c_int32), ("union_bound", C.c_int32)]
+
+
+class simrank_params(C.Structure):
+    _fields_ = [("R", C.c_int32), ("L", C.c_int32), ("T", C.c_uint32), ("reserved", C.c_int32)]
+
+
+class simrank_stats(C.Structure):
+    _fields_ = [("pairs", C.c_uint64), ("pairs_walked", C.c_uint64), ("moves", C.c_uint64),
+                ("draws", C.c_uint64), ("meets", C.c_uint64), ("tail_steps", C.c_uint64),
+                ("source_moves", C.c_uint64), ("ms", C.c_double), ("meet_ms", C.c_double),
+                ("R", C.c_int32),
+                ("L", C.c_int32), ("T", C.c_uint32), ("reserved", C.c_int32)]
+
+    def asdict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class simrank_index_params(C.Structure):
+    _fields_ = [("seg_log2", C.c_int32), ("reserved", C.c_int32), ("kappa", C.c_double),
+                ("c", C.c_double), ("seed", C.c_uint64)]
+
+
+class simrank_index_summary(C.Structure):
+    _fields_ = [("segments", C.c_int64), ("bytes", C.c_int64), ("seg_log2", C.c_int32),
+                ("levels", C.c_int32), ("build_ms", C.c_double), ("build_moves", C.c_uint64)]
+
+    def asdict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it is missing (build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2304_04015_amd/build.py "
+                          "(or __graft_entry__.build()) first; there is no fallback")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+    P = C.POINTER
+    sig = {
+        "simrank_load_graph": [i32, i64, vp, vp, P(vp)],
+        "simrank_free_graph": [vp],
+        "simrank_graph_info": [vp, P(i32), P(i64), P(i32), P(i64)],
+        "simrank_derive_params": [P(simrank_query), i32, P(simrank_params)],
+        "simrank_single_source": [vp, i32, dbl, dbl, dbl, vp],
+        "simrank_single_source_ex": [vp, P(simrank_query), vp, vp, P(simrank_stats)],
+        "simrank_workspace_create": [vp, i32, i32, P(vp)],
+        "simrank_workspace_free": [vp],
+        "simrank_single_source_async": [vp, P(simrank_query), vp, vp, vp, vp],
+        "simrank_workspace_stats": [vp, P(simrank_stats)],
+        "simrank_walks": [vp, P(simrank_query), vp, vp, i64, vp, vp],
+        "simrank_build_index": [vp, P(simrank_index_params)],
+        "simrank_index_info": [vp, P(simrank_index_summary)],
+        "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
+        "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.simrank_last_error.argtypes = []
+    L.simrank_last_error.restype = C.c_char_p
+    L.simrank_version.argtypes = []
+    L.simrank_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/simrank.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(simrank_\w+)\s*\(", text, re.M)))
+
+
+def _check(rc: int) -> None:
+    if rc != SIMRANK_OK:
+        raise SimRankError(rc, lib().simrank_last_error().decode())
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _dev_ptr(t) -> int | None:
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return int(t.data_ptr())
+    return int(t)
+
+
+def make_query(s: int, c: float = 0.6, eps: float = 0.02, delta: float = 1e-3, seed: int = 0,
+               walk_cap: int = 64, R: int = 0, mode: int = MODE_PLAIN, union_bound: bool = False,
+               graph: int = 0) -> simrank_query:
+    return simrank_query(s=s, graph=graph, c=c, eps=eps, delta=delta, seed=seed,
+                         walk_cap=walk_cap, R_override=R, mode=mode,
+                         union_bound=1 if union_bound else 0)
+
+
+class Graph:
+    """A device-resident graph handle (simrank_load_graph / simrank_free_graph)."""
+
+    def __init__(self, handle: int, n: int, m: int):
+        self.handle = C.c_void_p(handle)
+        self.n = n
+        self.m = m
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self) -> None:
+        if self.handle and self.handle.value:
+            _check(lib().simrank_free_graph(self.handle))
+            self.handle = C.c_void_p(None)
+
+    def info(self) -> dict:
+        n, na = C.c_int32(), C.c_int32()
+        m, b = C.c_int64(), C.c_int64()
+        _check(lib().simrank_graph_info(self.handle, C.byref(n), C.byref(m), C.byref(na),
+                                        C.byref(b)))
+        return dict(n=n.value, m=m.value, n_active=na.value, device_bytes=b.value)
+
+
+def simrank_load_graph(n: int, in_off, in_src) -> Graph:
+    in_off = np.ascontiguousarray(in_off, np.int32)
+    in_src = np.ascontiguousarray(in_src, np.int32)
+    if in_off.shape != (n + 1,):
+        raise ValueError("in_off must have n + 1 entries")
+    h = C.c_void_p()
+    _check(lib().simrank_load_graph(n, in_src.size, _ptr(in_off), _ptr(in_src) if in_src.size else None,
+                                    C.byref(h)))
+    return Graph(h.value, n, int(in_src.size))
+
+
+def load_csr(g) -> Graph:
+    """Loads an object with fields n, in_off, in_src (e.g. inputs.CSR)."""
+    return simrank_load_graph(g.n, g.in_off, g.in_src)
+
+
+def simrank_derive_params(q: simrank_query, n: int) -> simrank_params:
+    p = simrank_params()
+    _check(lib().simrank_derive_params(C.byref(q), n, C.byref(p)))
+    return p
+
+
+def simrank_single_source(g: Graph, s: int, c: float, eps: float, delta: float) -> np.ndarray:
+    out = np.empty(g.n, np.float64)
+    _check(lib().simrank_single_source(g.handle, s, c, eps, delta, _ptr(out)))
+    return out
+
+
+def simrank_single_source_ex(g: Graph, q: simrank_query, want_out: bool = True,
+                             want_counts: bool = True):
+    out = np.empty(g.n, np.float64) if want_out else None
+    cnt = np.empty(g.n, np.uint32) if want_counts else None
+    st = simrank_stats()
+    _check(lib().simrank_single_source_ex(g.handle, C.byref(q),
+                                          _ptr(out) if out is not None else None,
+                                          _ptr(cnt) if cnt is not None else None, C.byref(st)))
+    return out, cnt, st
+
+
+class Workspace:
+    def __init__(self, g: Graph, max_R: int, max_L: int):
+        h = C.c_void_p()
+        _check(lib().simrank_workspace_create(g.handle, max_R, max_L, C.byref(h)))
+        self.handle = h
+        self.graph = g
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self) -> None:
+        if self.handle and self.handle.value:
+            _check(lib().simrank_workspace_free(self.handle))
+            self.handle = C.c_void_p(None)
+
+
+def simrank_workspace_create(g: Graph, max_R: int, max_L: int) -> Workspace:
+    return Workspace(g, max_R, max_L)
+
+
+def simrank_single_source_async(g: Graph, q: simrank_query, ws: Workspace, out_dev, counts_dev,
+                                stream=None) -> None:
+    """out_dev: float64 device buffer of n (or None); counts_dev: uint32/int32 device
+    buffer of n; stream: a torch.cuda.Stream, a raw hipStream_t int, or None."""
+    sp = None
+    if stream is not None:
+        sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+    _check(lib().simrank_single_source_async(g.handle, C.byref(q), ws.handle, _dev_ptr(out_dev),
+                                             _dev_ptr(counts_dev), sp))
+
+
+def simrank_workspace_stats(ws: Workspace) -> simrank_stats:
+    st = simrank_stats()
+    _check(lib().simrank_workspace_stats(ws.handle, C.byref(st)))
+    return st
+
+
+def simrank_walks(g: Graph, q: simrank_query, vs, js):
+    vs = np.ascontiguousarray(vs, np.int32)
+    js = np.ascontiguousarray(js, np.uint32)
+    p = simrank_derive_params(q, g.n)
+    paths = np.empty((vs.size, p.L + 1), np.int32)
+    lens = np.empty(vs.size, np.int32)
+    _check(lib().simrank_walks(g.handle, C.byref(q), _ptr(vs), _ptr(js), vs.size, _ptr(paths),
+                               _ptr(lens)))
+    return paths, lens
+
+
+def simrank_build_index(g: Graph, seg_log2: int = 3, kappa: float = 1.0, c: float = 0.6,
+                        seed: int = 0) -> dict:
+    p = simrank_index_params(seg_log2=seg_log2, reserved=0, kappa=kappa, c=c, seed=seed)
+    _check(lib().simrank_build_index(g.handle, C.byref(p)))
+    return simrank_index_info(g)
+
+
+def simrank_index_info(g: Graph) -> dict:
+    s = simrank_index_summary()
+    _check(lib().simrank_index_info(g.handle, C.byref(s)))
+    return s.asdict()
+
+
+def simrank_index_read(g: Graph, sigma, with_chain: bool = True):
+    sigma = np.ascontiguousarray(sigma, np.int64)
+    info = simrank_index_info(g)
+    seg_len = 1 << info["seg_log2"]
+    width = 64 // seg_len
+    nodes = np.empty((sigma.size, seg_len), np.int32)
+    lens = np.empty(sigma.size, np.int32)
+    succ = np.empty(sigma.size, np.int64)
+    chain = np.empty((sigma.size, width), np.int64) if with_chain else None
+    _check(lib().simrank_index_read(g.handle, _ptr(sigma), sigma.size, _ptr(nodes), _ptr(lens),
+                                    _ptr(succ), _ptr(chain) if with_chain else None))
+    return nodes, lens, succ, chain
+
+
+def simrank_batch(graphs: list[Graph], queries: list[simrank_query], want_counts: bool = True):
+    ng = len(graphs)
+    nq = len(queries)
+    garr = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
+    qarr = (simrank_query * nq)(*queries)
+    outs = [np.empty(graphs[q.graph].n, np.float64) for q in queries]
+    cnts = [np.empty(graphs[q.graph].n, np.uint32) for q in queries] if want_counts else None
+    oarr = (C.c_void_p * nq)(*[o.ctypes.data for o in outs])
+    carr = (C.c_void_p * nq)(*[c.ctypes.data for c in cnts]) if want_counts else None
+    st = simrank_stats()
+    _check(lib().simrank_batch(garr, ng, qarr, nq, oarr, carr, C.byref(st)))
+    return outs, cnts, st
+
+
+def simrank_version() -> str:
+    return lib().simrank_version().decode()
+
+
+@dataclass
+class Params:
+    R: int
+    L: int
+    T: int

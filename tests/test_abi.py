@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function include/simrank.h declares, derives the parameters the oracle
+derives, and rejects malformed input before touching the device."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2304_04015_amd import simrank as S
+
+
+@pytest.fixture(scope="module")
+def L():
+    return S.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = S.header_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(L, name), name
+    assert S.simrank_version().startswith("simrank")
+
+
+@pytest.mark.parametrize("eps,c,L_,n,union", [
+    (0.02, 0.6, 64, 1 << 20, False), (0.05, 0.6, 64, 1 << 20, False),
+    (0.01, 0.6, 64, 1 << 20, False), (0.02, 0.6, 32, 500, True), (0.1, 0.8, 16, 100, False),
+    (0.03, 0.36, 255, 10, True),
+])
+def test_derive_params_matches_oracle(eps, c, L_, n, union):
+    q = S.make_query(0, c=c, eps=eps, delta=1e-3, walk_cap=L_, union_bound=union)
+    p = S.simrank_derive_params(q, n)
+    assert p.L == L_
+    assert p.R == exact.hoeffding_R(eps, 1e-3, c, L_, n=n if union else None)
+    assert p.T == oracle.continue_threshold(c)
+
+
+def test_derive_params_defaults_and_override():
+    q = S.make_query(0, walk_cap=0)
+    assert S.simrank_derive_params(q, 10).L == 64
+    q = S.make_query(0, R=123)
+    assert S.simrank_derive_params(q, 10).R == 123
+
+
+@pytest.mark.parametrize("kw", [
+    dict(c=0.0), dict(c=1.0), dict(eps=0.0), dict(eps=1.0), dict(delta=0.0), dict(delta=1.0),
+    dict(walk_cap=256), dict(walk_cap=-1), dict(R=-1), dict(mode=7),
+    dict(eps=1e-12),                      # R beyond 2^24
+    dict(mode=S.MODE_STITCHED, walk_cap=65),
+])
+def test_derive_params_rejects(kw):
+    q = S.make_query(0, **kw)
+    with pytest.raises(S.SimRankError) as e:
+        S.simrank_derive_params(q, 100)
+    assert e.value.code == S.SIMRANK_EINVAL
+
+
+def test_eps_below_truncation_bias_rejected():
+    # c^(L+1) at c = 0.9, L = 4 is 0.59: eps = 0.5 leaves nothing for sampling
+    q = S.make_query(0, c=0.9, eps=0.5, walk_cap=4)
+    with pytest.raises(S.SimRankError, match="c\\^\\(L\\+1\\)"):
+        S.simrank_derive_params(q, 100)
+
+
+@pytest.mark.parametrize("off,src,m,msg", [
+    ([1, 1, 2], [0, 1], 2, "in_off\\[0\\]"),
+    ([0, 2, 1], [0, 1], 2, "decreases"),
+    ([0, 1, 2], [0, 1, 7], 3, "in_off\\[n\\]"),
+    ([0, 1, 2], [0, 5], 2, "out of range"),
+    ([0, 1, 2], [-1, 0], 2, "out of range"),
+])
+def test_load_graph_rejects_malformed_csr(off, src, m, msg):
+    import ctypes as C
+    h = C.c_void_p()
+    offa = np.array(off, np.int32)
+    srca = np.array(src, np.int32)
+    rc = S.lib().simrank_load_graph(2, m, offa.ctypes.data, srca.ctypes.data, C.byref(h))
+    assert rc == S.SIMRANK_EINVAL
+    assert h.value is None
+    import re
+    assert re.search(msg, S.lib().simrank_last_error().decode())
+
+
+def test_null_arguments_rejected():
+    assert S.lib().simrank_load_graph(2, 0, None, None, None) == S.SIMRANK_EINVAL
+    assert b"NULL" in S.lib().simrank_last_error()
+    assert S.lib().simrank_derive_params(None, 10, None) == S.SIMRANK_EINVAL
+    assert S.lib().simrank_single_source(None, 0, 0.6, 0.02, 1e-3, None) == S.SIMRANK_EINVAL
+    assert S.lib().simrank_free_graph(None) == S.SIMRANK_OK
+    assert S.lib().simrank_workspace_free(None) == S.SIMRANK_OK
+    assert S.lib().simrank_batch(None, 0, None, 0, None, None, None) == S.SIMRANK_OK
+    assert S.lib().simrank_last_error() == b""
+
+
+def test_union_bound_grows_R():
+    q1 = S.make_query(0, eps=0.02)
+    q2 = S.make_query(0, eps=0.02, union_bound=True)
+    n = 1 << 20
+    r1 = S.simrank_derive_params(q1, n).R
+    r2 = S.simrank_derive_params(q2, n).R
+    assert r2 > r1
+    assert r2 == math.ceil(math.log(2 * n / 1e-3) / (2 * (0.02 - 0.6 ** 65) ** 2))
