@@ -1,0 +1,176 @@
+"""Benchmark: single-source sqrt(c)-walk SimRank on one MI355X.
+
+Workload (the medium configuration): R-MAT graph, n = 2^20 nodes, 16 n edge
+draws with (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), duplicates removed,
+vertices relabelled by a seeded permutation; c = 0.6, eps = 0.02,
+delta = 1e-3 (R = 9502 walks per node from Hoeffding), walk cap L = 64;
+8 sources drawn uniformly among nodes with in-edges, each run as its own
+single-source query.  One step = those 8 queries, each a full pass of the
+query path (source walks, compaction, fused walk + meet + count, estimate),
+with the graph already resident in HBM.
+
+Prints one JSON line.  `value` is walk steps per second (moves along in-edges
+made by the meet kernel, plus the source walks' steps); `queries_per_s` is
+single-source queries per second.  `roofline` reports the fused walk + meet
+kernel: algorithmic bytes (8 bytes per move: the gathered edge slot) over its
+launch time measured with HIP events on the stream it runs on.  `cpu_baseline`
+times the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walk-steps/s + single-source queries/s at eps=0.02; batched vs plain, % roofline"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_MOVE = 8
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-nodes", type=int, default=2048,
+                    help="nodes in the CPU oracle's sample (x R pairs, one source)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_meet_medium.json"),
+                    help="measured HBM traffic per meet launch (JSON), if present")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards over nodes v with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = inputs.C2
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = inputs.workload_graph(cfg)
+    sources = inputs.sources_with_in_edges(g, cfg["n_sources"], cfg["source_seed"])
+    print(f"# graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s", file=sys.stderr)
+    G = S.load_csr(g)
+    queries = [S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
+                            seed=cfg["walk_seed"], walk_cap=cfg["L"]) for s in sources]
+    R = S.simrank_derive_params(queries[0], g.n).R
+    stream = torch.cuda.Stream()
+    wss = [S.simrank_workspace_create(G, R, cfg["L"]) for _ in queries]
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in queries]
+    cnts = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in queries]
+
+    def step():
+        for q, ws, o, c in zip(queries, wss, outs, cnts):
+            S.simrank_single_source_async(G, q, ws, o, c, stream)
+        return [S.simrank_workspace_stats(ws) for ws in wss]
+
+    for _ in range(max(args.warmup, 1)):
+        ref = step()
+    work = [st.moves + st.tail_steps + st.source_moves for st in ref]
+    steps_per_step = int(sum(work))
+
+    torch.cuda.synchronize()
+    meet_ms, query_ms = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        sts = step()
+        for st, r in zip(sts, ref):
+            assert st.moves == r.moves and st.meets == r.meets   # deterministic work
+        meet_ms += [st.meet_ms for st in sts]
+        query_ms += [st.ms for st in sts]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    nq = len(queries) * args.steps
+    value = steps_per_step * args.steps / elapsed
+    moves_per_launch = float(np.mean([st.moves for st in ref]))
+    avg_meet_s = float(np.mean(meet_ms)) / 1e3
+    achieved = BYTES_PER_MOVE * moves_per_launch / avg_meet_s / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "medium: R-MAT n=2^20, 16n edge draws (.57,.19,.19,.05), dedup, "
+                        "permuted; c=0.6 eps=0.02 delta=1e-3 R=9502 L=64; "
+                        "8 single-source queries per step",
+            "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries_per_step": len(queries),
+        },
+        "queries_per_s": nq / elapsed,
+        "pairs_per_s": sum(st.pairs for st in ref) * args.steps / elapsed,
+        "moves_per_query": moves_per_launch,
+        "draws_per_query": float(np.mean([st.draws for st in ref])),
+        "meet_kernel_ms": float(np.mean(meet_ms)),
+        "query_ms": float(np.mean(query_ms)),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_meet (fused walk + meet + count)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+    }
+
+    if not args.no_cpu:
+        import oracle as O
+        s0 = int(sources[0])
+        rng = np.random.default_rng(11)
+        act = np.nonzero(g.in_degree() > 0)[0]
+        vs = np.sort(rng.choice(act, args.cpu_nodes, replace=False)).astype(np.int32)
+        t1 = time.perf_counter()
+        cnt, w = O.meet_counts_plain(g, s0, cfg["walk_seed"], cfg["c"], cfg["L"], R, vs=vs,
+                                     with_work=True)
+        dt = time.perf_counter() - t1
+        gpu_cnt = cnts[0].cpu().numpy().view(np.uint32)
+        same = bool(np.array_equal(gpu_cnt[vs], cnt))
+        pairs = vs.size * R
+        result["cpu_baseline"] = {
+            "value": float(w.sum()) / dt,
+            "unit": "walk-steps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"source {s0}, {vs.size} random nodes with in-edges x R={R} pairs "
+                      f"({pairs} pairs, {dt:.1f}s single-threaded); counts equal to the GPU's: {same}",
+            "queries_per_s": pairs / dt / ((g.n - 1) * R),
+        }
+    print(json.dumps(result))
+    for ws in wss:
+        ws.free()
+    G.free()
+
+
+if __name__ == "__main__":
+    main()

@@ -75,6 +75,15 @@ def lib() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_2304_04015_amd/build.py "
                           "(or __graft_entry__.build()) first; there is no fallback")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7.  When
+    # torch is loaded first, the loader satisfies this library's dependency on
+    # that soname with torch's copy, so device pointers and stream handles are
+    # shared; loading this library first would bring a second runtime that
+    # torch then fails to initialise next to.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
     P = C.POINTER
