@@ -37,9 +37,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-nodes", type=int, default=2048,
+    ap.add_argument("--cpu-nodes", type=int, default=6144,
                     help="nodes in the CPU oracle's sample (x R pairs, one source)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the queries, copy a buffer of this many MiB once (a kernel "
+                         "of known traffic that calibrates the profiler's byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_meet_medium.json"),
                     help="measured HBM traffic per meet launch (JSON), if present")
     return ap.parse_args()
@@ -61,6 +64,12 @@ def main():
 
     cfg = inputs.C2
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.time()
     g = inputs.workload_graph(cfg)
     sources = inputs.sources_with_in_edges(g, cfg["n_sources"], cfg["source_seed"])
