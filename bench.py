@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the queries, copy a buffer of this many MiB once (a kernel "
                          "of known traffic that calibrates the profiler's byte counters)")
+    ap.add_argument("--scale", type=int, default=0,
+                    help="R-MAT scale of the graph (0: the medium workload's 20)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_meet_medium.json"),
                     help="measured HBM traffic per meet launch (JSON), if present")
     return ap.parse_args()
@@ -62,7 +64,9 @@ def main():
     from paper_2304_04015_amd import inputs
     from paper_2304_04015_amd import simrank as S
 
-    cfg = inputs.C2
+    cfg = dict(inputs.C2)
+    if args.scale:
+        cfg["scale"] = args.scale
     torch.cuda.set_device(0)
     if args.copy_probe_mib:
         a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
@@ -131,7 +135,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "medium: R-MAT n=2^20, 16n edge draws (.57,.19,.19,.05), dedup, "
+            "workload": f"{'medium: ' if cfg['scale'] == 20 else ''}R-MAT n=2^{cfg['scale']}, "
+                        "16n edge draws (.57,.19,.19,.05), dedup, "
                         "permuted; c=0.6 eps=0.02 delta=1e-3 R=9502 L=64; "
                         "8 single-source queries per step",
             "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries_per_step": len(queries),

@@ -233,6 +233,20 @@ struct MeetArgs {
     int32_t n_chunks;
 };
 
+// The walk's gather of an edge slot.  SRK_EDGE_LOAD selects the cache policy
+// (0: default, 1: non-temporal).
+#ifndef SRK_EDGE_LOAD
+#define SRK_EDGE_LOAD 0
+#endif
+__device__ __forceinline__ uint2 load_edge(const uint2 *p) {
+#if SRK_EDGE_LOAD == 1
+    const uint64_t v = __builtin_nontemporal_load((const uint64_t *)p);
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+#else
+    return *p;
+#endif
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -298,7 +312,8 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
         uint32_t ck = 0;
 
         bool busy = false;
-        uint32_t my_vl = 0, my_v = 0, my_j = 0, my_base = 0, my_len = 0, t = 0, o = 0, d = 0;
+        uint32_t my_vl = 0, my_v = 0, my_base = 0, my_len = 0, t = 0, o = 0, d = 0;
+        WalkDraws rng{};
         // stitched tail state: tail >= 1 once the private head is complete
         uint32_t tail_sigma = 0, tail_m = 0, tail_u = 0, tail_seg = 0, tail_sl = 0;
         bool in_tail = false;
@@ -315,7 +330,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
                     const uint32_t kk = ck + rank;
                     my_vl = cv;
                     my_v = cv_id;
-                    my_j = s_j[kk];
+                    rng = walk_draws_begin(cv_id, s_j[kk], a.key);
                     my_base = s_off[kk];
                     my_len = (uint32_t)s_off[kk + 1] - my_base;
                     o = cv_row.x;
@@ -337,12 +352,12 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
 
             if (!STITCHED || !in_tail) {
                 ++t;
-                const uint4 x = philox4x32_10(my_v, my_j, t, DOM_WALK, a.key);
+                const uint2 x = walk_draw_next(rng, a.key);
                 ++st_draws;
                 if (x.x >= a.T) {
                     busy = false;
                 } else {
-                    const uint2 e = a.E[o + pick32(x.y, d)];
+                    const uint2 e = load_edge(a.E + o + pick32(x.y, d));
                     ++st_moves;
                     o = e.x;
                     d = e.y;
@@ -354,7 +369,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
                         busy = false;
                     } else if (STITCHED && t == (uint32_t)a.ix.seg_len) {
                         const uint32_t y = a.ix.node_of[o];
-                        tail_sigma = entry_slot(a.ix, a.key, my_v, my_j, y);
+                        tail_sigma = entry_slot(a.ix, a.key, my_v, rng.j, y);
                         tail_m = 0;
                         tail_u = 0;
                         tail_seg = tail_sigma;

@@ -16,7 +16,9 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsimrank.so")
+# SIMRANK_LIB may name another build of the same sources (e.g. one compiled
+# with different -D options); the default is the package's own library.
+LIB_PATH = os.environ.get("SIMRANK_LIB") or os.path.join(HERE, "libsimrank.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "simrank.h")
 
 SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
