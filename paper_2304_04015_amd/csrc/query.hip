@@ -205,11 +205,16 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t *__restrict__ sl
 //
 // Persistent blocks take work units (tile of source walks x chunk of MEET_VB
 // nodes) from a device cursor.  A block stages its tile (walk ids, packed
-// positions) in LDS once and keeps it while consecutive units share the tile.
-// Inside a unit each wave takes one node v at a time from an LDS cursor and
-// spreads the tile's K pairs (v, j) over its 64 lanes; a lane that finishes a
-// pair (stop, meet, or end of walk (s, j)) is refilled with the next pair
-// before the next step, so all lanes keep stepping until the unit runs dry.
+// positions) in LDS once and keeps it while consecutive units share the tile,
+// and stages the chunk's nodes (id, row) per unit.
+//
+// Inside a unit the pairs (v, k), v-major, are handed out from one block-wide
+// cursor in chunks of 64 to the waves, so all waves of a block work on the same
+// one or two nodes v at a time: the rows a walk reads at its first two steps
+// (v's own row and those of its in-neighbours) are then shared by the whole
+// block and stay in the CU's L1.  Each lane runs NS independent pairs (slots)
+// so that NS gathers per lane are in flight at once; a slot whose pair ended
+// (stop, meet, or end of walk (s, j)) is refilled before the next step.
 // A step: one Philox draw, a multiply-high neighbour pick, one 8-byte gather
 // of E, one LDS compare.  Meets go to an LDS counter per node, flushed to the
 // global counts once per unit.
@@ -252,13 +257,28 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-template <bool STITCHED>
+// One pair in flight on a lane.
+struct Slot {
+    uint32_t pos;    // packed: LDS offset of walk (s, j) (16 bits) | its length << 16 | node index << 24
+    uint32_t t;      // steps taken
+    uint32_t o, d;   // current node: slot offset in E and in-degree
+    WalkDraws rng;
+    bool busy;
+    bool in_tail;    // stitched: the private head is complete
+    uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position, segment, its length
+};
+
+constexpr uint32_t ITEM_CHUNK = 64;
+
+template <bool STITCHED, int NS>
 __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
     __shared__ uint32_t s_nodes[TILE_NODES];
     __shared__ uint32_t s_j[TILE_J];
     __shared__ uint16_t s_off[TILE_J + 1];
     __shared__ uint32_t s_cnt[MEET_VB];
-    __shared__ uint32_t s_unit, s_vnext;
+    __shared__ uint32_t s_vid[MEET_VB];
+    __shared__ uint2 s_vrow[MEET_VB];
+    __shared__ uint32_t s_unit, s_item;
 
     const int lane = threadIdx.x & 63;
     const uint32_t n_tiles = a.meta[2];
@@ -286,122 +306,175 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
             for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = a.swc[nb + i];
             cur_tile = tile;
         }
-        for (uint32_t i = threadIdx.x; i < MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
-        if (threadIdx.x == 0) s_vnext = 0u;
-        __syncthreads();
-
         const int32_t vbase = (int32_t)chunk * MEET_VB;
         const uint32_t nv = (uint32_t)min(MEET_VB, a.n_active - vbase);
-
-        // wave-uniform cursor: current node (local index cv, id, row) and next pair index ck
-        uint32_t cv, cv_id = 0;
-        uint2 cv_row = make_uint2(0u, 0u);
-        auto fetch_v = [&]() {
-            for (;;) {
-                uint32_t x = 0;
-                if (lane == 0) x = atomicAdd(&s_vnext, 1u);
-                cv = __builtin_amdgcn_readfirstlane(x);
-                if (cv >= nv) return;
-                cv_id = (uint32_t)a.active[vbase + (int32_t)cv];
-                if ((int32_t)cv_id == a.s) continue;   // the source's own pairs are not walked
-                cv_row = a.nodes[cv_id];
-                return;
+        for (uint32_t i = threadIdx.x; i < MEET_VB; i += blockDim.x) {
+            s_cnt[i] = 0u;
+            if (i < nv) {
+                const uint32_t id = (uint32_t)a.active[vbase + (int32_t)i];
+                s_vid[i] = id;
+                s_vrow[i] = a.nodes[id];
             }
-        };
-        fetch_v();
-        uint32_t ck = 0;
+        }
+        if (threadIdx.x == 0) s_item = 0u;
+        __syncthreads();
 
-        bool busy = false;
-        uint32_t my_vl = 0, my_v = 0, my_base = 0, my_len = 0, t = 0, o = 0, d = 0;
-        WalkDraws rng{};
-        // stitched tail state: tail >= 1 once the private head is complete
-        uint32_t tail_sigma = 0, tail_m = 0, tail_u = 0, tail_seg = 0, tail_sl = 0;
-        bool in_tail = false;
+        // Pairs of the unit: item i = vl * K + k for node vl < nv and walk k < K.
+        const uint32_t total = nv * K;
+        // wave-uniform chunk of items [ci, ce) and the (node, walk) of item ci
+        uint32_t ci = 0, ce = 0, cvl = 0, ck = 0;
+        bool drained = false;
+
+        Slot sl[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            sl[q].busy = false;
+            sl[q].in_tail = false;
+        }
 
         for (;;) {
-            uint64_t need = __ballot(!busy);
-            while (need != 0ull && cv < nv) {
-                const uint32_t avail = K - ck;
-                const uint32_t want = (uint32_t)__popcll(need);
-                const uint32_t take = avail < want ? avail : want;
-                const uint32_t rank = lane_rank(need);
-                const bool mine = ((need >> lane) & 1ull) && rank < take;
-                if (mine) {
-                    const uint32_t kk = ck + rank;
-                    my_vl = cv;
-                    my_v = cv_id;
-                    rng = walk_draws_begin(cv_id, s_j[kk], a.key);
-                    my_base = s_off[kk];
-                    my_len = (uint32_t)s_off[kk + 1] - my_base;
-                    o = cv_row.x;
-                    d = cv_row.y;
-                    t = 0;
-                    busy = true;
-                    in_tail = false;
-                    ++st_pairs;
-                }
-                need &= ~__ballot(mine);
-                ck += take;
-                if (ck == K) {
-                    fetch_v();
-                    ck = 0;
-                }
-            }
-            if (__ballot(busy) == 0ull) break;
-            if (!busy) continue;
-
-            if (!STITCHED || !in_tail) {
-                ++t;
-                const uint2 x = walk_draw_next(rng, a.key);
-                ++st_draws;
-                if (x.x >= a.T) {
-                    busy = false;
-                } else {
-                    const uint2 e = load_edge(a.E + o + pick32(x.y, d));
-                    ++st_moves;
-                    o = e.x;
-                    d = e.y;
-                    if (o == s_nodes[my_base + t - 1]) {
-                        atomicAdd(&s_cnt[my_vl], 1u);
-                        ++st_meets;
-                        busy = false;
-                    } else if (t == my_len || d == 0u) {
-                        busy = false;
-                    } else if (STITCHED && t == (uint32_t)a.ix.seg_len) {
-                        const uint32_t y = a.ix.node_of[o];
-                        tail_sigma = entry_slot(a.ix, a.key, my_v, rng.j, y);
-                        tail_m = 0;
-                        tail_u = 0;
-                        tail_seg = tail_sigma;
-                        tail_sl = a.ix.seg_lens[tail_seg];
-                        in_tail = true;
-                        if (tail_sl == 0u) busy = false;
+            // ---- refill idle slots from the block's cursor
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                uint64_t need = __ballot(!sl[q].busy);
+                while (need != 0ull) {
+                    if (ci == ce) {
+                        if (drained) break;
+                        uint32_t x = 0;
+                        if (lane == 0) x = atomicAdd(&s_item, ITEM_CHUNK);
+                        x = __builtin_amdgcn_readfirstlane(x);
+                        if (x >= total) {
+                            drained = true;
+                            break;
+                        }
+                        ci = x;
+                        ce = min(x + ITEM_CHUNK, total);
+                        cvl = x / K;
+                        ck = x - cvl * K;
+                    }
+                    const uint32_t want = (uint32_t)__popcll(need);
+                    const uint32_t avail = ce - ci;
+                    const uint32_t take = avail < want ? avail : want;
+                    const uint32_t rank = lane_rank(need);
+                    const bool mine = ((need >> lane) & 1ull) && rank < take;
+                    if (mine) {
+                        uint32_t k = ck + rank, vl = cvl;
+                        while (k >= K) {
+                            k -= K;
+                            ++vl;
+                        }
+                        const uint32_t id = s_vid[vl];
+                        if ((int32_t)id != a.s) {   // the source's own pairs are not walked
+                            const uint32_t base = s_off[k];
+                            const uint32_t len = (uint32_t)s_off[k + 1] - base;
+                            const uint2 row = s_vrow[vl];
+                            sl[q].pos = base | (len << 16) | (vl << 24);
+                            sl[q].rng = walk_draws_begin(id, s_j[k], a.key);
+                            sl[q].t = 0;
+                            sl[q].o = row.x;
+                            sl[q].d = row.y;
+                            sl[q].busy = true;
+                            sl[q].in_tail = false;
+                            ++st_pairs;
+                        }
+                    }
+                    need &= ~__ballot(mine);
+                    ci += take;
+                    ck += take;
+                    while (ck >= K && K > 0) {
+                        ck -= K;
+                        ++cvl;
                     }
                 }
-            } else {
-                // one step read from the index: position u of segment tail_seg
-                ++t;
-                ++st_tail;
-                o = a.ix.seg[(size_t)tail_seg * a.ix.seg_len + tail_u];
-                ++tail_u;
-                if (o == s_nodes[my_base + t - 1]) {
-                    atomicAdd(&s_cnt[my_vl], 1u);
-                    ++st_meets;
-                    busy = false;
-                } else if (t == my_len) {
-                    busy = false;
-                } else if (tail_u == tail_sl) {
-                    if (tail_sl < (uint32_t)a.ix.seg_len || tail_m + 1 >= (uint32_t)a.ix.width) {
-                        busy = false;
+            }
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) any |= sl[q].busy;
+            // A refill round can hand out only the source's own pairs, which are
+            // skipped: a wave leaves only once the block's cursor is drained.
+            if (__ballot(any) == 0ull) {
+                if (drained) break;
+                continue;
+            }
+
+            // ---- head steps: draws, then all gathers, then the compares
+            bool go[NS];
+            uint32_t at[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                go[q] = false;
+                at[q] = 0;
+                if (sl[q].busy && !(STITCHED && sl[q].in_tail)) {
+                    ++sl[q].t;
+                    const uint2 x = walk_draw_next(sl[q].rng, a.key);
+                    ++st_draws;
+                    if (x.x >= a.T) {
+                        sl[q].busy = false;
                     } else {
-                        ++tail_m;
-                        tail_seg = a.ix.chain[(size_t)tail_sigma * a.ix.width + tail_m];
-                        tail_u = 0;
-                        if (tail_seg == NIL) {
-                            busy = false;
+                        go[q] = true;
+                        at[q] = sl[q].o + pick32(x.y, sl[q].d);
+                    }
+                }
+            }
+            uint2 e[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (go[q]) e[q] = load_edge(a.E + at[q]);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                if (!go[q]) continue;
+                ++st_moves;
+                Slot &w = sl[q];
+                w.o = e[q].x;
+                w.d = e[q].y;
+                const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
+                if (w.o == s_nodes[base + w.t - 1]) {
+                    atomicAdd(&s_cnt[w.pos >> 24], 1u);
+                    ++st_meets;
+                    w.busy = false;
+                } else if (w.t == len || w.d == 0u) {
+                    w.busy = false;
+                } else if (STITCHED && w.t == (uint32_t)a.ix.seg_len) {
+                    const uint32_t y = a.ix.node_of[w.o];
+                    w.tsig = entry_slot(a.ix, a.key, s_vid[w.pos >> 24], w.rng.j, y);
+                    w.tm = 0;
+                    w.tu = 0;
+                    w.tseg = w.tsig;
+                    w.tsl = a.ix.seg_lens[w.tseg];
+                    w.in_tail = true;
+                    if (w.tsl == 0u) w.busy = false;
+                }
+            }
+            // ---- stitched tails: one step read from the index
+            if (STITCHED) {
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    Slot &w = sl[q];
+                    if (!(w.busy && w.in_tail) || go[q]) continue;
+                    ++w.t;
+                    ++st_tail;
+                    w.o = a.ix.seg[(size_t)w.tseg * a.ix.seg_len + w.tu];
+                    ++w.tu;
+                    const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
+                    if (w.o == s_nodes[base + w.t - 1]) {
+                        atomicAdd(&s_cnt[w.pos >> 24], 1u);
+                        ++st_meets;
+                        w.busy = false;
+                    } else if (w.t == len) {
+                        w.busy = false;
+                    } else if (w.tu == w.tsl) {
+                        if (w.tsl < (uint32_t)a.ix.seg_len || w.tm + 1 >= (uint32_t)a.ix.width) {
+                            w.busy = false;
                         } else {
-                            tail_sl = a.ix.seg_lens[tail_seg];
-                            if (tail_sl == 0u) busy = false;
+                            ++w.tm;
+                            w.tseg = a.ix.chain[(size_t)w.tsig * a.ix.width + w.tm];
+                            w.tu = 0;
+                            if (w.tseg == NIL) {
+                                w.busy = false;
+                            } else {
+                                w.tsl = a.ix.seg_lens[w.tseg];
+                                if (w.tsl == 0u) w.busy = false;
+                            }
                         }
                     }
                 }
@@ -410,7 +483,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
             const uint32_t c = s_cnt[i];
-            if (c) atomicAdd(&a.cnt[a.active[vbase + (int32_t)i]], c);
+            if (c) atomicAdd(&a.cnt[s_vid[i]], c);
         }
     }
 
@@ -430,6 +503,13 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
         atomicAdd(&a.counters[C_PAIRS], v4);
     }
 }
+
+#ifndef SRK_MEET_SLOTS
+#define SRK_MEET_SLOTS 2
+#endif
+#ifndef SRK_MEET_SLOTS_STITCHED
+#define SRK_MEET_SLOTS_STITCHED 1
+#endif
 
 // ------------------------------------------------------ walk materialisation
 
@@ -501,7 +581,8 @@ int meet_grid_blocks() {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<false>, MEET_BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<false, SRK_MEET_SLOTS>,
+                                                           MEET_BLOCK, 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
         blocks = cus * per;
@@ -629,9 +710,9 @@ int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &
         const int64_t max_units = (int64_t)max_tiles_for(p.R, p.L) * n_chunks;
         const int blocks = (int)std::min<int64_t>(max_units, meet_grid_blocks());
         if (stitched)
-            k_meet<true><<<blocks, MEET_BLOCK, 0, st>>>(ma);
+            k_meet<true, SRK_MEET_SLOTS_STITCHED><<<blocks, MEET_BLOCK, 0, st>>>(ma);
         else
-            k_meet<false><<<blocks, MEET_BLOCK, 0, st>>>(ma);
+            k_meet<false, SRK_MEET_SLOTS><<<blocks, MEET_BLOCK, 0, st>>>(ma);
     }
     SRK_HIP(hipEventRecord(ws->evm1, st));
     k_estimate<<<grid_for(g->n, 256), 256, 0, st>>>(counts_dev, out_dev, g->n, p.R, q->s);
