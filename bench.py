@@ -32,6 +32,29 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_MOVE = 8
 
 
+def kernel_fingerprint() -> str:
+    """sha256 (16 hex digits) of the sources the meet kernel is built from."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2304_04015_amd", "csrc")
+    h = b"".join(open(os.path.join(csrc, f), "rb").read()
+                 for f in ("query.hip", "philox.hpp", "common.hpp"))
+    return hashlib.sha256(h).hexdigest()[:16]
+
+
+def measured_traffic(path: str):
+    """HBM bytes per meet launch from the profiler's byte counters (scaled by a
+    copy kernel of known size), if they were taken on the current kernel."""
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("source_sha256_16") != kernel_fingerprint():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +66,8 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the queries, copy a buffer of this many MiB once (a kernel "
                          "of known traffic that calibrates the profiler's byte counters)")
+    ap.add_argument("--no-roofs", action="store_true",
+                    help="skip the measured gather / Philox / copy ceilings")
     ap.add_argument("--scale", type=int, default=0,
                     help="R-MAT scale of the graph (0: the medium workload's 20)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_meet_medium.json"),
@@ -114,12 +139,7 @@ def main():
     moves_per_launch = float(np.mean([st.moves for st in ref]))
     avg_meet_s = float(np.mean(meet_ms)) / 1e3
     achieved = BYTES_PER_MOVE * moves_per_launch / avg_meet_s / 1e9
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic)
 
     result = {
         "metric": METRIC,
@@ -157,6 +177,27 @@ def main():
             "traffic": traffic,
         },
     }
+
+    if not args.no_roofs:
+        info = G.info()
+        slots_bytes = 8 * (info["m"] + info["n"] - info["n_active"])
+        gi = S.simrank_roofline_gather(slots_bytes, 8, dependent=False)
+        gd = S.simrank_roofline_gather(slots_bytes, 8, dependent=True)
+        ph = S.simrank_roofline_philox()
+        cp = S.simrank_roofline_copy(1 << 30)
+        moves_per_s = moves_per_launch / avg_meet_s
+        draws_per_s = float(np.mean([st.draws for st in ref])) / avg_meet_s
+        result["measured_roofs"] = {
+            "footprint_bytes": slots_bytes,
+            "random_gather_8B_per_s": gi["per_s"],
+            "dependent_chain_gather_8B_per_s": gd["per_s"],
+            "philox_draws_per_s": ph["per_s"],
+            "copy_bytes_per_s": cp["per_s"],
+            "kernel_moves_per_s": moves_per_s,
+            "kernel_draws_per_s": draws_per_s,
+            "moves_vs_random_gather": moves_per_s / gi["per_s"],
+            "draws_vs_philox": draws_per_s / ph["per_s"],
+        }
 
     if not args.no_cpu:
         import oracle as O

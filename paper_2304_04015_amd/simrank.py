@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # SIMRANK_LIB may name another build of the same sources (e.g. one compiled
 # with different -D options); the default is the package's own library.
 LIB_PATH = os.environ.get("SIMRANK_LIB") or os.path.join(HERE, "libsimrank.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "simrank.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADER = os.path.join(INCLUDE, "simrank.h")
 
 SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
 MODE_PLAIN, MODE_STITCHED = 0, 1
@@ -56,6 +57,13 @@ class simrank_stats(C.Structure):
 class simrank_index_params(C.Structure):
     _fields_ = [("seg_log2", C.c_int32), ("reserved", C.c_int32), ("kappa", C.c_double),
                 ("c", C.c_double), ("seed", C.c_uint64)]
+
+
+class simrank_rate(C.Structure):
+    _fields_ = [("per_s", C.c_double), ("ms", C.c_double), ("count", C.c_double)]
+
+    def asdict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class simrank_index_summary(C.Structure):
@@ -105,6 +113,9 @@ def lib() -> C.CDLL:
         "simrank_index_info": [vp, P(simrank_index_summary)],
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
         "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
+        "simrank_roofline_gather": [i64, i32, i32, P(simrank_rate)],
+        "simrank_roofline_philox": [P(simrank_rate)],
+        "simrank_roofline_copy": [i64, P(simrank_rate)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -119,10 +130,15 @@ def lib() -> C.CDLL:
 
 
 def header_functions() -> list[str]:
-    """Names of the functions include/simrank.h declares."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(simrank_\w+)\s*\(", text, re.M)))
+    """Names of the functions the headers under include/ declare."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if not f.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(simrank_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def _check(rc: int) -> None:
@@ -306,6 +322,26 @@ def simrank_batch(graphs: list[Graph], queries: list[simrank_query], want_counts
     st = simrank_stats()
     _check(lib().simrank_batch(garr, ng, qarr, nq, oarr, carr, C.byref(st)))
     return outs, cnts, st
+
+
+def simrank_roofline_gather(footprint_bytes: int, entry_bytes: int = 8,
+                            dependent: bool = False) -> dict:
+    r = simrank_rate()
+    _check(lib().simrank_roofline_gather(int(footprint_bytes), entry_bytes, 1 if dependent else 0,
+                                         C.byref(r)))
+    return r.asdict()
+
+
+def simrank_roofline_philox() -> dict:
+    r = simrank_rate()
+    _check(lib().simrank_roofline_philox(C.byref(r)))
+    return r.asdict()
+
+
+def simrank_roofline_copy(nbytes: int) -> dict:
+    r = simrank_rate()
+    _check(lib().simrank_roofline_copy(int(nbytes), C.byref(r)))
+    return r.asdict()
 
 
 def simrank_version() -> str:

@@ -183,3 +183,14 @@ def test_c2_full_size_sampled(c2):
         assert cnt[s] == st.R
         assert np.all(cnt[deg == 0][np.nonzero(deg == 0)[0] != s] == 0)
         _say(f"  moves={st.moves} draws={st.draws} meet_ms={st.meet_ms:.2f} ms={st.ms:.2f}")
+
+
+def test_roofline_probes_run():
+    r = S.simrank_roofline_gather(1 << 24, 8, dependent=False)
+    assert r["per_s"] > 1e9 and r["ms"] > 0
+    r = S.simrank_roofline_gather(1 << 24, 4, dependent=True)
+    assert r["per_s"] > 1e8
+    assert S.simrank_roofline_philox()["per_s"] > 1e10
+    assert S.simrank_roofline_copy(1 << 26)["per_s"] > 1e11
+    with pytest.raises(S.SimRankError):
+        S.simrank_roofline_gather(100, 8)
