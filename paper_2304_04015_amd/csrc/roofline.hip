@@ -52,13 +52,17 @@ __global__ __launch_bounds__(RF_BLOCK) void k_rf_gather(const T *__restrict__ bu
     if (acc == 0x5eed5eed5eedull) sink[0] = acc;   // keeps the loads
 }
 
-// Dependent chains: each lane follows next = buf[cur].
+// Dependent chains: each lane's next index is a hash of the value it just
+// loaded and its own salt, so lanes never fall into shared paths (plain
+// next = buf[cur] chains merge and then share cache lines).
 template <typename T>
 __global__ __launch_bounds__(RF_BLOCK) void k_rf_chase(const T *__restrict__ buf, uint64_t n,
                                                        int32_t iters, uint64_t *__restrict__ sink) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t salt = mix32(gid ^ 0xa5a5a5a5u);
     uint64_t cur = ((uint64_t)mix32(gid + 7u) * n) >> 32;
-    for (int32_t i = 0; i < iters; ++i) cur = (uint64_t)buf[cur] % n;
+    for (int32_t i = 0; i < iters; ++i)
+        cur = ((uint64_t)mix32((uint32_t)buf[cur] ^ salt ^ (uint32_t)i) * n) >> 32;
     if (cur == 0x5eed5eedull) sink[0] = cur;
 }
 
