@@ -21,6 +21,7 @@ Recipes (numpy PCG64 throughout):
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -85,8 +86,50 @@ def erdos_renyi_in(n: int, mean_in: float = 5.0, seed: int = 1) -> CSR:
                       dedupe=True, drop_self_loops=True)
 
 
+def _rmat_chunk(seed_seq, scale: int, e: int, t_a, t_ab, t_abc, n: int, full: int):
+    """e R-MAT draws from one independent stream; returns (u, v) kept draws."""
+    rng = np.random.Generator(np.random.PCG64(seed_seq))
+    u = np.zeros(e, np.int64)
+    v = np.zeros(e, np.int64)
+    for bit in range(scale):
+        r = rng.random(e, dtype=np.float32)
+        ub = r >= t_ab                                  # quadrants c, d: lower half of rows
+        vb = ((r >= t_a) & (r < t_ab)) | (r >= t_abc)   # quadrants b, d
+        u |= ub.astype(np.int64) << bit
+        v |= vb.astype(np.int64) << bit
+    if n < full:
+        keep = (u < n) & (v < n)
+        u, v = u[keep], v[keep]
+    return u, v
+
+
+def _unique_keys_parallel(key: np.ndarray, n_buckets: int, threads: int) -> np.ndarray:
+    """np.unique(key) for non-negative keys, computed bucket by bucket (buckets by
+    the top bits of the key, split with one radix argsort) on a thread pool."""
+    import concurrent.futures as cf
+    if key.size == 0:
+        return key
+    kmax = int(key.max()) + 1
+    shift = max(0, int(kmax - 1).bit_length() - int(n_buckets - 1).bit_length())
+    b = (key >> shift).astype(np.uint8)
+    order = np.argsort(b, kind="stable")       # radix sort of small integers
+    key = key[order]
+    del order
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(b, minlength=n_buckets))])
+    del b
+    parts = [key[bounds[i]:bounds[i + 1]] for i in range(n_buckets)]
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(np.unique, parts))
+    return np.concatenate(parts)
+
+
 def rmat_in(scale: int, n_edges: int, abcd=(0.57, 0.19, 0.19, 0.05), seed: int = 2,
-            n: int | None = None, permute: bool = True, chunk: int = 1 << 23) -> CSR:
+            n: int | None = None, permute: bool = True, chunk: int = 1 << 22,
+            threads: int | None = None) -> CSR:
+    """R-MAT draws in chunks of `chunk`; chunk i is drawn from the child stream
+    SeedSequence(seed, spawn_key=(i,)), so the graph does not depend on the
+    thread count."""
+    import concurrent.futures as cf
     a, b, c, d = abcd
     if abs(a + b + c + d - 1.0) > 1e-9:
         raise ValueError("R-MAT probabilities must sum to 1")
@@ -94,36 +137,43 @@ def rmat_in(scale: int, n_edges: int, abcd=(0.57, 0.19, 0.19, 0.05), seed: int =
     n = full if n is None else int(n)
     if not (0 < n <= full):
         raise ValueError("n must lie in (0, 2**scale]")
-    rng = np.random.Generator(np.random.PCG64(seed))
+    threads = threads or min(16, os.cpu_count() or 1)
     t_ab, t_abc = np.float32(a + b), np.float32(a + b + c)
     t_a = np.float32(a)
-    keys = []
+    us, vs = [], []
     kept = 0
+    next_child = 0
+    # draw rounds of `threads` chunks until n_edges draws are kept (rejection for n < 2^scale)
     while kept < n_edges:
-        e = min(chunk, max(int(n_edges) - kept, 1 << 16))
-        u = np.zeros(e, np.int64)
-        v = np.zeros(e, np.int64)
-        for bit in range(scale):
-            r = rng.random(e, dtype=np.float32)
-            ub = r >= t_ab                      # quadrants c, d: lower half of rows
-            vb = ((r >= t_a) & (r < t_ab)) | (r >= t_abc)   # quadrants b, d
-            u |= ub.astype(np.int64) << bit
-            v |= vb.astype(np.int64) << bit
-        if n < full:
-            keep = (u < n) & (v < n)
-            u, v = u[keep], v[keep]
-        take = min(u.size, int(n_edges) - kept)
-        keys.append((u[:take], v[:take]))
-        kept += take
-    u = np.concatenate([k[0] for k in keys])
-    v = np.concatenate([k[1] for k in keys])
-    del keys
+        need = int(n_edges) - kept
+        nch = max(1, min(threads, -(-need // chunk)))
+        seqs = [np.random.SeedSequence(seed, spawn_key=(next_child + i,)) for i in range(nch)]
+        next_child += nch
+        sizes = [min(chunk, max(need - i * chunk, 1 << 16)) for i in range(nch)]
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            res = list(ex.map(lambda ar: _rmat_chunk(ar[0], scale, ar[1], t_a, t_ab, t_abc, n, full),
+                              zip(seqs, sizes)))
+        for u, v in res:
+            take = min(u.size, int(n_edges) - kept)
+            if take <= 0:
+                break
+            us.append(u[:take])
+            vs.append(v[:take])
+            kept += take
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    del us, vs
     if permute:
         perm = np.random.Generator(np.random.PCG64(seed ^ 0x5EED)).permutation(n).astype(np.int64)
         u = perm[u]
         v = perm[v]
+    key = v * n + u
+    del u, v
+    key = _unique_keys_parallel(key, 64, threads)
+    dst = key // n
+    src = key - dst * n
     name = f"rmat_s{scale}_n{n}_e{n_edges}_seed{seed}"
-    return from_edges(n, u, v, name=name, dedupe=True, drop_self_loops=False)
+    return _csr_from_sorted_keys(n, dst, src, name)
 
 
 def sources_with_in_edges(g: CSR, count: int, seed: int) -> np.ndarray:

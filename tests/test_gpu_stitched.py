@@ -138,3 +138,66 @@ def test_stitched_requires_matching_index(small):
     with pytest.raises(S.SimRankError) as e:
         S.simrank_single_source_ex(G, S.make_query(1, c=0.6, mode=S.MODE_STITCHED, R=10))
     assert e.value.code == S.SIMRANK_EINVAL
+
+
+@pytest.mark.slow
+def test_c3_stitching_at_scale():
+    """Stitching workload at full size: R-MAT n=2^24, avg degree 16 (~2.6e8
+    edges), segment pools sized by in-degree (kappa=1, 2^3-step segments,
+    3 doubling rounds), eps=0.02 -> R=9502, L=64.  Bit-exact against the
+    oracle's direct generation (each segment regenerated from the CSR under the
+    same Philox keys): the index size, 4096 sampled slots (segment, successor),
+    all R source walks, 2^20 sampled stitched walks (v, j), and the stitched
+    query's meet counts on 48 sampled nodes."""
+    cfg = inputs.C3
+    _say("generating the R-MAT scale-24 graph")
+    g = inputs.workload_graph(cfg)
+    _say(f"n={g.n} m={g.m}; loading")
+    G = S.load_csr(g)
+    k = cfg["seg_log2"]
+    info = S.simrank_build_index(G, seg_log2=k, kappa=cfg["kappa"], c=cfg["c"],
+                                 seed=cfg["index_seed"])
+    _say(f"index: {info}")
+    P = O.pool_sizes(g, cfg["kappa"])
+    assert info["segments"] == int(P.sum()) and info["levels"] == 3
+    pool_off = np.concatenate([[0], np.cumsum(P)])
+    rng = np.random.default_rng(24)
+    # sampled slots: segment nodes and successor slot
+    sig = np.sort(rng.integers(0, int(P.sum()), 4096)).astype(np.int64)
+    nodes, lens, succ, chain = S.simrank_index_read(G, sig)
+    owner = np.searchsorted(pool_off, sig, side="right") - 1
+    for r, s_ in enumerate(sig):
+        y = int(owner[r])
+        i = int(s_ - pool_off[y])
+        want = O.segment(g, cfg["index_seed"], cfg["c"], 1 << k, y, i)
+        assert lens[r] == want.size and np.array_equal(nodes[r, : want.size], want)
+        if want.size == (1 << k):
+            x = O.philox([y, i, 0, 3], [cfg["index_seed"] & 0xffffffff, cfg["index_seed"] >> 32])
+            z = int(want[-1])
+            assert succ[r] == pool_off[z] + ((int(x[0]) * int(P[z])) >> 32)
+        else:
+            assert succ[r] == -1
+    s = int(inputs.sources_with_in_edges(g, 1, cfg["source_seed"])[0])
+    q = S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
+                     walk_cap=cfg["L"], mode=S.MODE_STITCHED)
+    R = S.simrank_derive_params(q, g.n).R
+    assert R == 9502
+    act = np.nonzero(g.in_degree() > 0)[0]
+    vs = np.concatenate([np.full(R, s), rng.choice(act, 1 << 20)]).astype(np.int32)
+    js = np.concatenate([np.arange(R), rng.integers(0, R, 1 << 20)]).astype(np.uint32)
+    _say("stitched walks on the GPU")
+    paths, plens = S.simrank_walks(G, q, vs, js)
+    _say("stitched walks in the oracle")
+    opaths, olens = O.walk_table_stitched(g, cfg["walk_seed"], cfg["index_seed"], cfg["c"],
+                                          cfg["L"], 1 << k, P, vs, js)
+    assert np.array_equal(plens, olens)
+    assert np.array_equal(paths, opaths)
+    assert (plens > (1 << k)).sum() > 10000
+    _say("stitched query")
+    out, cnt, st = S.simrank_single_source_ex(G, q)
+    smp = np.union1d(rng.choice(act, 40, replace=False), np.argsort(g.in_degree())[-8:])
+    smp = np.union1d(smp, [s]).astype(np.int32)
+    want = O.meet_counts_stitched(g, s, cfg["walk_seed"], cfg["index_seed"], cfg["c"], cfg["L"],
+                                  1 << k, P, R, vs=smp)
+    assert np.array_equal(cnt[smp], want)
+    _say(f"query: moves={st.moves} tail_steps={st.tail_steps} meet_ms={st.meet_ms:.1f}")
