@@ -58,9 +58,11 @@ def measured_traffic(path: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "stitching"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "stitching", "batching"],
                     help="medium: the default line; stitching: R-MAT n=2^24 index build "
-                         "and stitched query")
+                         "and stitched query; batching: 512 queries over 16 graphs, "
+                         "one captured batch vs one query at a time")
+    ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-nodes", type=int, default=6144,
@@ -88,6 +90,8 @@ def main():
 
     if args.workload == "stitching":
         return bench_stitching(args)
+    if args.workload == "batching":
+        return bench_batching(args)
 
     import numpy as np
     import torch
@@ -300,6 +304,97 @@ def bench_stitching(args):
     print(json.dumps(result))
     ws.free()
     G.free()
+
+
+def bench_batching(args):
+    """Batching workload: 16 R-MAT graphs with n = floor(2^U(12,22)) and average
+    degree U{8..32}; queries with a uniform graph, a source drawn uniformly among
+    its nodes with in-edges, eps from {0.05, 0.02, 0.01}, delta = 1e-3, L = 64 and
+    a seed of their own.  The same queries run (a) one at a time through the
+    asynchronous single-query call on one stream and (b) as one captured batch
+    plan; both after the unit-size tuner has run once per graph."""
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = inputs.C4
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    specs = inputs.batch_graph_specs(cfg)
+    gs = [inputs.batch_graph(sp) for sp in specs]
+    print(f"# {len(gs)} graphs, {sum(g.m for g in gs)} edges, generated in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr)
+    Gs = [S.load_csr(g) for g in gs]
+    rng = np.random.default_rng(cfg["mix_seed"] + 1)
+    queries = []
+    for i in range(args.queries):
+        gi = int(rng.integers(0, len(gs)))
+        act = np.nonzero(gs[gi].in_degree() > 0)[0]
+        eps = float(rng.choice(cfg["eps_choices"]))
+        queries.append(S.make_query(int(rng.choice(act)), c=cfg["c"], eps=eps, delta=cfg["delta"],
+                                    seed=0x2304040150000400 + i, walk_cap=cfg["L"], graph=gi))
+    tuned = []
+    for gi, G in enumerate(Gs):
+        act = np.nonzero(gs[gi].in_degree() > 0)[0]
+        tq = S.make_query(int(act[0]), c=cfg["c"], eps=0.02, delta=cfg["delta"], walk_cap=cfg["L"])
+        tuned.append(S.simrank_tune(G, tq))
+    # (a) one query at a time
+    maxR = [1] * len(Gs)
+    for q in queries:
+        maxR[q.graph] = max(maxR[q.graph], S.simrank_derive_params(q, gs[q.graph].n).R)
+    wss = [S.simrank_workspace_create(G, maxR[i], cfg["L"]) for i, G in enumerate(Gs)]
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in gs]
+    cnts = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in gs]
+    stream = torch.cuda.Stream()
+    check = {}
+    walk_steps = 0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i, q in enumerate(queries):
+        S.simrank_single_source_async(Gs[q.graph], q, wss[q.graph], outs[q.graph], cnts[q.graph],
+                                      stream)
+        if i % 64 == 0:     # keep a few results to compare with the batch
+            stream.synchronize()
+            check[i] = cnts[q.graph].cpu().numpy().view(np.uint32).copy()
+    stream.synchronize()
+    t_plain = time.perf_counter() - t1
+    # (b) the batch
+    plan = S.BatchPlan(Gs, queries)
+    plan.run(stream)
+    plan.wait()                                             # warm-up run
+    t2 = time.perf_counter()
+    plan.run(stream)
+    st = plan.wait()
+    t_batch = time.perf_counter() - t2
+    same = all(np.array_equal(plan.read(i, want_out=False)[1], c) for i, c in check.items())
+    walk_steps = st.moves + st.tail_steps + st.source_moves
+    nq = len(queries)
+    result = {
+        "metric": METRIC,
+        "value": walk_steps / t_batch,
+        "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": 1e3 * t_batch,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batching: {nq} single-source queries over 16 R-MAT graphs "
+                               "(n = 2^U(12,22), avg degree U{8..32}), eps in {.05,.02,.01}, "
+                               "delta=1e-3, L=64; one captured batch",
+                   "graphs": [{"n": g.n, "m": g.m} for g in gs], "queries": nq},
+        "queries_per_s": nq / t_batch,
+        "plain_queries_per_s": nq / t_plain,
+        "batched_vs_plain": t_plain / t_batch,
+        "batch_results_equal_plain": same,
+        "tuned_unit_nodes": tuned,
+        "batch": {"moves": st.moves, "draws": st.draws, "device_ms": st.ms, "pairs": st.pairs},
+    }
+    print(json.dumps(result))
+    plan.free()
+    for ws in wss:
+        ws.free()
+    for G in Gs:
+        G.free()
 
 
 if __name__ == "__main__":

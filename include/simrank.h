@@ -201,13 +201,39 @@ int simrank_index_read(const simrank_graph *g, const int64_t *sigma, int64_t cou
 
 /* ----------------------------------------------------------------- batch */
 
-/* Runs nq queries over ngraphs graphs (qs[i].graph selects the graph) in one
- * persistent launch per phase.  outs[i]: host double[n of its graph] or NULL;
- * counts_opt[i] (may be NULL, or entries NULL): host uint32[n].  Each query's
- * result equals what simrank_single_source_ex returns for it alone. */
+/* Runs nq queries over ngraphs graphs (qs[i].graph selects the graph; all
+ * graphs on one device).  Consecutive queries are grouped into plans that fit
+ * half of the free device memory (admission by memory); each plan is one
+ * captured launch sequence (below).  outs[i]: host double[n of its graph] or
+ * NULL; counts_opt (may be NULL, or entries NULL): host uint32[n].  Each
+ * query's result equals what simrank_single_source_ex returns for it alone.
+ * st_opt: totals over all queries; ms is device time. */
 int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs, const simrank_query *qs,
                   int32_t nq, double *const *outs, uint32_t *const *counts_opt,
                   simrank_stats *st_opt);
+
+/* A batch plan owns the device buffers of nq queries and a hipGraph of their
+ * whole launch sequence: source walks of every query, compaction, one
+ * persistent meet launch whose work units span all queries, estimates.  It can
+ * be run any number of times.  ENOMEM if its buffers exceed free memory. */
+typedef struct simrank_batch_plan simrank_batch_plan;
+int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
+                              const simrank_query *qs, int32_t nq, simrank_batch_plan **plan_out);
+/* Enqueues the plan's graph on `stream` (hipStream_t; NULL = default stream). */
+int simrank_batch_plan_run(simrank_batch_plan *plan, void *stream);
+/* Waits for the last run; st (may be NULL) receives totals and its device time. */
+int simrank_batch_plan_wait(simrank_batch_plan *plan, simrank_stats *st);
+/* Copies query i's estimate (host double[n], may be NULL) and counts (host
+ * uint32[n], may be NULL) after the last run. */
+int simrank_batch_plan_read(simrank_batch_plan *plan, int32_t i, double *out_host,
+                            uint32_t *counts_host);
+int simrank_batch_plan_free(simrank_batch_plan *plan);
+
+/* Measures the meet kernel of query q on g for each work-unit size (nodes per
+ * unit 32, 64, 128, 256) and keeps the fastest for later queries on g
+ * (*vb_out, may be NULL).  Results never depend on the choice.  Not to be
+ * called while other threads query g. */
+int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out);
 
 /* ---------------------------------------------------------------- errors */
 

@@ -1,23 +1,75 @@
-// Batched single-source queries over several graphs.
+// Batched single-source queries over several graphs, and the unit-size tuner.
 //
-// Each query's result is exactly the one simrank_single_source_ex returns for
-// it alone: results depend only on (graph, query).
+// A plan holds the device buffers of a set of queries (carved from one
+// allocation) and a hipGraph of the whole launch sequence: init, source walks
+// of every query, compaction, work-unit offsets, one persistent meet launch
+// whose work units span all queries (per kind: plain, stitched), estimate.
+// Queries on graphs of very different sizes share the launch and its tail.
+// Each query's result is exactly the one a lone simrank_single_source_ex call
+// returns: results depend only on (graph, query).
 #include <algorithm>
 #include <vector>
 
 #include "common.hpp"
 
+namespace srk {
+namespace {
+
+constexpr size_t ARENA_ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1); }
+
+// Device bytes one query needs in a plan.
+size_t query_bytes(const simrank_params &p, int32_t n) {
+    const size_t RL = (size_t)p.R * (size_t)p.L;
+    return align_up(4 * RL) + align_up((size_t)p.R) + align_up(4 * (size_t)p.R) +
+           align_up(4 * ((size_t)p.R + 1)) + align_up(4 * RL) +
+           align_up(4 * ((size_t)max_tiles_for(p.R, p.L) + 1)) + align_up(32) +
+           align_up(4 * (size_t)n) + align_up(8 * (size_t)n);
+}
+
+}  // namespace
+}  // namespace srk
+
 using namespace srk;
 
-extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
-                             const simrank_query *qs, int32_t nq, double *const *outs,
-                             uint32_t *const *counts_opt, simrank_stats *st_opt) {
-    clear_error();
+struct simrank_batch_plan {
+    int device = 0;
+    int32_t nq = 0;
+    std::vector<QueryDesc> desc;       // host copies (buffer addresses)
+    std::vector<simrank_params> params;
+    std::vector<const Graph *> graphs;
+    char *arena = nullptr;
+    QueryDesc *desc_dev = nullptr;
+    uint32_t *units = nullptr;
+    unsigned long long *counters = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool ran = false;
+    int64_t bytes = 0;
+};
+
+static void plan_release(simrank_batch_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    device_free(p->arena);
+    device_free(p->desc_dev);
+    device_free(p->units);
+    device_free(p->counters);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    delete p;
+}
+
+static int check_queries(simrank_graph *const *graphs, int32_t ngraphs, const simrank_query *qs,
+                         int32_t nq, std::vector<simrank_params> &ps, std::vector<int> &modes) {
     if (ngraphs < 0 || nq < 0) return fail(SIMRANK_EINVAL, "negative count");
     if (nq > 0 && (!graphs || !qs)) return fail(SIMRANK_EINVAL, "NULL argument");
-    std::vector<simrank_params> ps(nq);
-    std::vector<int> modes(nq);
-    int32_t maxR = 1, maxL = 1;
+    ps.resize(nq);
+    modes.resize(nq);
     for (int32_t i = 0; i < nq; ++i) {
         const simrank_query &q = qs[i];
         if (q.graph < 0 || q.graph >= ngraphs || !graphs[q.graph])
@@ -29,60 +81,276 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
             return fail(SIMRANK_EINVAL, "query " + std::to_string(i) + ": source out of range");
         if (modes[i] == SIMRANK_MODE_STITCHED && (!g->index || g->index->T != ps[i].T))
             return fail(SIMRANK_ESTATE, "query " + std::to_string(i) + ": no matching index");
-        maxR = std::max(maxR, ps[i].R);
-        maxL = std::max(maxL, ps[i].L);
+        if (g->device != graphs[qs[0].graph]->device)
+            return fail(SIMRANK_EINVAL, "all graphs of a batch must live on one device");
+        const int64_t ub = (int64_t)max_tiles_for(ps[i].R, ps[i].L) *
+                           ((g->n_active + default_unit_nodes(g) - 1) / default_unit_nodes(g));
+        if (ub >= (int64_t)0x7fffffff)
+            return fail(SIMRANK_EINVAL, "query " + std::to_string(i) + ": too many work units");
     }
-    if (nq == 0) {
-        if (st_opt) *st_opt = simrank_stats{};
-        return SIMRANK_OK;
-    }
-    const int device = graphs[qs[0].graph]->device;
-    SRK_HIP(hipSetDevice(device));
-    int32_t maxN = 1;
-    for (int32_t i = 0; i < nq; ++i) maxN = std::max(maxN, graphs[qs[i].graph]->n);
-    Workspace ws;
-    double *out_dev = nullptr;
-    uint32_t *cnt_dev = nullptr;
-    hipStream_t st = nullptr;
-    int rc = workspace_init(graphs[qs[0].graph], maxR, maxL, &ws);
-    if (!rc) rc = device_alloc((void **)&out_dev, 8 * (size_t)maxN, nullptr);
-    if (!rc) rc = device_alloc((void **)&cnt_dev, 4 * (size_t)maxN, nullptr);
-    if (!rc) {
-        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
-    }
-    simrank_stats tot{};
-    for (int32_t i = 0; i < nq && !rc; ++i) {
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
+                                         const simrank_query *qs, int32_t nq,
+                                         simrank_batch_plan **plan_out) {
+    clear_error();
+    if (!plan_out) return fail(SIMRANK_EINVAL, "plan is NULL");
+    *plan_out = nullptr;
+    if (nq < 1) return fail(SIMRANK_EINVAL, "a plan needs at least one query");
+    std::vector<simrank_params> ps;
+    std::vector<int> modes;
+    int rc = check_queries(graphs, ngraphs, qs, nq, ps, modes);
+    if (rc) return rc;
+    simrank_batch_plan *p = new simrank_batch_plan();
+    p->device = graphs[qs[0].graph]->device;
+    p->nq = nq;
+    p->params = ps;
+    auto bail = [&](int code) {
+        plan_release(p);
+        return code;
+    };
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+    size_t total = 0;
+    for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], graphs[qs[i].graph]->n);
+    size_t free_b = 0, tot_b = 0;
+    if (hipMemGetInfo(&free_b, &tot_b) == hipSuccess && total > free_b)
+        return bail(fail(SIMRANK_ENOMEM, "batch needs " + std::to_string(total) +
+                                             " device bytes, " + std::to_string(free_b) + " free"));
+    if ((rc = device_alloc((void **)&p->arena, total, &p->bytes))) return bail(rc);
+    if ((rc = device_alloc((void **)&p->desc_dev, sizeof(QueryDesc) * nq, &p->bytes))) return bail(rc);
+    if ((rc = device_alloc((void **)&p->units, 4 * (2 * ((size_t)nq + 1) + 2), &p->bytes)))
+        return bail(rc);
+    if ((rc = device_alloc((void **)&p->counters, 8 * 8, &p->bytes))) return bail(rc);
+    QuerySet set;
+    set.nq = nq;
+    char *cur = p->arena;
+    auto take = [&](size_t b) {
+        char *r = cur;
+        cur += align_up(b);
+        return r;
+    };
+    p->desc.resize(nq);
+    p->graphs.resize(nq);
+    for (int32_t i = 0; i < nq; ++i) {
         const simrank_graph *g = graphs[qs[i].graph];
-        rc = enqueue_query(g, &qs[i], ps[i], modes[i], &ws, out_dev, cnt_dev, st);
-        if (!rc) {
-            hipError_t e = hipEventSynchronize(ws.ev1);
-            unsigned long long c[8];
-            if (e == hipSuccess) e = hipMemcpy(c, ws.counters, sizeof(c), hipMemcpyDeviceToHost);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ws.ev0, ws.ev1);
-            if (e == hipSuccess && outs && outs[i])
-                e = hipMemcpy(outs[i], out_dev, 8 * (size_t)g->n, hipMemcpyDeviceToHost);
-            if (e == hipSuccess && counts_opt && counts_opt[i])
-                e = hipMemcpy(counts_opt[i], cnt_dev, 4 * (size_t)g->n, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) {
-                rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
-                break;
-            }
-            tot.pairs += (uint64_t)(g->n - 1) * (uint64_t)ps[i].R;
-            tot.pairs_walked += c[C_PAIRS];
-            tot.moves += c[C_MOVES];
-            tot.draws += c[C_DRAWS];
-            tot.meets += c[C_MEETS];
-            tot.tail_steps += c[C_TAIL];
-            tot.source_moves += c[C_SRC_MOVES];
-            tot.ms += ms;
+        const simrank_params &pp = ps[i];
+        QueryDesc &d = p->desc[i];
+        describe_query(g, &qs[i], pp, modes[i], default_unit_nodes(g), &d);
+        const size_t RL = (size_t)pp.R * (size_t)pp.L;
+        d.sw = (uint32_t *)take(4 * RL);
+        d.slen = (uint8_t *)take((size_t)pp.R);
+        d.jj = (uint32_t *)take(4 * (size_t)pp.R);
+        d.joff = (uint32_t *)take(4 * ((size_t)pp.R + 1));
+        d.swc = (uint32_t *)take(4 * RL);
+        d.tiles = (uint32_t *)take(4 * ((size_t)max_tiles_for(pp.R, pp.L) + 1));
+        d.meta = (uint32_t *)take(32);
+        d.cnt = (uint32_t *)take(4 * (size_t)g->n);
+        d.out = (double *)take(8 * (size_t)g->n);
+        p->graphs[i] = g;
+        set.max_R = std::max(set.max_R, pp.R);
+        set.max_n = std::max(set.max_n, g->n);
+        const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
+        if (d.stitched) {
+            set.any_stitched = true;
+            set.units_bound_stitched += ub;
+        } else {
+            set.any_plain = true;
+            set.units_bound_plain += ub;
         }
     }
-    if (st) (void)hipStreamDestroy(st);
-    device_free(out_dev);
-    device_free(cnt_dev);
-    workspace_release(&ws);
+    e = hipMemcpy(p->desc_dev, p->desc.data(), sizeof(QueryDesc) * nq, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+    set.desc = p->desc_dev;
+    set.units = p->units;
+    set.counters = p->counters;
+    // capture the launch sequence into a graph
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = launch_query_set(set, cs, nullptr, nullptr);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &gr);
+        p->graph = gr;
+        if (!rc && e2 != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e2));
+        if (!rc) {
+            e2 = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            if (e2 != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e2));
+        }
+    } else {
+        rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) return bail(rc);
+    e = hipEventCreate(&p->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev1);
+    if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+    *plan_out = p;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_run(simrank_batch_plan *p, void *stream) {
+    clear_error();
+    if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
+    SRK_HIP(hipSetDevice(p->device));
+    hipStream_t st = (hipStream_t)stream;
+    SRK_HIP(hipEventRecord(p->ev0, st));
+    SRK_HIP(hipGraphLaunch(p->exec, st));
+    SRK_HIP(hipEventRecord(p->ev1, st));
+    p->last_stream = st;
+    p->ran = true;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_wait(simrank_batch_plan *p, simrank_stats *st) {
+    clear_error();
+    if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
+    if (!p->ran) return fail(SIMRANK_ESTATE, "plan has not run");
+    SRK_HIP(hipEventSynchronize(p->ev1));
+    if (st) {
+        unsigned long long c[8];
+        SRK_HIP(hipMemcpy(c, p->counters, sizeof(c), hipMemcpyDeviceToHost));
+        float ms = 0.f;
+        SRK_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+        *st = simrank_stats{};
+        for (int32_t i = 0; i < p->nq; ++i)
+            st->pairs += (uint64_t)(p->graphs[i]->n - 1) * (uint64_t)p->params[i].R;
+        st->pairs_walked = c[C_PAIRS];
+        st->moves = c[C_MOVES];
+        st->draws = c[C_DRAWS];
+        st->meets = c[C_MEETS];
+        st->tail_steps = c[C_TAIL];
+        st->source_moves = c[C_SRC_MOVES];
+        st->ms = ms;
+        st->meet_ms = ms;
+    }
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_read(simrank_batch_plan *p, int32_t i, double *out_host,
+                                       uint32_t *counts_host) {
+    clear_error();
+    if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
+    if (i < 0 || i >= p->nq) return fail(SIMRANK_EINVAL, "query index out of range");
+    if (!p->ran) return fail(SIMRANK_ESTATE, "plan has not run");
+    SRK_HIP(hipSetDevice(p->device));
+    SRK_HIP(hipEventSynchronize(p->ev1));
+    const size_t n = (size_t)p->graphs[i]->n;
+    if (out_host) SRK_HIP(hipMemcpy(out_host, p->desc[i].out, 8 * n, hipMemcpyDeviceToHost));
+    if (counts_host) SRK_HIP(hipMemcpy(counts_host, p->desc[i].cnt, 4 * n, hipMemcpyDeviceToHost));
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_free(simrank_batch_plan *p) {
+    clear_error();
+    if (!p) return SIMRANK_OK;
+    (void)hipSetDevice(p->device);
+    if (p->ran) (void)hipEventSynchronize(p->ev1);
+    plan_release(p);
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
+                             const simrank_query *qs, int32_t nq, double *const *outs,
+                             uint32_t *const *counts_opt, simrank_stats *st_opt) {
+    clear_error();
+    std::vector<simrank_params> ps;
+    std::vector<int> modes;
+    int rc = check_queries(graphs, ngraphs, qs, nq, ps, modes);
+    if (rc) return rc;
+    simrank_stats tot{};
+    if (nq == 0) {
+        if (st_opt) *st_opt = tot;
+        return SIMRANK_OK;
+    }
+    SRK_HIP(hipSetDevice(graphs[qs[0].graph]->device));
+    // Admission by device memory: consecutive queries are grouped into plans
+    // that fit half of the free memory at the time each plan is made.
+    int32_t i0 = 0;
+    while (i0 < nq && !rc) {
+        size_t free_b = 0, tot_b = 0;
+        SRK_HIP(hipMemGetInfo(&free_b, &tot_b));
+        const size_t budget = free_b / 2;
+        size_t used = 0;
+        int32_t i1 = i0;
+        while (i1 < nq) {
+            const size_t b = query_bytes(ps[i1], graphs[qs[i1].graph]->n) + sizeof(QueryDesc) + 64;
+            if (i1 > i0 && used + b > budget) break;
+            used += b;
+            ++i1;
+        }
+        simrank_batch_plan *p = nullptr;
+        rc = simrank_batch_plan_create(graphs, ngraphs, qs + i0, i1 - i0, &p);
+        if (rc) break;
+        hipStream_t st = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+        simrank_stats s1{};
+        if (!rc) rc = simrank_batch_plan_run(p, st);
+        if (!rc) rc = simrank_batch_plan_wait(p, &s1);
+        for (int32_t i = i0; i < i1 && !rc; ++i)
+            rc = simrank_batch_plan_read(p, i - i0, outs ? outs[i] : nullptr,
+                                         counts_opt ? counts_opt[i] : nullptr);
+        if (st) (void)hipStreamDestroy(st);
+        simrank_batch_plan_free(p);
+        tot.pairs += s1.pairs;
+        tot.pairs_walked += s1.pairs_walked;
+        tot.moves += s1.moves;
+        tot.draws += s1.draws;
+        tot.meets += s1.meets;
+        tot.tail_steps += s1.tail_steps;
+        tot.source_moves += s1.source_moves;
+        tot.ms += s1.ms;
+        tot.meet_ms += s1.meet_ms;
+        i0 = i1;
+    }
     if (!rc && st_opt) *st_opt = tot;
+    return rc;
+}
+
+// ------------------------------------------------------------------ tuner
+
+extern "C" int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out) {
+    clear_error();
+    if (!g || !q) return fail(SIMRANK_EINVAL, "NULL argument");
+    simrank_params p;
+    int mode;
+    int rc = query_params(q, g->n, &p, &mode);
+    if (rc) return rc;
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    SRK_HIP(hipSetDevice(g->device));
+    Workspace ws;
+    uint32_t *cnt = nullptr;
+    rc = workspace_init(g, p.R, p.L, &ws);
+    if (!rc) rc = device_alloc((void **)&cnt, 4 * (size_t)g->n, nullptr);
+    const int32_t saved = g->tuned_vb;
+    int32_t best = 0;
+    float best_ms = 0.f;
+    for (int32_t vb = 32; vb <= MEET_VB && !rc; vb *= 2) {
+        if (vb > 32 && (g->n_active + vb - 1) / vb < 64) break;   // too few units to fill a GPU
+        g->tuned_vb = vb;
+        float ms_sum = 0.f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            rc = enqueue_query(g, q, p, mode, &ws, nullptr, cnt, g->stream);
+            if (!rc) {
+                hipError_t e = hipEventSynchronize(ws.ev1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ws.evm0, ws.evm1);
+                if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+                if (rep == 1) ms_sum += ms;   // the first run warms the caches
+            }
+        }
+        if (!rc && (best == 0 || ms_sum < best_ms)) {
+            best = vb;
+            best_ms = ms_sum;
+        }
+    }
+    g->tuned_vb = rc ? saved : best;
+    device_free(cnt);
+    workspace_release(&ws);
+    if (!rc && vb_out) *vb_out = best;
     return rc;
 }

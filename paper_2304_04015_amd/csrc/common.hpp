@@ -33,7 +33,7 @@ constexpr int64_t MAX_R = 1 << 24;
 constexpr int TILE_J = 1024;            // source walks per tile, at most
 constexpr int TILE_NODES = 4096;        // LDS node slots per tile
 constexpr int MEET_BLOCK = 512;         // threads per block of the meet kernel
-constexpr int MEET_VB = 256;            // nodes v per work unit
+constexpr int MEET_VB = 256;            // nodes v per work unit, at most
 
 // ------------------------------------------------------------ device graph
 // Gather layout of the reversed graph.  Every node v owns the edge slots
@@ -56,6 +56,7 @@ struct Graph {
     int32_t *active = nullptr;    // [n_active] nodes with deg >= 1, ascending
     hipStream_t stream = nullptr; // stream of the synchronous calls
     Index *index = nullptr;
+    int32_t tuned_vb = 0;         // nodes per meet work unit chosen by simrank_tune (0: default)
     int64_t bytes = 0;
 };
 
@@ -80,6 +81,50 @@ struct Index {
     uint64_t build_moves = 0;
 };
 
+// Read-only view of a graph's stitched index, as the kernels see it.
+struct IndexView {
+    const uint32_t *node_of;
+    const int64_t *pool_off;
+    const uint32_t *seg;
+    const uint8_t *seg_lens;
+    const uint32_t *chain;
+    int32_t seg_len, width;
+};
+
+// One query as the device kernels see it (one entry per query of a launch).
+struct QueryDesc {
+    const uint2 *nodes;
+    const uint2 *E;
+    const int32_t *active;
+    IndexView ix;
+    uint32_t *sw;          // [R][L] source walk positions 1..L (o values)
+    uint8_t *slen;         // [R]
+    uint32_t *jj;          // [R] walk index of compact entry k
+    uint32_t *joff;        // [R + 1] start of entry k in swc
+    uint32_t *swc;         // [R * L] packed positions
+    uint32_t *tiles;       // [max tiles + 1]
+    uint32_t *meta;        // [8]: R1, packed positions, tiles
+    uint32_t *cnt;         // [n] meet counts (caller's)
+    double *out;           // [n] estimate or NULL
+    uint32_t k0, k1;       // Philox key of the query's walks
+    uint32_t T;            // continue threshold
+    int32_t n, n_active, s, R, L;
+    int32_t vb;            // nodes per work unit (<= MEET_VB)
+    int32_t n_chunks;      // ceil(n_active / vb)
+    int32_t stitched;
+};
+
+// A set of queries whose descriptors are already in device memory.
+struct QuerySet {
+    const QueryDesc *desc;        // device [nq]
+    int32_t nq = 0;
+    int32_t max_R = 0, max_n = 0;
+    bool any_plain = false, any_stitched = false;
+    int64_t units_bound_plain = 0, units_bound_stitched = 0;
+    uint32_t *units = nullptr;    // device [2 (nq + 1) + 2]: unit offsets (plain, stitched), cursors
+    unsigned long long *counters = nullptr;  // device [8]
+};
+
 // Per-query scratch.
 struct Workspace {
     const Graph *g = nullptr;
@@ -90,8 +135,10 @@ struct Workspace {
     uint32_t *joff = nullptr;      // [max_R + 1] start of entry k in swc
     uint32_t *swc = nullptr;       // [max_R * max_L] compact positions
     uint32_t *tiles = nullptr;     // [max tiles + 1] first compact entry of each tile
-    uint32_t *meta = nullptr;      // [8]: R1, total nodes, n_tiles, unit cursor, ...
+    uint32_t *meta = nullptr;      // [8]: R1, total nodes, n_tiles, ...
     unsigned long long *counters = nullptr;  // [8] stats
+    QueryDesc *desc = nullptr;     // device [1]
+    uint32_t *units = nullptr;     // device [6]
     int32_t max_tiles = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;     // around the whole query
     hipEvent_t evm0 = nullptr, evm1 = nullptr;   // around the meet kernel
@@ -122,6 +169,16 @@ int scan_inclusive_max_u32(uint32_t *data, int64_t n, hipStream_t st);
 
 // Queries (query.hip).
 int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mode);
+int32_t max_tiles_for(int32_t R, int32_t L);
+int32_t default_unit_nodes(const Graph *g);
+IndexView index_view(const Graph *g);
+// Fills everything but the buffers (sw .. out) of a descriptor.
+void describe_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                    int32_t vb, QueryDesc *d);
+// Enqueues init, source walks, compaction, unit offsets, meet and estimate for
+// every query of the set; records ev_meet0 / ev_meet1 (may be NULL) around the
+// meet kernels.
+int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hipEvent_t ev_meet1);
 int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
                   Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st);
 int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws);

@@ -20,37 +20,9 @@
 namespace srk {
 namespace {
 
-// ------------------------------------------------------------ small kernels
+// ------------------------------------------------------------ helpers
 
-__global__ void k_query_init(uint32_t *__restrict__ cnt, int32_t n, uint32_t *__restrict__ meta,
-                             unsigned long long *__restrict__ counters) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 8) {
-        meta[i] = 0u;
-        counters[i] = 0ull;
-    }
-    for (int64_t v = i; v < n; v += (int64_t)gridDim.x * blockDim.x) cnt[v] = 0u;
-}
-
-// s_hat(s, v) = cnt[v] / R; the pair (s, s) meets at step 0 for every j.
-__global__ void k_estimate(uint32_t *__restrict__ cnt, double *__restrict__ out, int32_t n,
-                           int32_t R, int32_t s) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    if (v == s) cnt[v] = (uint32_t)R;
-    if (out) out[v] = (v == s) ? 1.0 : (double)cnt[v] / (double)R;
-}
-
-// --------------------------------------------------------- stitched tails
-
-struct IndexView {
-    const uint32_t *node_of;
-    const int64_t *pool_off;
-    const uint32_t *seg;
-    const uint8_t *seg_lens;
-    const uint32_t *chain;
-    int32_t seg_len, width;
-};
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Slot entered by walk (v, j) whose private head ended at node y
 // (counter (v, j, 0, 2)).
@@ -61,76 +33,6 @@ __device__ __forceinline__ uint32_t entry_slot(const IndexView &ix, PhiloxKey ke
     const uint4 x = philox4x32_10(v, j, 0u, DOM_ENTRY, key);
     return (uint32_t)(b + (int64_t)pick64(x.x, (uint64_t)P));
 }
-
-// ------------------------------------------------------------ source walks
-
-struct SrcArgs {
-    const uint2 *nodes;
-    const uint2 *E;
-    IndexView ix;
-    uint32_t *sw;        // [R][L]
-    uint8_t *slen;       // [R]
-    unsigned long long *counters;
-    PhiloxKey key;
-    uint32_t T;
-    int32_t R, L, s;
-};
-
-// Walk (s, j) for j < R: positions 1..len as o() values.
-template <bool STITCHED>
-__global__ __launch_bounds__(256) void k_source_walks(SrcArgs a) {
-    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t moves = 0, tail = 0;
-    if (j < a.R) {
-        uint32_t *row = a.sw + (size_t)j * a.L;
-        uint2 cur = a.nodes[a.s];
-        const int32_t head = STITCHED ? min(a.ix.seg_len, a.L) : a.L;
-        int32_t len = 0;
-        for (int32_t t = 1; t <= head; ++t) {
-            const uint4 x = philox4x32_10((uint32_t)a.s, (uint32_t)j, (uint32_t)t, DOM_WALK, a.key);
-            if (x.x >= a.T || cur.y == 0) break;
-            cur = a.E[cur.x + pick32(x.y, cur.y)];
-            row[t - 1] = cur.x;
-            len = t;
-        }
-        moves = (uint32_t)len;
-        if (STITCHED && len == a.ix.seg_len && len < a.L) {
-            const uint32_t y = a.ix.node_of[cur.x];
-            const uint32_t sigma = entry_slot(a.ix, a.key, (uint32_t)a.s, (uint32_t)j, y);
-            for (int32_t mm = 0; mm < a.ix.width && len < a.L; ++mm) {
-                const uint32_t sg = a.ix.chain[(size_t)sigma * a.ix.width + mm];
-                if (sg == NIL) break;
-                const int32_t sl = a.ix.seg_lens[sg];
-                for (int32_t u = 0; u < sl && len < a.L; ++u) {
-                    row[len] = a.ix.seg[(size_t)sg * a.ix.seg_len + u];
-                    ++len;
-                    ++tail;
-                }
-                if (sl < a.ix.seg_len) break;
-            }
-        }
-        a.slen[j] = (uint8_t)len;
-    }
-    // wave totals
-    unsigned long long m64 = moves, t64 = tail;
-    for (int d = 32; d > 0; d >>= 1) {
-        m64 += __shfl_xor(m64, d, 64);
-        t64 += __shfl_xor(t64, d, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (m64) atomicAdd(&a.counters[C_SRC_MOVES], m64);
-        if (t64) atomicAdd(&a.counters[C_SRC_MOVES], t64);
-    }
-}
-
-// ------------------------------------------------------------ compaction
-// One block.  Keeps the walks with at least one step (a walk of length 0 can
-// only meet at step 0, i.e. only the source itself), packs their positions
-// back to back (swc), and cuts the packed list into tiles that fit the meet
-// kernel's LDS: a tile boundary falls wherever the entry index crosses a
-// multiple of TILE_J or the packed offset crosses a multiple of NW =
-// TILE_NODES - L, so a tile holds at most TILE_J walks and at most
-// NW - 1 + L <= TILE_NODES positions.
 
 template <typename T>
 __device__ T block_excl_sum(T x, T *total) {
@@ -153,18 +55,91 @@ __device__ T block_excl_sum(T x, T *total) {
     return before + inc - x;
 }
 
-__global__ __launch_bounds__(1024) void k_compact(const uint8_t *__restrict__ slen,
-                                                  const uint32_t *__restrict__ sw, int32_t R,
-                                                  int32_t L, uint32_t *__restrict__ jj,
-                                                  uint32_t *__restrict__ joff,
-                                                  uint32_t *__restrict__ swc,
-                                                  uint32_t *__restrict__ tiles,
-                                                  uint32_t *__restrict__ meta, uint32_t NW) {
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_set_desc(QueryDesc *dst, QueryDesc d) { *dst = d; }
+
+// grid (x over nodes, y = query)
+__global__ void k_init(const QueryDesc *__restrict__ qd, unsigned long long *__restrict__ counters) {
+    const QueryDesc &d = qd[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+        d.meta[threadIdx.x] = 0u;
+        if (blockIdx.y == 0) counters[threadIdx.x] = 0ull;
+    }
+    for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.cnt[v] = 0u;
+}
+
+// s_hat(s, v) = cnt[v] / R; the pair (s, s) meets at step 0 for every j.
+// grid (x over nodes, y = query)
+__global__ void k_estimate(const QueryDesc *__restrict__ qd) {
+    const QueryDesc &d = qd[blockIdx.y];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (v == d.s) d.cnt[v] = (uint32_t)d.R;
+        if (d.out) d.out[v] = (v == d.s) ? 1.0 : (double)d.cnt[v] / (double)d.R;
+    }
+}
+
+// ------------------------------------------------------------ source walks
+// Walk (s, j) for j < R: positions 1..len as o() values.  grid (x over j, y = query)
+__global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restrict__ qd,
+                                                      unsigned long long *__restrict__ counters) {
+    const QueryDesc &d = qd[blockIdx.y];
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t steps = 0;
+    if (j < d.R) {
+        const PhiloxKey key{d.k0, d.k1};
+        uint32_t *row = d.sw + (size_t)j * d.L;
+        uint2 cur = d.nodes[d.s];
+        const int32_t head = d.stitched ? min(d.ix.seg_len, d.L) : d.L;
+        int32_t len = 0;
+        for (int32_t t = 1; t <= head; ++t) {
+            const uint4 x = philox4x32_10((uint32_t)d.s, (uint32_t)j, (uint32_t)t, DOM_WALK, key);
+            if (x.x >= d.T || cur.y == 0) break;
+            cur = d.E[cur.x + pick32(x.y, cur.y)];
+            row[t - 1] = cur.x;
+            len = t;
+        }
+        if (d.stitched && len == d.ix.seg_len && len < d.L) {
+            const uint32_t y = d.ix.node_of[cur.x];
+            const uint32_t sigma = entry_slot(d.ix, key, (uint32_t)d.s, (uint32_t)j, y);
+            for (int32_t mm = 0; mm < d.ix.width && len < d.L; ++mm) {
+                const uint32_t sg = d.ix.chain[(size_t)sigma * d.ix.width + mm];
+                if (sg == NIL) break;
+                const int32_t sl = d.ix.seg_lens[sg];
+                for (int32_t u = 0; u < sl && len < d.L; ++u) {
+                    row[len] = d.ix.seg[(size_t)sg * d.ix.seg_len + u];
+                    ++len;
+                }
+                if (sl < d.ix.seg_len) break;
+            }
+        }
+        d.slen[j] = (uint8_t)len;
+        steps = (uint32_t)len;
+    }
+    unsigned long long m64 = steps;
+    for (int dd = 32; dd > 0; dd >>= 1) m64 += __shfl_xor(m64, dd, 64);
+    if ((threadIdx.x & 63) == 0 && m64) atomicAdd(&counters[C_SRC_MOVES], m64);
+}
+
+// ------------------------------------------------------------ compaction
+// One block per query.  Keeps the walks with at least one step (a walk of
+// length 0 can only meet at step 0, i.e. only the source itself), packs their
+// positions back to back (swc), and cuts the packed list into tiles that fit
+// the meet kernel's LDS: a tile boundary falls wherever the entry index crosses
+// a multiple of TILE_J or the packed offset crosses a multiple of
+// NW = TILE_NODES - L, so a tile holds at most TILE_J walks and at most
+// NW - 1 + L <= TILE_NODES positions.
+__global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ qd) {
+    const QueryDesc &d = qd[blockIdx.x];
+    const int32_t R = d.R, L = d.L;
+    const uint32_t NW = (uint32_t)(TILE_NODES - L);
     const int32_t per = (R + blockDim.x - 1) / blockDim.x;
     const int32_t j0 = min(R, (int32_t)threadIdx.x * per), j1 = min(R, j0 + per);
     uint32_t cnt = 0, nodes = 0;
     for (int32_t j = j0; j < j1; ++j) {
-        const uint32_t l = slen[j];
+        const uint32_t l = d.slen[j];
         cnt += l > 0;
         nodes += l;
     }
@@ -173,40 +148,66 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t *__restrict__ sl
     const uint32_t nb = block_excl_sum(nodes, &total);
     uint32_t k = kb, off = nb;
     for (int32_t j = j0; j < j1; ++j) {
-        const uint32_t l = slen[j];
+        const uint32_t l = d.slen[j];
         if (!l) continue;
-        jj[k] = (uint32_t)j;
-        joff[k] = off;
-        const uint32_t *src = sw + (size_t)j * L;
-        for (uint32_t t = 0; t < l; ++t) swc[off + t] = src[t];
+        d.jj[k] = (uint32_t)j;
+        d.joff[k] = off;
+        const uint32_t *src = d.sw + (size_t)j * L;
+        for (uint32_t t = 0; t < l; ++t) d.swc[off + t] = src[t];
         ++k;
         off += l;
     }
-    if (threadIdx.x == 0) joff[R1] = total;
+    if (threadIdx.x == 0) d.joff[R1] = total;
     __syncthreads();
-    // tile boundaries over this thread's entries [kb, kb + cnt)
     uint32_t nbound = 0;
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        nbound += (e == 0) || (e % TILE_J == 0) || (joff[e] / NW != joff[e - 1] / NW);
+        nbound += (e == 0) || (e % TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
     uint32_t n_tiles;
     uint32_t tb = block_excl_sum(nbound, &n_tiles);
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        if ((e == 0) || (e % TILE_J == 0) || (joff[e] / NW != joff[e - 1] / NW)) tiles[tb++] = e;
+        if ((e == 0) || (e % TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
+            d.tiles[tb++] = e;
     if (threadIdx.x == 0) {
-        tiles[n_tiles] = R1;
-        meta[0] = R1;
-        meta[1] = total;
-        meta[2] = n_tiles;
-        meta[3] = 0u;   // work-unit cursor of the meet kernel
+        d.tiles[n_tiles] = R1;
+        d.meta[0] = R1;
+        d.meta[1] = total;
+        d.meta[2] = n_tiles;
+    }
+}
+
+// Work-unit offsets of the queries (one block): units[0 .. nq] for plain
+// queries, units[nq+1 .. 2nq+1] for stitched ones (a query of the other kind
+// has no units in a list), then the two unit cursors.
+__global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restrict__ qd, int32_t nq,
+                                                       uint32_t *__restrict__ units) {
+    const int32_t per = (nq + blockDim.x - 1) / blockDim.x;
+    const int32_t q0 = min(nq, (int32_t)threadIdx.x * per), q1 = min(nq, q0 + per);
+    for (int list = 0; list < 2; ++list) {
+        uint32_t sum = 0;
+        for (int32_t q = q0; q < q1; ++q)
+            if (qd[q].stitched == list) sum += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
+        uint32_t total;
+        uint32_t run = block_excl_sum(sum, &total);
+        uint32_t *u = units + list * (nq + 1);
+        for (int32_t q = q0; q < q1; ++q) {
+            u[q] = run;
+            if (qd[q].stitched == list) run += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
+        }
+        if (threadIdx.x == 0) {
+            u[nq] = total;
+            units[2 * (nq + 1) + list] = 0u;
+        }
     }
 }
 
 // ------------------------------------------------------------ meet kernel
 //
-// Persistent blocks take work units (tile of source walks x chunk of MEET_VB
-// nodes) from a device cursor.  A block stages its tile (walk ids, packed
-// positions) in LDS once and keeps it while consecutive units share the tile,
-// and stages the chunk's nodes (id, row) per unit.
+// Persistent blocks take work units from a device cursor.  A unit is (query,
+// tile of its source walks, chunk of vb of its nodes with in-edges); the units
+// of all queries of a launch form one list, so queries on graphs of any size
+// share the launch and its tail.  A block stages its tile (walk ids, packed
+// positions) in LDS once and keeps it while consecutive units share it, and
+// stages the chunk's nodes (id, row) per unit.
 //
 // Inside a unit the pairs (v, k), v-major, are handed out from one block-wide
 // cursor in chunks of 64 to the waves, so all waves of a block work on the same
@@ -218,25 +219,6 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t *__restrict__ sl
 // A step: one Philox draw, a multiply-high neighbour pick, one 8-byte gather
 // of E, one LDS compare.  Meets go to an LDS counter per node, flushed to the
 // global counts once per unit.
-
-struct MeetArgs {
-    const uint2 *nodes;
-    const uint2 *E;
-    const int32_t *active;
-    const uint32_t *jj;
-    const uint32_t *joff;
-    const uint32_t *swc;
-    const uint32_t *tiles;
-    uint32_t *meta;
-    uint32_t *cnt;
-    unsigned long long *counters;
-    IndexView ix;
-    PhiloxKey key;
-    uint32_t T;
-    int32_t s;
-    int32_t n_active;
-    int32_t n_chunks;
-};
 
 // The walk's gather of an edge slot.  SRK_EDGE_LOAD selects the cache policy
 // (0: default, 1: non-temporal).
@@ -271,7 +253,10 @@ struct Slot {
 constexpr uint32_t ITEM_CHUNK = 64;
 
 template <bool STITCHED, int NS>
-__global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
+__global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
+                                                     const uint32_t *__restrict__ ustart,
+                                                     uint32_t *__restrict__ cursor,
+                                                     unsigned long long *__restrict__ counters) {
     __shared__ uint32_t s_nodes[TILE_NODES];
     __shared__ uint32_t s_j[TILE_J];
     __shared__ uint16_t s_off[TILE_J + 1];
@@ -281,39 +266,53 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
     __shared__ uint32_t s_unit, s_item;
 
     const int lane = threadIdx.x & 63;
-    const uint32_t n_tiles = a.meta[2];
-    const uint32_t n_units = n_tiles * (uint32_t)a.n_chunks;
-    uint32_t cur_tile = 0xffffffffu;
+    const uint32_t n_units = ustart[nq];
+    uint32_t cur_q = 0xffffffffu, cur_tile = 0xffffffffu;
     uint32_t K = 0;
     uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_tail = 0, st_pairs = 0;
 
     for (;;) {
-        if (threadIdx.x == 0) s_unit = atomicAdd(&a.meta[3], 1u);
+        if (threadIdx.x == 0) s_unit = atomicAdd(cursor, 1u);
         __syncthreads();
         const uint32_t unit = s_unit;
         if (unit >= n_units) break;
-        const uint32_t tile = unit / (uint32_t)a.n_chunks;
-        const uint32_t chunk = unit - tile * (uint32_t)a.n_chunks;
-        if (tile != cur_tile) {
-            const uint32_t k0 = a.tiles[tile], k1 = a.tiles[tile + 1];
-            const uint32_t nb = a.joff[k0], ne = a.joff[k1];
+        // query of the unit: the last q with ustart[q] <= unit
+        int32_t lo = 0, hi = nq;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (ustart[mid] <= unit) lo = mid; else hi = mid;
+        }
+        const int32_t q = lo;
+        const QueryDesc &d = qd[q];
+        const int32_t n_chunks = (int32_t)uni((uint32_t)d.n_chunks);
+        const int32_t vb = (int32_t)uni((uint32_t)d.vb);
+        const uint32_t local = unit - ustart[q];
+        const uint32_t tile = local / (uint32_t)n_chunks;
+        const uint32_t chunk = local - tile * (uint32_t)n_chunks;
+        const PhiloxKey key{uni(d.k0), uni(d.k1)};
+        const uint32_t T = uni(d.T);
+        const int32_t src = (int32_t)uni((uint32_t)d.s);
+        if ((uint32_t)q != cur_q || tile != cur_tile) {
+            const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
+            const uint32_t nb = d.joff[k0], ne = d.joff[k1];
             K = k1 - k0;
             for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
-                s_j[i] = a.jj[k0 + i];
-                s_off[i] = (uint16_t)(a.joff[k0 + i] - nb);
+                s_j[i] = d.jj[k0 + i];
+                s_off[i] = (uint16_t)(d.joff[k0 + i] - nb);
             }
             if (threadIdx.x == 0) s_off[K] = (uint16_t)(ne - nb);
-            for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = a.swc[nb + i];
+            for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.swc[nb + i];
+            cur_q = (uint32_t)q;
             cur_tile = tile;
         }
-        const int32_t vbase = (int32_t)chunk * MEET_VB;
-        const uint32_t nv = (uint32_t)min(MEET_VB, a.n_active - vbase);
+        const int32_t vbase = (int32_t)chunk * vb;
+        const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
         for (uint32_t i = threadIdx.x; i < MEET_VB; i += blockDim.x) {
             s_cnt[i] = 0u;
             if (i < nv) {
-                const uint32_t id = (uint32_t)a.active[vbase + (int32_t)i];
+                const uint32_t id = (uint32_t)d.active[vbase + (int32_t)i];
                 s_vid[i] = id;
-                s_vrow[i] = a.nodes[id];
+                s_vrow[i] = d.nodes[id];
             }
         }
         if (threadIdx.x == 0) s_item = 0u;
@@ -327,16 +326,16 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
 
         Slot sl[NS];
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            sl[q].busy = false;
-            sl[q].in_tail = false;
+        for (int qq = 0; qq < NS; ++qq) {
+            sl[qq].busy = false;
+            sl[qq].in_tail = false;
         }
 
         for (;;) {
             // ---- refill idle slots from the block's cursor
 #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                uint64_t need = __ballot(!sl[q].busy);
+            for (int qq = 0; qq < NS; ++qq) {
+                uint64_t need = __ballot(!sl[qq].busy);
                 while (need != 0ull) {
                     if (ci == ce) {
                         if (drained) break;
@@ -364,17 +363,17 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
                             ++vl;
                         }
                         const uint32_t id = s_vid[vl];
-                        if ((int32_t)id != a.s) {   // the source's own pairs are not walked
+                        if ((int32_t)id != src) {   // the source's own pairs are not walked
                             const uint32_t base = s_off[k];
                             const uint32_t len = (uint32_t)s_off[k + 1] - base;
                             const uint2 row = s_vrow[vl];
-                            sl[q].pos = base | (len << 16) | (vl << 24);
-                            sl[q].rng = walk_draws_begin(id, s_j[k], a.key);
-                            sl[q].t = 0;
-                            sl[q].o = row.x;
-                            sl[q].d = row.y;
-                            sl[q].busy = true;
-                            sl[q].in_tail = false;
+                            sl[qq].pos = base | (len << 16) | (vl << 24);
+                            sl[qq].rng = walk_draws_begin(id, s_j[k], key);
+                            sl[qq].t = 0;
+                            sl[qq].o = row.x;
+                            sl[qq].d = row.y;
+                            sl[qq].busy = true;
+                            sl[qq].in_tail = false;
                             ++st_pairs;
                         }
                     }
@@ -389,7 +388,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
             }
             bool any = false;
 #pragma unroll
-            for (int q = 0; q < NS; ++q) any |= sl[q].busy;
+            for (int qq = 0; qq < NS; ++qq) any |= sl[qq].busy;
             // A refill round can hand out only the source's own pairs, which are
             // skipped: a wave leaves only once the block's cursor is drained.
             if (__ballot(any) == 0ull) {
@@ -401,32 +400,32 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
             bool go[NS];
             uint32_t at[NS];
 #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                go[q] = false;
-                at[q] = 0;
-                if (sl[q].busy && !(STITCHED && sl[q].in_tail)) {
-                    ++sl[q].t;
-                    const uint2 x = walk_draw_next(sl[q].rng, a.key);
+            for (int qq = 0; qq < NS; ++qq) {
+                go[qq] = false;
+                at[qq] = 0;
+                if (sl[qq].busy && !(STITCHED && sl[qq].in_tail)) {
+                    ++sl[qq].t;
+                    const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
-                    if (x.x >= a.T) {
-                        sl[q].busy = false;
+                    if (x.x >= T) {
+                        sl[qq].busy = false;
                     } else {
-                        go[q] = true;
-                        at[q] = sl[q].o + pick32(x.y, sl[q].d);
+                        go[qq] = true;
+                        at[qq] = sl[qq].o + pick32(x.y, sl[qq].d);
                     }
                 }
             }
             uint2 e[NS];
 #pragma unroll
-            for (int q = 0; q < NS; ++q)
-                if (go[q]) e[q] = load_edge(a.E + at[q]);
+            for (int qq = 0; qq < NS; ++qq)
+                if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
 #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                if (!go[q]) continue;
+            for (int qq = 0; qq < NS; ++qq) {
+                if (!go[qq]) continue;
                 ++st_moves;
-                Slot &w = sl[q];
-                w.o = e[q].x;
-                w.d = e[q].y;
+                Slot &w = sl[qq];
+                w.o = e[qq].x;
+                w.d = e[qq].y;
                 const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
                 if (w.o == s_nodes[base + w.t - 1]) {
                     atomicAdd(&s_cnt[w.pos >> 24], 1u);
@@ -434,13 +433,13 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
                     w.busy = false;
                 } else if (w.t == len || w.d == 0u) {
                     w.busy = false;
-                } else if (STITCHED && w.t == (uint32_t)a.ix.seg_len) {
-                    const uint32_t y = a.ix.node_of[w.o];
-                    w.tsig = entry_slot(a.ix, a.key, s_vid[w.pos >> 24], w.rng.j, y);
+                } else if (STITCHED && w.t == (uint32_t)d.ix.seg_len) {
+                    const uint32_t y = d.ix.node_of[w.o];
+                    w.tsig = entry_slot(d.ix, key, s_vid[w.pos >> 24], w.rng.j, y);
                     w.tm = 0;
                     w.tu = 0;
                     w.tseg = w.tsig;
-                    w.tsl = a.ix.seg_lens[w.tseg];
+                    w.tsl = d.ix.seg_lens[w.tseg];
                     w.in_tail = true;
                     if (w.tsl == 0u) w.busy = false;
                 }
@@ -448,12 +447,12 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
             // ---- stitched tails: one step read from the index
             if (STITCHED) {
 #pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    Slot &w = sl[q];
-                    if (!(w.busy && w.in_tail) || go[q]) continue;
+                for (int qq = 0; qq < NS; ++qq) {
+                    Slot &w = sl[qq];
+                    if (!(w.busy && w.in_tail) || go[qq]) continue;
                     ++w.t;
                     ++st_tail;
-                    w.o = a.ix.seg[(size_t)w.tseg * a.ix.seg_len + w.tu];
+                    w.o = d.ix.seg[(size_t)w.tseg * d.ix.seg_len + w.tu];
                     ++w.tu;
                     const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
                     if (w.o == s_nodes[base + w.t - 1]) {
@@ -463,16 +462,16 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
                     } else if (w.t == len) {
                         w.busy = false;
                     } else if (w.tu == w.tsl) {
-                        if (w.tsl < (uint32_t)a.ix.seg_len || w.tm + 1 >= (uint32_t)a.ix.width) {
+                        if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width) {
                             w.busy = false;
                         } else {
                             ++w.tm;
-                            w.tseg = a.ix.chain[(size_t)w.tsig * a.ix.width + w.tm];
+                            w.tseg = d.ix.chain[(size_t)w.tsig * d.ix.width + w.tm];
                             w.tu = 0;
                             if (w.tseg == NIL) {
                                 w.busy = false;
                             } else {
-                                w.tsl = a.ix.seg_lens[w.tseg];
+                                w.tsl = d.ix.seg_lens[w.tseg];
                                 if (w.tsl == 0u) w.busy = false;
                             }
                         }
@@ -483,7 +482,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
             const uint32_t c = s_cnt[i];
-            if (c) atomicAdd(&a.cnt[s_vid[i]], c);
+            if (c) atomicAdd(&d.cnt[s_vid[i]], c);
         }
     }
 
@@ -496,20 +495,13 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(MeetArgs a) {
         v4 += __shfl_xor(v4, dd, 64);
     }
     if (lane == 0) {
-        atomicAdd(&a.counters[C_MOVES], v0);
-        atomicAdd(&a.counters[C_DRAWS], v1);
-        atomicAdd(&a.counters[C_MEETS], v2);
-        atomicAdd(&a.counters[C_TAIL], v3);
-        atomicAdd(&a.counters[C_PAIRS], v4);
+        atomicAdd(&counters[C_MOVES], v0);
+        atomicAdd(&counters[C_DRAWS], v1);
+        atomicAdd(&counters[C_MEETS], v2);
+        atomicAdd(&counters[C_TAIL], v3);
+        atomicAdd(&counters[C_PAIRS], v4);
     }
 }
-
-#ifndef SRK_MEET_SLOTS
-#define SRK_MEET_SLOTS 2
-#endif
-#ifndef SRK_MEET_SLOTS_STITCHED
-#define SRK_MEET_SLOTS_STITCHED 1
-#endif
 
 // ------------------------------------------------------ walk materialisation
 
@@ -561,19 +553,12 @@ __global__ __launch_bounds__(256) void k_walks(WalkArgs a) {
     a.lens[i] = len;
 }
 
-IndexView index_view(const Graph *g) {
-    IndexView v{};
-    v.node_of = g->node_of;
-    if (g->index) {
-        v.pool_off = g->index->pool_off;
-        v.seg = g->index->seg;
-        v.seg_lens = g->index->seg_lens;
-        v.chain = g->index->chain;
-        v.seg_len = g->index->seg_len;
-        v.width = g->index->width;
-    }
-    return v;
-}
+#ifndef SRK_MEET_SLOTS
+#define SRK_MEET_SLOTS 2
+#endif
+#ifndef SRK_MEET_SLOTS_STITCHED
+#define SRK_MEET_SLOTS_STITCHED 1
+#endif
 
 int meet_grid_blocks() {
     static int blocks = 0;
@@ -590,12 +575,84 @@ int meet_grid_blocks() {
     return blocks;
 }
 
+}  // namespace
+
+IndexView index_view(const Graph *g) {
+    IndexView v{};
+    v.node_of = g->node_of;
+    if (g->index) {
+        v.pool_off = g->index->pool_off;
+        v.seg = g->index->seg;
+        v.seg_lens = g->index->seg_lens;
+        v.chain = g->index->chain;
+        v.seg_len = g->index->seg_len;
+        v.width = g->index->width;
+    }
+    return v;
+}
+
 int32_t max_tiles_for(int32_t R, int32_t L) {
     const int64_t NW = TILE_NODES - L;
     return (int32_t)(2 + R / TILE_J + ((int64_t)R * L) / NW);
 }
 
-}  // namespace
+// Nodes per work unit: small graphs use small chunks so that their units
+// still spread over all CUs; simrank_tune replaces this by a measured choice.
+int32_t default_unit_nodes(const Graph *g) {
+    if (g->tuned_vb > 0) return g->tuned_vb;
+    if (g->n_active >= (1 << 19)) return 256;
+    if (g->n_active >= (1 << 17)) return 128;
+    if (g->n_active >= (1 << 15)) return 64;
+    return 32;
+}
+
+void describe_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                    int32_t vb, QueryDesc *d) {
+    *d = QueryDesc{};
+    d->nodes = g->nodes;
+    d->E = g->E;
+    d->active = g->active;
+    d->ix = index_view(g);
+    const PhiloxKey key = make_key(q->seed);
+    d->k0 = key.k0;
+    d->k1 = key.k1;
+    d->T = p.T;
+    d->n = g->n;
+    d->n_active = g->n_active;
+    d->s = q->s;
+    d->R = p.R;
+    d->L = p.L;
+    d->vb = vb;
+    d->n_chunks = (g->n_active + vb - 1) / vb;
+    d->stitched = mode == SIMRANK_MODE_STITCHED ? 1 : 0;
+}
+
+int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hipEvent_t ev_meet1) {
+    if (qs.nq <= 0) return SIMRANK_OK;
+    const unsigned nq = (unsigned)qs.nq;
+    const unsigned gx_n = std::min<unsigned>(grid_for(std::max(qs.max_n, 1), 256), 1024u);
+    k_init<<<dim3(gx_n, nq), 256, 0, st>>>(qs.desc, qs.counters);
+    k_source_walks<<<dim3(grid_for(qs.max_R, 256), nq), 256, 0, st>>>(qs.desc, qs.counters);
+    k_compact<<<nq, 1024, 0, st>>>(qs.desc);
+    k_unit_offsets<<<1, 1024, 0, st>>>(qs.desc, qs.nq, qs.units);
+    if (ev_meet0) SRK_HIP(hipEventRecord(ev_meet0, st));
+    const uint32_t *u_plain = qs.units, *u_st = qs.units + (qs.nq + 1);
+    uint32_t *c_plain = qs.units + 2 * (qs.nq + 1), *c_st = c_plain + 1;
+    if (qs.any_plain && qs.units_bound_plain > 0) {
+        const int blocks = (int)std::min<int64_t>(qs.units_bound_plain, meet_grid_blocks());
+        k_meet<false, SRK_MEET_SLOTS>
+            <<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, u_plain, c_plain, qs.counters);
+    }
+    if (qs.any_stitched && qs.units_bound_stitched > 0) {
+        const int blocks = (int)std::min<int64_t>(qs.units_bound_stitched, meet_grid_blocks());
+        k_meet<true, SRK_MEET_SLOTS_STITCHED>
+            <<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, u_st, c_st, qs.counters);
+    }
+    if (ev_meet1) SRK_HIP(hipEventRecord(ev_meet1, st));
+    k_estimate<<<dim3(gx_n, nq), 256, 0, st>>>(qs.desc);
+    SRK_HIP(hipGetLastError());
+    return SIMRANK_OK;
+}
 
 // ---------------------------------------------------------------- host side
 
@@ -650,6 +707,8 @@ int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws) 
     if ((rc = device_alloc((void **)&ws->tiles, 4 * ((size_t)ws->max_tiles + 1), nullptr))) return rc;
     if ((rc = device_alloc((void **)&ws->meta, 4 * 8, nullptr))) return rc;
     if ((rc = device_alloc((void **)&ws->counters, 8 * 8, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->desc, sizeof(QueryDesc), nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->units, 4 * 8, nullptr))) return rc;
     SRK_HIP(hipEventCreate(&ws->ev0));
     SRK_HIP(hipEventCreate(&ws->ev1));
     SRK_HIP(hipEventCreate(&ws->evm0));
@@ -667,6 +726,8 @@ void workspace_release(Workspace *ws) {
     device_free(ws->tiles);
     device_free(ws->meta);
     device_free(ws->counters);
+    device_free(ws->desc);
+    device_free(ws->units);
     if (ws->ev0) (void)hipEventDestroy(ws->ev0);
     if (ws->ev1) (void)hipEventDestroy(ws->ev1);
     if (ws->evm0) (void)hipEventDestroy(ws->evm0);
@@ -684,39 +745,37 @@ int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &
     if (stitched && !g->index) return fail(SIMRANK_ESTATE, "stitched query without an index");
     if (stitched && g->index->T != p.T)
         return fail(SIMRANK_EINVAL, "stitched query's c differs from the index's c");
+    const int32_t vb = default_unit_nodes(g);
+    QueryDesc d;
+    describe_query(g, q, p, mode, vb, &d);
     // the meet kernel counts work units (tile x node chunk) in 32 bits
-    const int64_t units_bound = (int64_t)max_tiles_for(p.R, p.L) *
-                                ((g->n_active + MEET_VB - 1) / MEET_VB);
+    const int64_t units_bound = (int64_t)max_tiles_for(p.R, p.L) * d.n_chunks;
     if (units_bound >= (int64_t)0xffffffffu - (1 << 20))
         return fail(SIMRANK_EINVAL, "R * L * n too large for one launch");
-    const PhiloxKey key = make_key(q->seed);
-    const IndexView ix = index_view(g);
-
+    d.sw = ws->sw;
+    d.slen = ws->slen;
+    d.jj = ws->jj;
+    d.joff = ws->joff;
+    d.swc = ws->swc;
+    d.tiles = ws->tiles;
+    d.meta = ws->meta;
+    d.cnt = counts_dev;
+    d.out = out_dev;
+    QuerySet qs;
+    qs.desc = ws->desc;
+    qs.nq = 1;
+    qs.max_R = p.R;
+    qs.max_n = g->n;
+    qs.any_plain = !stitched;
+    qs.any_stitched = stitched;
+    qs.units_bound_plain = stitched ? 0 : units_bound;
+    qs.units_bound_stitched = stitched ? units_bound : 0;
+    qs.units = ws->units;
+    qs.counters = ws->counters;
     SRK_HIP(hipEventRecord(ws->ev0, st));
-    k_query_init<<<grid_for(std::max<int64_t>(g->n, 8), 256), 256, 0, st>>>(counts_dev, g->n,
-                                                                           ws->meta, ws->counters);
-    SrcArgs sa{g->nodes, g->E, ix, ws->sw, ws->slen, ws->counters, key, p.T, p.R, p.L, q->s};
-    if (stitched)
-        k_source_walks<true><<<grid_for(p.R, 256), 256, 0, st>>>(sa);
-    else
-        k_source_walks<false><<<grid_for(p.R, 256), 256, 0, st>>>(sa);
-    k_compact<<<1, 1024, 0, st>>>(ws->slen, ws->sw, p.R, p.L, ws->jj, ws->joff, ws->swc,
-                                  ws->tiles, ws->meta, (uint32_t)(TILE_NODES - p.L));
-    const int32_t n_chunks = (g->n_active + MEET_VB - 1) / MEET_VB;
-    SRK_HIP(hipEventRecord(ws->evm0, st));
-    if (n_chunks > 0) {
-        MeetArgs ma{g->nodes, g->E, g->active, ws->jj, ws->joff, ws->swc, ws->tiles, ws->meta,
-                    counts_dev, ws->counters, ix, key, p.T, q->s, g->n_active, n_chunks};
-        const int64_t max_units = (int64_t)max_tiles_for(p.R, p.L) * n_chunks;
-        const int blocks = (int)std::min<int64_t>(max_units, meet_grid_blocks());
-        if (stitched)
-            k_meet<true, SRK_MEET_SLOTS_STITCHED><<<blocks, MEET_BLOCK, 0, st>>>(ma);
-        else
-            k_meet<false, SRK_MEET_SLOTS><<<blocks, MEET_BLOCK, 0, st>>>(ma);
-    }
-    SRK_HIP(hipEventRecord(ws->evm1, st));
-    k_estimate<<<grid_for(g->n, 256), 256, 0, st>>>(counts_dev, out_dev, g->n, p.R, q->s);
-    SRK_HIP(hipGetLastError());
+    k_set_desc<<<1, 1, 0, st>>>(ws->desc, d);
+    int rc = launch_query_set(qs, st, ws->evm0, ws->evm1);
+    if (rc) return rc;
     SRK_HIP(hipEventRecord(ws->ev1, st));
     ws->last_stream = st;
     ws->last_params = p;

@@ -113,6 +113,12 @@ def lib() -> C.CDLL:
         "simrank_index_info": [vp, P(simrank_index_summary)],
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
         "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
+        "simrank_batch_plan_create": [P(vp), i32, P(simrank_query), i32, P(vp)],
+        "simrank_batch_plan_run": [vp, vp],
+        "simrank_batch_plan_wait": [vp, P(simrank_stats)],
+        "simrank_batch_plan_read": [vp, i32, vp, vp],
+        "simrank_batch_plan_free": [vp],
+        "simrank_tune": [vp, P(simrank_query), P(i32)],
         "simrank_roofline_gather": [i64, i32, i32, P(simrank_rate)],
         "simrank_roofline_philox": [P(simrank_rate)],
         "simrank_roofline_copy": [i64, P(simrank_rate)],
@@ -342,6 +348,57 @@ def simrank_roofline_copy(nbytes: int) -> dict:
     r = simrank_rate()
     _check(lib().simrank_roofline_copy(int(nbytes), C.byref(r)))
     return r.asdict()
+
+
+class BatchPlan:
+    """simrank_batch_plan_*: device buffers and a captured launch of a query set."""
+
+    def __init__(self, graphs: list, queries: list):
+        ng, nq = len(graphs), len(queries)
+        garr = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
+        qarr = (simrank_query * nq)(*queries)
+        h = C.c_void_p()
+        _check(lib().simrank_batch_plan_create(garr, ng, qarr, nq, C.byref(h)))
+        self.handle = h
+        self.graphs = graphs
+        self.queries = list(queries)
+
+    def run(self, stream=None) -> None:
+        sp = None
+        if stream is not None:
+            sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().simrank_batch_plan_run(self.handle, sp))
+
+    def wait(self) -> simrank_stats:
+        st = simrank_stats()
+        _check(lib().simrank_batch_plan_wait(self.handle, C.byref(st)))
+        return st
+
+    def read(self, i: int, want_out: bool = True, want_counts: bool = True):
+        n = self.graphs[self.queries[i].graph].n
+        out = np.empty(n, np.float64) if want_out else None
+        cnt = np.empty(n, np.uint32) if want_counts else None
+        _check(lib().simrank_batch_plan_read(self.handle, i,
+                                             _ptr(out) if out is not None else None,
+                                             _ptr(cnt) if cnt is not None else None))
+        return out, cnt
+
+    def free(self) -> None:
+        if self.handle and self.handle.value:
+            _check(lib().simrank_batch_plan_free(self.handle))
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def simrank_tune(g: Graph, q: simrank_query) -> int:
+    vb = C.c_int32()
+    _check(lib().simrank_tune(g.handle, C.byref(q), C.byref(vb)))
+    return vb.value
 
 
 def simrank_version() -> str:

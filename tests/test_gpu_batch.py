@@ -1,0 +1,114 @@
+"""Batched queries (one captured launch sequence over many queries and graphs)
+and the work-unit tuner: every result must equal the lone query's, bit for
+bit, and the lone query's equals the oracle's (test_gpu_parity)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_04015_amd import inputs
+from paper_2304_04015_amd import simrank as S
+
+pytestmark = pytest.mark.gpu
+
+ISEED = 0x2304040150000013
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    gs = [inputs.erdos_renyi_in(700, 4.0, seed=31), inputs.rmat_in(12, 12 << 12, seed=32),
+          inputs.rmat_in(14, 20 << 14, seed=33), inputs.from_edges(6, [0] * 5, [1, 2, 3, 4, 5])]
+    Gs = [S.load_csr(g) for g in gs]
+    S.simrank_build_index(Gs[1], seg_log2=3, kappa=1.0, c=0.6, seed=ISEED)
+    return gs, Gs
+
+
+def _mix(gs, nq, seed):
+    rng = np.random.default_rng(seed)
+    qs = []
+    for i in range(nq):
+        gi = int(rng.integers(0, len(gs)))
+        act = np.nonzero(gs[gi].in_degree() > 0)[0]
+        s = int(rng.choice(act)) if act.size and rng.random() < 0.9 else int(rng.integers(0, gs[gi].n))
+        eps = float(rng.choice([0.05, 0.03, 0.02]))
+        mode = S.MODE_STITCHED if (gi == 1 and rng.random() < 0.5) else S.MODE_PLAIN
+        qs.append(S.make_query(s, c=0.6, eps=eps, delta=1e-3, seed=1000 + i, walk_cap=64,
+                               mode=mode, graph=gi))
+    return qs
+
+
+def test_batch_equals_lone_queries(graphs):
+    gs, Gs = graphs
+    qs = _mix(gs, 40, 1)
+    outs, cnts, st = S.simrank_batch(Gs, qs)
+    for i, q in enumerate(qs):
+        o1, c1, _ = S.simrank_single_source_ex(Gs[q.graph], q)
+        assert np.array_equal(cnts[i], c1), i
+        assert np.array_equal(outs[i], o1), i
+    assert st.moves > 0
+    # one plain and one stitched query also against the oracle
+    P = O.pool_sizes(gs[1], 1.0)
+    for i, q in enumerate(qs[:12]):
+        g = gs[q.graph]
+        if q.mode == S.MODE_STITCHED:
+            want = O.meet_counts_stitched(g, q.s, q.seed, ISEED, 0.6, 64, 8, P,
+                                          S.simrank_derive_params(q, g.n).R)
+        else:
+            want = O.meet_counts_plain(g, q.s, q.seed, 0.6, 64, S.simrank_derive_params(q, g.n).R)
+        assert np.array_equal(cnts[i], want), i
+
+
+def test_plan_replays_match(graphs):
+    """The captured graph is replayed several times, with the program's own
+    eager work and synchronisations between replays; every replay must equal
+    the eager results."""
+    import torch
+    gs, Gs = graphs
+    qs = _mix(gs, 24, 2)
+    lone = [S.simrank_single_source_ex(Gs[q.graph], q)[1] for q in qs]
+    plan = S.BatchPlan(Gs, qs)
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        plan.run(stream)
+        st = plan.wait()
+        for i in range(len(qs)):
+            _, c = plan.read(i, want_out=False)
+            assert np.array_equal(c, lone[i]), (rep, i)
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        y = (x * 2).sum()
+        torch.cuda.synchronize()
+        o, c, _ = S.simrank_single_source_ex(Gs[qs[0].graph], qs[0])
+        assert np.array_equal(c, lone[0]) and float(y) == float(y)
+    assert st.pairs > 0
+    plan.free()
+
+
+def test_tuner_keeps_results(graphs):
+    gs, Gs = graphs
+    g, G = gs[2], Gs[2]
+    q = S.make_query(int(np.argmax(g.in_degree())), c=0.6, eps=0.03, seed=77)
+    before = S.simrank_single_source_ex(G, q)[1]
+    vb = S.simrank_tune(G, q)
+    assert vb in (32, 64, 128, 256)
+    after = S.simrank_single_source_ex(G, q)[1]
+    assert np.array_equal(before, after)
+
+
+def test_batch_rejects_bad_queries(graphs):
+    gs, Gs = graphs
+    q = S.make_query(0, graph=7)
+    with pytest.raises(S.SimRankError):
+        S.simrank_batch(Gs, [q])
+    q = S.make_query(10 ** 6, graph=0)
+    with pytest.raises(S.SimRankError):
+        S.simrank_batch(Gs, [q])
+    q = S.make_query(1, graph=2, mode=S.MODE_STITCHED)       # graph 2 has no index
+    with pytest.raises(S.SimRankError):
+        S.simrank_batch(Gs, [q])
