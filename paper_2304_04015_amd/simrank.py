@@ -321,8 +321,10 @@ def simrank_batch(graphs: list[Graph], queries: list[simrank_query], want_counts
     nq = len(queries)
     garr = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
     qarr = (simrank_query * nq)(*queries)
-    outs = [np.empty(graphs[q.graph].n, np.float64) for q in queries]
-    cnts = [np.empty(graphs[q.graph].n, np.uint32) for q in queries] if want_counts else None
+    # an invalid graph index is the library's to reject (EINVAL); size its buffers at 1
+    sizes = [graphs[q.graph].n if 0 <= q.graph < ng else 1 for q in queries]
+    outs = [np.empty(n, np.float64) for n in sizes]
+    cnts = [np.empty(n, np.uint32) for n in sizes] if want_counts else None
     oarr = (C.c_void_p * nq)(*[o.ctypes.data for o in outs])
     carr = (C.c_void_p * nq)(*[c.ctypes.data for c in cnts]) if want_counts else None
     st = simrank_stats()
