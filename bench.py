@@ -58,10 +58,13 @@ def measured_traffic(path: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "stitching", "batching"],
+    ap.add_argument("--workload", default="medium",
+                    choices=["medium", "stitching", "batching", "serving"],
                     help="medium: the default line; stitching: R-MAT n=2^24 index build "
                          "and stitched query; batching: 512 queries over 16 graphs, "
-                         "one captured batch vs one query at a time")
+                         "one captured batch vs one query at a time; serving: Poisson "
+                         "arrivals on R-MAT n=2^22 at fractions of the plain capacity")
+    ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -92,6 +95,8 @@ def main():
         return bench_stitching(args)
     if args.workload == "batching":
         return bench_batching(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import numpy as np
     import torch
@@ -395,6 +400,112 @@ def bench_batching(args):
         ws.free()
     for G in Gs:
         G.free()
+
+
+def bench_serving(args):
+    """Serving workload: R-MAT n=2^22, avg degree 16, graph and stitched segment
+    index resident in HBM.  Requests: sources drawn proportionally to in-degree,
+    eps uniform in {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks.  First the
+    plain capacity (requests back to back, one at a time); then Poisson arrivals
+    at 0.5, 0.8, 1.0 and 1.2 times that rate into the server (4 slots):
+    achieved queries/s and p50 / p99 latency per level."""
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = dict(inputs.C5)
+    if args.scale:
+        cfg["scale"] = args.scale
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = inputs.workload_graph(cfg)
+    print(f"# graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s", file=sys.stderr)
+    G = S.load_csr(g)
+    S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=cfg["c"], seed=0x2304040150000023)
+    rng = np.random.default_rng(31)
+    deg = g.in_degree().astype(np.float64)
+
+    def make(i):
+        s = int(rng.choice(g.n, p=deg / deg.sum()))
+        return S.make_query(s, c=cfg["c"], eps=float(rng.choice(cfg["eps_choices"])),
+                            delta=cfg["delta"], seed=0x2304040150000500 + i, walk_cap=cfg["L"],
+                            mode=S.MODE_STITCHED)
+
+    S.simrank_tune(G, make(0))
+    # plain capacity: one request at a time, back to back
+    warm = [make(i) for i in range(2)]
+    cap_q = [make(100 + i) for i in range(12)]
+    ws = S.simrank_workspace_create(G, 9502, cfg["L"])
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    cnt = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    for q in warm:
+        S.simrank_single_source_async(G, q, ws, out, cnt, stream)
+        S.simrank_workspace_stats(ws)
+    t1 = time.perf_counter()
+    steps = 0
+    for q in cap_q:
+        S.simrank_single_source_async(G, q, ws, out, cnt, stream)
+        st = S.simrank_workspace_stats(ws)
+        steps += st.moves + st.tail_steps + st.source_moves
+        _ = out.cpu()                       # results to host, as a served request has
+    plain_s = time.perf_counter() - t1
+    capacity = len(cap_q) / plain_s
+    ws.free()
+    srv = S.Server(G, max_slots=4, max_R=9502, max_L=cfg["L"])
+    levels = []
+    k = 1000
+    for load in (0.5, 0.8, 1.0, 1.2):
+        qps = load * capacity
+        reqs = [make(k + i) for i in range(args.requests)]
+        k += args.requests
+        gaps = rng.exponential(1.0 / qps, size=len(reqs))
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for q, gap in zip(reqs, gaps):
+            t_next += gap
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(q))
+        lat, qwait, wsteps = [], [], 0
+        for t in tickets:
+            _, _, info = srv.wait(t, want_counts=False)
+            lat.append(info.latency_s)
+            qwait.append(info.queue_s)
+            wsteps += info.stats.moves + info.stats.tail_steps + info.stats.source_moves
+        t_end = time.perf_counter()
+        levels.append({"load": load, "offered_qps": qps,
+                       "achieved_qps": len(reqs) / (t_end - t_start),
+                       "walk_steps_per_s": wsteps / (t_end - t_start),
+                       "p50_latency_s": float(np.percentile(lat, 50)),
+                       "p99_latency_s": float(np.percentile(lat, 99)),
+                       "mean_queue_s": float(np.mean(qwait))})
+        print(f"# load {load}: {levels[-1]}", file=sys.stderr)
+    top = levels[-1]
+    result = {
+        "metric": METRIC,
+        "value": top["walk_steps_per_s"],
+        "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": len(levels), "warmup": len(warm),
+        "ms_per_step": 1e3 * args.requests / top["achieved_qps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"serving: R-MAT n=2^{cfg['scale']}, avg degree 16, index "
+                               "resident; sources by in-degree, eps in {.05,.02}, stitched; "
+                               "Poisson arrivals at 0.5-1.2x plain capacity; 4 slots",
+                   "n": g.n, "m": g.m, "requests_per_level": args.requests},
+        "queries_per_s": top["achieved_qps"],
+        "plain_queries_per_s": capacity,
+        "served_vs_plain": top["achieved_qps"] / capacity,
+        "levels": levels,
+    }
+    print(json.dumps(result))
+    srv.destroy()
+    G.free()
 
 
 if __name__ == "__main__":

@@ -235,6 +235,48 @@ int simrank_batch_plan_free(simrank_batch_plan *plan);
  * called while other threads query g. */
 int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out);
 
+/* --------------------------------------------------------------- serving */
+
+/* A request loop over one device-resident graph (and its index).  Requests
+ * are queued by simrank_server_submit and admitted by a worker thread into
+ * slots as slots free up; a slot (workspace, device and pinned host buffers,
+ * own stream) holds one running request, and as many slots are made as the
+ * device-memory budget admits (at most max_slots), so requests that arrive
+ * while others run start as soon as a slot frees and run concurrently on the
+ * device.  Each result equals what simrank_single_source_ex returns for the
+ * same query alone. */
+typedef struct simrank_server simrank_server;
+
+typedef struct simrank_server_params {
+    int32_t max_slots;    /* 1..64 concurrent requests */
+    int32_t max_R;        /* largest R a request may need */
+    int32_t max_L;        /* largest walk cap a request may use */
+    int32_t reserved;
+    int64_t hbm_budget;   /* device bytes the slots may take; 0: half the free memory */
+} simrank_server_params;
+
+typedef struct simrank_request_info {
+    double queue_s;       /* submit -> start of its kernels being enqueued */
+    double latency_s;     /* submit -> results in host memory */
+    simrank_stats stats;  /* work and device time of the request */
+} simrank_request_info;
+
+/* The graph must outlive the server.  ENOMEM when the budget admits no slot. */
+int simrank_server_create(simrank_graph *g, const simrank_server_params *p,
+                          simrank_server **server_out);
+/* Slots made and device bytes per slot. */
+int simrank_server_info(const simrank_server *server, int32_t *slots, int64_t *slot_bytes);
+/* Validates and queues a query (q->graph ignored); returns at once with a ticket. */
+int simrank_server_submit(simrank_server *server, const simrank_query *q, uint64_t *ticket);
+/* Waits up to timeout_s seconds (< 0: no limit) for the request, copies its
+ * estimate (host double[n], may be NULL) and counts (host uint32[n], may be
+ * NULL) and fills info (may be NULL); the ticket is then retired.  ESTATE on
+ * timeout (the ticket stays valid). */
+int simrank_server_wait(simrank_server *server, uint64_t ticket, double timeout_s,
+                        double *out_host, uint32_t *counts_host, simrank_request_info *info);
+/* Finishes the queued and running requests, then frees the server. */
+int simrank_server_destroy(simrank_server *server);
+
 /* ---------------------------------------------------------------- errors */
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -59,6 +59,15 @@ class simrank_index_params(C.Structure):
                 ("c", C.c_double), ("seed", C.c_uint64)]
 
 
+class simrank_server_params(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("max_R", C.c_int32), ("max_L", C.c_int32),
+                ("reserved", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class simrank_request_info(C.Structure):
+    _fields_ = [("queue_s", C.c_double), ("latency_s", C.c_double), ("stats", simrank_stats)]
+
+
 class simrank_rate(C.Structure):
     _fields_ = [("per_s", C.c_double), ("ms", C.c_double), ("count", C.c_double)]
 
@@ -119,6 +128,11 @@ def lib() -> C.CDLL:
         "simrank_batch_plan_read": [vp, i32, vp, vp],
         "simrank_batch_plan_free": [vp],
         "simrank_tune": [vp, P(simrank_query), P(i32)],
+        "simrank_server_create": [vp, P(simrank_server_params), P(vp)],
+        "simrank_server_info": [vp, P(i32), P(i64)],
+        "simrank_server_submit": [vp, P(simrank_query), P(C.c_uint64)],
+        "simrank_server_wait": [vp, C.c_uint64, dbl, vp, vp, P(simrank_request_info)],
+        "simrank_server_destroy": [vp],
         "simrank_roofline_gather": [i64, i32, i32, P(simrank_rate)],
         "simrank_roofline_philox": [P(simrank_rate)],
         "simrank_roofline_copy": [i64, P(simrank_rate)],
@@ -393,6 +407,51 @@ class BatchPlan:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """simrank_server_*: continuous admission of single-source requests."""
+
+    def __init__(self, g: Graph, max_slots: int = 4, max_R: int = 9502, max_L: int = 64,
+                 hbm_budget: int = 0):
+        p = simrank_server_params(max_slots=max_slots, max_R=max_R, max_L=max_L, reserved=0,
+                                  hbm_budget=hbm_budget)
+        h = C.c_void_p()
+        _check(lib().simrank_server_create(g.handle, C.byref(p), C.byref(h)))
+        self.handle = h
+        self.graph = g
+
+    def info(self) -> dict:
+        s, b = C.c_int32(), C.c_int64()
+        _check(lib().simrank_server_info(self.handle, C.byref(s), C.byref(b)))
+        return dict(slots=s.value, slot_bytes=b.value)
+
+    def submit(self, q: simrank_query) -> int:
+        t = C.c_uint64()
+        _check(lib().simrank_server_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0, want_out: bool = True,
+             want_counts: bool = True):
+        n = self.graph.n
+        out = np.empty(n, np.float64) if want_out else None
+        cnt = np.empty(n, np.uint32) if want_counts else None
+        info = simrank_request_info()
+        _check(lib().simrank_server_wait(self.handle, ticket, float(timeout_s),
+                                         _ptr(out) if out is not None else None,
+                                         _ptr(cnt) if cnt is not None else None, C.byref(info)))
+        return out, cnt, info
+
+    def destroy(self) -> None:
+        if self.handle and self.handle.value:
+            _check(lib().simrank_server_destroy(self.handle))
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass
 

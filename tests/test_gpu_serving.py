@@ -1,0 +1,83 @@
+"""The serving loop: requests admitted into slots as they free up, running
+concurrently; each result must equal the lone query's bit for bit."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2304_04015_amd import inputs
+from paper_2304_04015_amd import simrank as S
+
+pytestmark = pytest.mark.gpu
+
+ISEED = 0x2304040150000013
+
+
+@pytest.fixture(scope="module")
+def served():
+    g = inputs.rmat_in(14, 16 << 14, seed=41)
+    G = S.load_csr(g)
+    S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=0.6, seed=ISEED)
+    return g, G
+
+
+def _requests(g, k, seed):
+    rng = np.random.default_rng(seed)
+    deg = g.in_degree().astype(np.float64)
+    qs = []
+    for i in range(k):
+        s = int(rng.choice(g.n, p=deg / deg.sum()))
+        eps = float(rng.choice([0.05, 0.02]))
+        mode = S.MODE_STITCHED if i % 7 == 3 else S.MODE_PLAIN
+        qs.append(S.make_query(s, c=0.6, eps=eps, delta=1e-3, seed=0x5E12 + i, mode=mode))
+    return qs
+
+
+def test_results_in_the_mix_equal_lone(served):
+    g, G = served
+    qs = _requests(g, 30, 1)
+    lone = [S.simrank_single_source_ex(G, q) for q in qs]
+    srv = S.Server(G, max_slots=4, max_R=9502, max_L=64)
+    assert srv.info()["slots"] == 4
+    tickets = []
+    for i, q in enumerate(qs):
+        tickets.append(srv.submit(q))
+        if i % 5 == 4:
+            time.sleep(0.002)          # arrivals while earlier requests run
+    for t, (o1, c1, _) in zip(tickets, lone):
+        o, c, info = srv.wait(t)
+        assert np.array_equal(c, c1)
+        assert np.array_equal(o, o1)
+        assert info.latency_s >= info.queue_s >= 0.0
+        assert info.stats.moves > 0 or c1.sum() == info.stats.R
+    srv.destroy()
+
+
+def test_budget_limits_slots(served):
+    g, G = served
+    probe = S.Server(G, max_slots=1, max_R=1521, max_L=64)
+    per = probe.info()["slot_bytes"]
+    probe.destroy()
+    srv = S.Server(G, max_slots=8, max_R=1521, max_L=64, hbm_budget=int(2.5 * per))
+    assert srv.info()["slots"] == 2
+    qs = [S.make_query(q.s, c=0.6, eps=0.05, seed=q.seed, mode=q.mode) for q in _requests(g, 6, 2)]
+    ts = [srv.submit(q) for q in qs]
+    for t, q in zip(ts, qs):
+        _, c, _ = srv.wait(t)
+        assert np.array_equal(c, S.simrank_single_source_ex(G, q)[1])
+    srv.destroy()
+    with pytest.raises(S.SimRankError) as e:
+        S.Server(G, max_slots=2, max_R=1521, max_L=64, hbm_budget=per // 2)
+    assert e.value.code == S.SIMRANK_ENOMEM
+
+
+def test_rejects(served):
+    g, G = served
+    srv = S.Server(G, max_slots=1, max_R=1521, max_L=64)
+    with pytest.raises(S.SimRankError):
+        srv.submit(S.make_query(0, eps=0.02))            # R = 9502 > the slots' 1521
+    with pytest.raises(S.SimRankError):
+        srv.submit(S.make_query(g.n, eps=0.05))          # source out of range
+    with pytest.raises(S.SimRankError):
+        srv.wait(123456)
+    srv.destroy()
