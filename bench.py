@@ -37,7 +37,7 @@ def kernel_fingerprint() -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_04015_amd", "csrc")
     h = b"".join(open(os.path.join(csrc, f), "rb").read()
-                 for f in ("query.hip", "philox.hpp", "common.hpp"))
+                 for f in ("query.hip", "device_common.hpp", "philox.hpp", "common.hpp"))
     return hashlib.sha256(h).hexdigest()[:16]
 
 

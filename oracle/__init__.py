@@ -9,7 +9,9 @@ library and never imports it.
               formulas (Hoeffding sample size, truncation bias).
 * this file : ctypes bindings of the single-threaded C oracle in
               `simrank_oracle.c` (Philox4x32-10, plain and stitched sqrt(c)-walks,
-              meet counts, walk tables).
+              meet counts, walk tables; the length-stratified estimator of
+              Algorithms 1 and 2: class sizes, shuffle, fixed-length walks,
+              weighted meet sums).
 """
 from __future__ import annotations
 
@@ -82,6 +84,27 @@ def lib():
         L.oracle_draw_block.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                         C.c_int64, u32p]
         L.oracle_draw_block.restype = None
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.oracle_strat_params.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double,
+                                          C.c_int32, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int64), f64p, i64p]
+        L.oracle_strat_params.restype = C.c_int
+        L.oracle_shuffle_slot.argtypes = [C.c_uint64, C.c_int32, C.c_uint32, C.c_int64]
+        L.oracle_shuffle_slot.restype = C.c_uint32
+        L.oracle_walk_strat.argtypes = [i32p, i32p, C.c_uint64, C.c_int32, C.c_int32, C.c_uint32,
+                                        i32p]
+        L.oracle_walk_strat.restype = C.c_int32
+        L.oracle_walk_table_strat.argtypes = [i32p, i32p, C.c_uint64, i64p, C.c_int32, C.c_int64,
+                                              i32p, u32p, C.c_int64, i32p, i32p, u32p, i32p]
+        L.oracle_walk_table_strat.restype = None
+        L.oracle_strat_weight.argtypes = [f64p, i64p, C.c_int32, C.c_int32]
+        L.oracle_strat_weight.restype = C.c_uint64
+        L.oracle_strat_sums.argtypes = [i32p, i32p, C.c_uint64, f64p, i64p, C.c_int32, C.c_int64,
+                                        C.c_int32, i32p, C.c_int64, u64p, C.c_void_p, C.c_void_p]
+        L.oracle_strat_sums.restype = None
+        L.oracle_strat_estimates.argtypes = [u64p, i32p, C.c_int64, C.c_int32, C.c_double,
+                                             C.c_int64, f64p, f64p]
+        L.oracle_strat_estimates.restype = None
         _lib = L
     return _lib
 
@@ -174,3 +197,91 @@ def meet_counts_stitched(g, s, seed, index_seed, c, L, seglen, P, R, vs=None):
                                       continue_threshold(c), L, seglen,
                                       np.ascontiguousarray(P, np.int64), R, s, vs, vs.size, cnt)
     return cnt
+
+
+# --------------------------------------------------------------------------
+# Length-stratified estimator (Algorithms 1 and 2)
+# --------------------------------------------------------------------------
+
+class StratParams:
+    """z, walk cap phi, class sizes Z_l (expected) and Zhat_l = ceil(Z_l)
+    (generated), N = sum Zhat_l walks per node."""
+
+    def __init__(self, z, phi, N, Z, Zhat):
+        self.z, self.phi, self.N = z, phi, N
+        self.Z, self.Zhat = Z, Zhat
+
+    def __repr__(self):
+        return f"StratParams(z={self.z!r}, phi={self.phi}, N={self.N})"
+
+
+def strat_params(n: int, c: float, eps: float, z: float = 0.0, phi: int = 0) -> StratParams:
+    Z = np.zeros(256, np.float64)
+    Zhat = np.zeros(256, np.int64)
+    zo, po, No = C.c_double(), C.c_int32(), C.c_int64()
+    rc = lib().oracle_strat_params(n, float(c), float(eps), float(z), int(phi), C.byref(zo),
+                                   C.byref(po), C.byref(No), Z, Zhat)
+    if rc != 0:
+        raise ValueError("invalid stratified-estimator parameters")
+    k = po.value + 1
+    return StratParams(zo.value, po.value, No.value, Z[:k].copy(), Zhat[:k].copy())
+
+
+def _padded(P: StratParams):
+    Z = np.zeros(256, np.float64)
+    Zhat = np.zeros(256, np.int64)
+    Z[: P.phi + 1] = P.Z
+    Zhat[: P.phi + 1] = P.Zhat
+    return Z, Zhat
+
+
+def shuffle_slot(seed: int, v: int, j: int, N: int) -> int:
+    return int(lib().oracle_shuffle_slot(seed, v, j, N))
+
+
+def walk_strat(g, seed: int, length: int, v: int, r: int) -> np.ndarray:
+    path = np.full(length + 1, -1, np.int32)
+    k = lib().oracle_walk_strat(_i32(g.in_off), _i32(g.in_src), seed, length, v, r, path)
+    return path[: k + 1].copy()
+
+
+def walk_table_strat(g, seed: int, P: StratParams, vs, js):
+    """Walk j of node v after the shuffle, for the listed (v, j): paths
+    [count][phi+1] (-1 padded), lengths, generated slots and classes."""
+    vs = _i32(vs)
+    js = np.ascontiguousarray(js, np.uint32)
+    _, Zhat = _padded(P)
+    paths = np.empty((vs.size, P.phi + 1), np.int32)
+    lens = np.empty(vs.size, np.int32)
+    slots = np.empty(vs.size, np.uint32)
+    cls = np.empty(vs.size, np.int32)
+    lib().oracle_walk_table_strat(_i32(g.in_off), _i32(g.in_src), seed, Zhat, P.phi, P.N, vs, js,
+                                  vs.size, paths, lens, slots, cls)
+    return paths, lens, slots, cls
+
+
+def strat_weight(P: StratParams, l1: int, l2: int) -> int:
+    Z, Zhat = _padded(P)
+    return int(lib().oracle_strat_weight(Z, Zhat, l1, l2))
+
+
+def strat_sums(g, s: int, seed: int, P: StratParams, vs=None, with_stats=False):
+    """Weighted meet sums (fixed point, 2^40 = weight 1) of walk pairs (s, u)."""
+    vs = np.arange(g.n, dtype=np.int32) if vs is None else _i32(vs)
+    Z, Zhat = _padded(P)
+    wsum = np.zeros(vs.size, np.uint64)
+    meets = np.zeros(vs.size, np.uint32)
+    work = np.zeros(vs.size, np.uint64)
+    lib().oracle_strat_sums(_i32(g.in_off), _i32(g.in_src), seed, Z, Zhat, P.phi, P.N, s, vs,
+                            vs.size, wsum, meets.ctypes.data, work.ctypes.data)
+    return (wsum, meets, work) if with_stats else wsum
+
+
+def strat_estimates(wsum, s: int, P: StratParams, vs=None):
+    """(Algorithm 2's estimate, the estimate normalised by the N pairs)."""
+    wsum = np.ascontiguousarray(wsum, np.uint64)
+    vs = np.arange(wsum.size, dtype=np.int32) if vs is None else _i32(vs)
+    out = np.empty(vs.size, np.float64)
+    out_n = np.empty(vs.size, np.float64)
+    lib().oracle_strat_estimates(wsum, vs, vs.size, s, P.z, P.N, out, out_n)
+    return out, out_n

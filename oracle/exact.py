@@ -85,3 +85,49 @@ def hoeffding_R(eps: float, delta: float, c: float, L: int, n: int | None = None
         raise ValueError("eps must exceed the truncation bias c^(L+1)")
     numer = math.log(2.0 / delta) if n is None else math.log(2.0 * n / delta)
     return int(math.ceil(numer / (2.0 * lam * lam)))
+
+
+# ---------------------------------------------------------------------------
+# First-meeting probabilities and the length-stratified estimator's mean
+# ---------------------------------------------------------------------------
+
+def first_meet_probs(n, in_off, in_src, s: int, T: int) -> np.ndarray:
+    """F[t, u] = probability that two uniform walks on the reversed graph (no
+    stopping), from s and from u, first occupy the same node at step t,
+    t = 0..T.  Pair dynamics: the joint law Q of the two positions moves by
+    Q <- W Q W^T (column v of W is the law of the next position from v);
+    after each step the mass on the diagonal is the first-meeting mass and is
+    removed.  A walk at a node without in-neighbours loses its mass."""
+    W = transition(n, in_off, in_src)
+    F = np.zeros((T + 1, n), np.float64)
+    F[0, s] = 1.0
+    Q = np.zeros((n, n, n), np.float64)       # Q[u] = joint law for the pair (s, u)
+    for u in range(n):
+        if u != s:
+            Q[u, s, u] = 1.0
+    idx = np.arange(n)
+    for t in range(1, T + 1):
+        Q = np.einsum("ax,uxy,by->uab", W, Q, W, optimize=True)
+        F[t] = Q[:, idx, idx].sum(axis=1)
+        Q[:, idx, idx] = 0.0
+    return F
+
+
+def stratified_expectation(n, in_off, in_src, c: float, s: int, phi: int) -> np.ndarray:
+    """Mean of the length-stratified estimate normalised by its N pairs, for
+    every u, on a graph without dead ends: walk j of s and of u have lengths
+    l1, l2 in 0..phi drawn with weights proportional to Zhat_l (the shuffle),
+    and a meeting pair is weighted by the ratio of the geometric law
+    p_l = sqrt(c)^l (1 - sqrt(c)) to that sampling law, so the mean is
+        sum_{l1, l2 <= phi} p_l1 p_l2 Pr[meet within min(l1, l2) steps]
+      = sum_{t=1..phi} F_t (sqrt(c)^t - sqrt(c)^(phi+1))^2,
+    since both lengths lie in [t, phi] with probability
+    (sqrt(c)^t - sqrt(c)^(phi+1))^2.  Algorithm 2's own normalisation by z
+    multiplies this by z / N.  The value at u = s is 1."""
+    F = first_meet_probs(n, in_off, in_src, s, phi)
+    r = math.sqrt(c)
+    tail = r ** (phi + 1)
+    w = np.array([0.0] + [(r ** t - tail) ** 2 for t in range(1, phi + 1)])
+    E = (w[:, None] * F).sum(axis=0)
+    E[s] = 1.0
+    return E

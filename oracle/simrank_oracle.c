@@ -18,7 +18,9 @@
  * (node, walk, step, domain) with domains
  *   0 = step of a plain walk, 1 = step of a pool segment,
  *   2 = pick of the pool slot a walk enters after its private head,
- *   3 = pick of the successor slot of a pool segment.
+ *   3 = pick of the successor slot of a pool segment,
+ *   4 = step of a fixed-length walk of the length-stratified estimator,
+ *   5 = round keys of a node's walk shuffle.
  *
  * Readings of the paper that the oracle fixes (each listed in the design notes):
  *  - a walk at step t first draws; it stops if x0 >= T, T = floor(sqrt(c)*2^32)
@@ -35,7 +37,10 @@
  * stitched-walk functions are pinned only by their special cases (a segment at
  * least as long as the walk cap reduces them to plain walks, heads equal plain
  * prefixes, serial traversal); the statistical effect of shared tails has no
- * closed form: parity unpinned for that effect.
+ * closed form: parity unpinned for that effect.  The length-stratified
+ * estimator is pinned by its expectation, computed exactly from first-meeting
+ * probabilities (oracle/exact.py), by the permutation property of the shuffle
+ * and by the class sizes.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -297,4 +302,237 @@ void oracle_draw_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2_firs
 {
     for (int64_t i = 0; i < count; ++i)
         draw(seed, c0, c1, c2_first + (uint32_t)i, c3, out + 4 * i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Length-stratified estimator (Algorithm 1: N_l walks of exact length l     */
+/* from every node, l = 0..phi, then a shuffle of each node's walks;          */
+/* Algorithm 2 with Lemma 5: the j-th walks of s and u are paired, and a      */
+/* pair that meets adds (Z_l1 Z_l2) / (Zhat_l1 Zhat_l2) / z to s~(s,u)).       */
+/* ------------------------------------------------------------------------ */
+
+/* Parameters.  phi = floor(ln n / ln(1/sqrt c)) (Algorithm 1's walk length
+ * cap), unless phi_override > 0 (the p-fold cap of the error-threshold
+ * extension).  z = ln(2n) / (2 (eps - 3/n)^2) (Algorithm 2), unless
+ * z_override > 0.  Z_l = z * sqrt(c)^l * (1 - sqrt(c)), the expected number of
+ * length-l walks, and Zhat_l = ceil(Z_l) walks are generated (Section 5 on
+ * rounding); N = sum of Zhat_l.  sqrt(c)^l is formed by repeated
+ * multiplication.  Z and Zhat need phi + 1 entries (at most 256).
+ * Returns 0, or -1 for an invalid request (eps <= 3/n, phi outside [0, 255]). */
+int oracle_strat_params(int32_t n, double c, double eps, double z_override, int32_t phi_override,
+                        double *z_out, int32_t *phi_out, int64_t *N_out, double *Z, int64_t *Zhat)
+{
+    double z;
+    if (z_override > 0.0) {
+        z = z_override;
+    } else {
+        double gap = eps - 3.0 / (double)n;
+        if (!(gap > 0.0)) return -1;
+        z = log(2.0 * (double)n) / (2.0 * gap * gap);
+    }
+    double r = sqrt(c);
+    int32_t phi;
+    if (phi_override > 0) {
+        phi = phi_override;
+    } else {
+        double f = floor(log((double)n) / log(1.0 / r));
+        if (!(f >= 0.0 && f <= 255.0)) return -1;
+        phi = (int32_t)f;
+    }
+    if (phi > 255) return -1;
+    double g = 1.0;                 /* sqrt(c)^l */
+    int64_t N = 0;
+    for (int32_t l = 0; l <= phi; ++l) {
+        Z[l] = (z * g) * (1.0 - r);
+        Zhat[l] = (int64_t)ceil(Z[l]);
+        N += Zhat[l];
+        g = g * r;
+    }
+    *z_out = z;
+    *phi_out = phi;
+    *N_out = N;
+    return 0;
+}
+
+/* MurmurHash3's 32-bit finalizer (A. Appleby, public domain): the round
+ * function of the shuffle's Feistel network. */
+static uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* A keyed bijection of [0, 2^bits): split x into a high part of
+ * bits - bits/2 bits and a low part of bits/2 bits, then four rounds that
+ * alternately XOR one part with the round function of the other part (each
+ * round is invertible, so the whole map is). */
+static uint32_t feistel4(uint32_t x, int bits, const uint32_t k[4])
+{
+    int a = bits / 2, h = bits - a;
+    uint32_t ma = (1u << a) - 1u, mh = (1u << h) - 1u;
+    uint32_t hi = x >> a, lo = x & ma;
+    hi ^= fmix32(lo ^ k[0]) & mh;
+    lo ^= fmix32(hi ^ k[1]) & ma;
+    hi ^= fmix32(lo ^ k[2]) & mh;
+    lo ^= fmix32(hi ^ k[3]) & ma;
+    return (hi << a) | lo;
+}
+
+/* Shuffle of node v's N walks (Section 4.2; the paper leaves the method
+ * open): walk j after the shuffle is the walk generated in slot pi_v(j), where
+ * pi_v is the Feistel bijection above on the smallest power of two >= N (at
+ * least 4), restricted to [0, N) by cycle walking (Black and Rogaway, "Ciphers
+ * with Arbitrary Finite Domains", CT-RSA 2002): apply it again while the value
+ * is >= N.  Round keys: Philox(ctr = (v, 0, 0, 5)). */
+uint32_t oracle_shuffle_slot(uint64_t seed, int32_t v, uint32_t j, int64_t N)
+{
+    int bits = 2;
+    while (((int64_t)1 << bits) < N) ++bits;
+    uint32_t k[4];
+    draw(seed, (uint32_t)v, 0u, 0u, 5u, k);
+    uint32_t y = feistel4(j, bits, k);
+    while ((int64_t)y >= N) y = feistel4(y, bits, k);
+    return y;
+}
+
+/* Length class of generated slot r: the walks of node v are generated class
+ * by class, Zhat_0 of length 0 first, then Zhat_1 of length 1, ... */
+static int32_t slot_class(uint32_t r, const int64_t *Zhat, int32_t phi)
+{
+    int64_t start = 0;
+    for (int32_t l = 0; l <= phi; ++l) {
+        if ((int64_t)r < start + Zhat[l]) return l;
+        start += Zhat[l];
+    }
+    return -1;   /* r >= N: not a slot */
+}
+
+/* The walk generated in slot r of node v: `length` uniform steps on the
+ * reversed graph, step t picking in-neighbour floor(x1 * deg / 2^32) of
+ * x = Philox(ctr = (v, r, t, 4)).  It ends early at a node without
+ * in-neighbours (the paper does not say what a fixed-length walk does there).
+ * path[0..len]; returns len. */
+int32_t oracle_walk_strat(const int32_t *off, const int32_t *src, uint64_t seed, int32_t length,
+                          int32_t v, uint32_t r, int32_t *path)
+{
+    int32_t cur = v;
+    path[0] = v;
+    int32_t t;
+    for (t = 1; t <= length; ++t) {
+        int32_t deg = off[cur + 1] - off[cur];
+        if (deg == 0) break;
+        uint32_t x[4];
+        draw(seed, (uint32_t)v, r, (uint32_t)t, 4u, x);
+        cur = src[off[cur] + (int32_t)pick(x[1], (uint64_t)deg)];
+        path[t] = cur;
+    }
+    return t - 1;
+}
+
+/* Walk j of node v after the shuffle: its slot, class and path. */
+int32_t oracle_walk_strat_j(const int32_t *off, const int32_t *src, uint64_t seed,
+                            const int64_t *Zhat, int32_t phi, int64_t N, int32_t v, uint32_t j,
+                            uint32_t *slot_out, int32_t *class_out, int32_t *path)
+{
+    uint32_t r = oracle_shuffle_slot(seed, v, j, N);
+    int32_t l = slot_class(r, Zhat, phi);
+    if (slot_out) *slot_out = r;
+    if (class_out) *class_out = l;
+    return oracle_walk_strat(off, src, seed, l, v, r, path);
+}
+
+void oracle_walk_table_strat(const int32_t *off, const int32_t *src, uint64_t seed,
+                             const int64_t *Zhat, int32_t phi, int64_t N, const int32_t *vs,
+                             const uint32_t *js, int64_t count, int32_t *paths, int32_t *lens,
+                             uint32_t *slots, int32_t *classes)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        int32_t *row = paths + (size_t)i * (phi + 1);
+        for (int32_t t = 0; t <= phi; ++t) row[t] = -1;
+        lens[i] = oracle_walk_strat_j(off, src, seed, Zhat, phi, N, vs[i], js[i], slots + i,
+                                      classes + i, row);
+    }
+}
+
+/* Meet weight of a pair of classes (Lemma 5) in fixed point: the product
+ * (Z_l1 / Zhat_l1) * (Z_l2 / Zhat_l2), scaled by 2^40 and truncated to an
+ * integer, so that sums of weights are exact and independent of order. */
+uint64_t oracle_strat_weight(const double *Z, const int64_t *Zhat, int32_t l1, int32_t l2)
+{
+    double a1 = Z[l1] / (double)Zhat[l1];
+    double a2 = Z[l2] / (double)Zhat[l2];
+    return (uint64_t)ldexp(a1 * a2, 40);
+}
+
+/*
+ * Weighted meet sums of Algorithm 2 for the listed nodes u:
+ *   wsum[i] = sum over j < N of [walks j of s and of u meet] * weight(l1, l2),
+ * with l1, l2 the classes of the two walks and a meet = the same node at the
+ * same step i >= 1 (the tuples of a walk are its steps 1..len, Section 4.3),
+ * counted once per pair.  u == s has no pairs (its estimate is 1).
+ * meets_opt: number of meeting pairs; work_opt: moves a walker needs to follow
+ * walk j of u only as far as the pair can still meet (min(len_s, len_u, first
+ * meeting step)), summed over j.
+ */
+void oracle_strat_sums(const int32_t *off, const int32_t *src, uint64_t seed, const double *Z,
+                       const int64_t *Zhat, int32_t phi, int64_t N, int32_t s, const int32_t *vs,
+                       int64_t nv, uint64_t *wsum, uint32_t *meets_opt, uint64_t *work_opt)
+{
+    int32_t *sw = (int32_t *)malloc(sizeof(int32_t) * (size_t)N * (size_t)(phi + 1));
+    int32_t *sl = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *sc = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *pu = (int32_t *)malloc(sizeof(int32_t) * (size_t)(phi + 1));
+    for (int64_t j = 0; j < N; ++j)
+        sl[j] = oracle_walk_strat_j(off, src, seed, Zhat, phi, N, s, (uint32_t)j, NULL, sc + j,
+                                    sw + (size_t)j * (phi + 1));
+    for (int64_t i = 0; i < nv; ++i) {
+        uint64_t acc = 0, work = 0;
+        uint32_t meets = 0;
+        if (vs[i] != s) {
+            for (int64_t j = 0; j < N; ++j) {
+                int32_t cu;
+                int32_t lu = oracle_walk_strat_j(off, src, seed, Zhat, phi, N, vs[i], (uint32_t)j,
+                                                 NULL, &cu, pu);
+                const int32_t *ps = sw + (size_t)j * (phi + 1);
+                int32_t lim = lu < sl[j] ? lu : sl[j];
+                int32_t first = 0;
+                for (int32_t t = 1; t <= lim; ++t)
+                    if (ps[t] == pu[t]) { first = t; break; }
+                if (first) {
+                    acc += oracle_strat_weight(Z, Zhat, sc[j], cu);
+                    meets += 1;
+                    work += (uint64_t)first;
+                } else {
+                    work += (uint64_t)lim;
+                }
+            }
+        }
+        wsum[i] = acc;
+        if (meets_opt) meets_opt[i] = meets;
+        if (work_opt) work_opt[i] = work;
+    }
+    free(sw); free(sl); free(sc); free(pu);
+}
+
+/* Estimates from the weighted sums: Algorithm 2's s~(s,u) = wsum 2^-40 / z,
+ * and the variant normalised by the N pairs actually formed,
+ * s~(s,u) * N / z, whose expectation is the meeting probability of two
+ * sqrt(c)-walks truncated at phi steps; both are 1 for u == s. */
+void oracle_strat_estimates(const uint64_t *wsum, const int32_t *vs, int64_t nv, int32_t s,
+                            double z, int64_t N, double *out, double *out_n)
+{
+    for (int64_t i = 0; i < nv; ++i) {
+        if (vs[i] == s) {
+            out[i] = 1.0;
+            out_n[i] = 1.0;
+            continue;
+        }
+        double x = ldexp((double)wsum[i], -40);
+        out[i] = x / z;
+        out_n[i] = (x / z) * ((double)N / z);
+    }
 }
