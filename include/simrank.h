@@ -53,6 +53,8 @@ extern "C" {
 
 #define SIMRANK_MODE_PLAIN 0     /* every walk generated step by step */
 #define SIMRANK_MODE_STITCHED 1  /* private head + tail read from the segment index */
+#define SIMRANK_MODE_STRATIFIED 2 /* Algorithms 1-2: fixed-length walk classes, shuffled,
+                                     meets weighted by Lemma 5; see the stratified calls */
 
 typedef struct simrank_graph simrank_graph;         /* opaque; device resident */
 typedef struct simrank_workspace simrank_workspace; /* opaque; per-call scratch */
@@ -65,9 +67,11 @@ typedef struct simrank_query {
     double eps;          /* absolute error target, c^(L+1) < eps < 1 */
     double delta;        /* failure probability, 0 < delta < 1 */
     uint64_t seed;       /* Philox key of the query's walks */
-    int32_t walk_cap;    /* L, the truncation length; 0 selects 64; at most 255 */
-    int32_t R_override;  /* walks per node; 0 selects the Hoeffding count */
-    int32_t mode;        /* SIMRANK_MODE_PLAIN or SIMRANK_MODE_STITCHED */
+    int32_t walk_cap;    /* L, the truncation length; 0 selects 64 (stratified mode:
+                            0 selects phi = floor(log_{1/sqrt c} n)); at most 255 */
+    int32_t R_override;  /* walks per node; 0 selects the Hoeffding count (stratified
+                            mode: the value of z; 0 selects Algorithm 2's z) */
+    int32_t mode;        /* SIMRANK_MODE_PLAIN, _STITCHED or _STRATIFIED */
     int32_t union_bound; /* 0: delta per node; 1: delta for all n nodes at once */
 } simrank_query;
 
@@ -96,6 +100,15 @@ typedef struct simrank_stats {
     uint32_t T;
     int32_t reserved;
 } simrank_stats;
+
+/* Length-stratified estimator constants (Algorithm 1 and Algorithm 2). */
+typedef struct simrank_strat_params {
+    double z;            /* ln(2n) / (2 (eps - 3/n)^2), the expected number of walks */
+    int32_t N;           /* walks per node: sum over l of ceil(z sqrt(c)^l (1 - sqrt(c))) */
+    int32_t phi;         /* walk length cap: floor(log_{1/sqrt c} n) */
+    int32_t shuffle_bits;/* the shuffle permutes [0, 2^bits), 2^bits >= N */
+    int32_t reserved;
+} simrank_strat_params;
 
 /* Stitched-walk index parameters. */
 typedef struct simrank_index_params {
@@ -180,6 +193,49 @@ int simrank_workspace_stats(simrank_workspace *ws, simrank_stats *st);
  * int32[count] (moves made).  For parity checks and inspection. */
 int simrank_walks(const simrank_graph *g, const simrank_query *q, const int32_t *v,
                   const uint32_t *j, int64_t count, int32_t *paths, int32_t *lens);
+
+/* ------------------------------------------- length-stratified estimator */
+/*
+ * Algorithm 1 draws, from every node v, N_l = ceil(Z_l) walks of exactly l
+ * steps for l = 0..phi, Z_l = z sqrt(c)^l (1 - sqrt(c)), and shuffles each
+ * node's N = sum N_l walks; Algorithm 2 pairs walk j of s with walk j of u and
+ * adds (Z_l1 Z_l2) / (N_l1 N_l2) / z to s~(s, u) for every pair that meets
+ * (Lemma 5), counted once per pair.  Here: the walks of v are generated class
+ * by class into slots 0..N-1 (slot r of class l walks l uniform steps keyed
+ * (v, r, t, 4); a walk that reaches a node without in-neighbours ends there),
+ * and the shuffle maps walk j to slot pi_v(j), a keyed permutation of [0, N)
+ * (a four-round Feistel network with round keys Philox(v, 0, 0, 5), cycle
+ * walked into [0, N)).  Weights are summed in fixed point, 2^40 per unit
+ * weight, each weight truncated: the sums are exact and order independent.
+ * Query fields used: s, c, eps (z, unless R_override > 0 gives z), walk_cap
+ * (0: phi from n), seed; delta is checked but not used by the method.
+ * EINVAL if eps <= 3/n, phi is outside [1, 255] or N >= 2^24.
+ */
+int simrank_derive_stratified(const simrank_query *q, int32_t n, simrank_strat_params *out);
+
+/* One stratified query, synchronous.  Host outputs, each n entries, any may be
+ * NULL: out = Algorithm 2's estimate (weighted meets / z), out_n = the estimate
+ * normalised by the N pairs actually formed (out * N / z), wsum = the weighted
+ * meet sums (2^40 = weight 1).  Entry s of out and out_n is 1, of wsum 0. */
+int simrank_single_source_stratified(const simrank_graph *g, const simrank_query *q, double *out,
+                                     double *out_n, uint64_t *wsum, simrank_stats *st_opt);
+
+/* Enqueues a stratified query on `stream` using the workspace (max_R >= N,
+ * max_L >= phi).  out_dev, out_n_dev: device double[n] or NULL; wsum_dev:
+ * device uint64[n], required.  The caller owns the buffers and keeps them
+ * until the stream has passed this call.  Stats via simrank_workspace_stats. */
+int simrank_stratified_async(const simrank_graph *g, const simrank_query *q,
+                             simrank_workspace *ws, double *out_dev, double *out_n_dev,
+                             uint64_t *wsum_dev, void *stream);
+
+/* The shuffle and walks of a stratified query for the listed (v[i], j[i]):
+ * slot host uint32[count] = pi_v(j), cls host int32[count] = the slot's length
+ * class, and (paths, lens may be NULL) paths host int32[count][phi+1] with the
+ * walk's nodes (-1 after its end), lens host int32[count] its moves.  For
+ * parity checks and inspection. */
+int simrank_stratified_walks(const simrank_graph *g, const simrank_query *q, const int32_t *v,
+                             const uint32_t *j, int64_t count, uint32_t *slot, int32_t *cls,
+                             int32_t *paths, int32_t *lens);
 
 /* ----------------------------------------------------------------- index */
 

@@ -77,6 +77,9 @@ static int check_queries(simrank_graph *const *graphs, int32_t ngraphs, const si
         const simrank_graph *g = graphs[q.graph];
         int rc = query_params(&q, g->n, &ps[i], &modes[i]);
         if (rc) return fail(rc, "query " + std::to_string(i) + ": " + simrank_last_error());
+        if (modes[i] == SIMRANK_MODE_STRATIFIED)
+            return fail(SIMRANK_EINVAL, "query " + std::to_string(i) +
+                                            ": stratified queries are not batched");
         if (q.s < 0 || q.s >= g->n)
             return fail(SIMRANK_EINVAL, "query " + std::to_string(i) + ": source out of range");
         if (modes[i] == SIMRANK_MODE_STITCHED && (!g->index || g->index->T != ps[i].T))
@@ -120,7 +123,7 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
                                              " device bytes, " + std::to_string(free_b) + " free"));
     if ((rc = device_alloc((void **)&p->arena, total, &p->bytes))) return bail(rc);
     if ((rc = device_alloc((void **)&p->desc_dev, sizeof(QueryDesc) * nq, &p->bytes))) return bail(rc);
-    if ((rc = device_alloc((void **)&p->units, 4 * (2 * ((size_t)nq + 1) + 2), &p->bytes)))
+    if ((rc = device_alloc((void **)&p->units, 4 * units_words(nq), &p->bytes)))
         return bail(rc);
     if ((rc = device_alloc((void **)&p->counters, 8 * 8, &p->bytes))) return bail(rc);
     QuerySet set;
@@ -152,13 +155,7 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
         const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
-        if (d.stitched) {
-            set.any_stitched = true;
-            set.units_bound_stitched += ub;
-        } else {
-            set.any_plain = true;
-            set.units_bound_plain += ub;
-        }
+        set.units_bound[d.kind] += ub;
     }
     e = hipMemcpy(p->desc_dev, p->desc.data(), sizeof(QueryDesc) * nq, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
@@ -321,6 +318,7 @@ extern "C" int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *v
     int rc = query_params(q, g->n, &p, &mode);
     if (rc) return rc;
     if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (mode == SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "the tuner takes plain queries");
     SRK_HIP(hipSetDevice(g->device));
     Workspace ws;
     uint32_t *cnt = nullptr;

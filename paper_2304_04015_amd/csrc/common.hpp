@@ -28,6 +28,10 @@ constexpr uint32_t NIL = 0xffffffffu;   // no successor / no segment
 constexpr int MAX_CAP = 255;            // walk cap limit (lengths fit a byte)
 constexpr int MAX_STITCH_CAP = 64;      // stitched walks: long walks span 64 steps
 constexpr int64_t MAX_R = 1 << 24;
+constexpr int64_t MAX_STRAT_N = (1 << 24) - 1;  // weighted sums stay below 2^64
+
+// Query kinds (one meet-kernel instance each).
+enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 
 // Meet-kernel tiling of the compacted source walks (see query.hip).
 constexpr int TILE_J = 1024;            // source walks per tile, at most
@@ -91,6 +95,20 @@ struct IndexView {
     int32_t seg_len, width;
 };
 
+// Length-stratified estimator: the first slot of each length class and
+// Lemma 5's per-class ratio Z_l / Zhat_l (computed on the host).
+struct StratTab {
+    uint32_t ccum[MAX_CAP + 2];   // ccum[l] = Zhat_0 + ... + Zhat_{l-1}; ccum[phi+1] = N
+    double a[MAX_CAP + 1];
+};
+
+struct StratParams {
+    double z = 0;                 // Algorithm 2's normaliser
+    int32_t N = 0;                // walks per node, sum of Zhat_l
+    int32_t phi = 0;              // walk length cap
+    int32_t bits = 2;             // shuffle domain 2^bits >= N
+};
+
 // One query as the device kernels see it (one entry per query of a launch).
 struct QueryDesc {
     const uint2 *nodes;
@@ -104,14 +122,21 @@ struct QueryDesc {
     uint32_t *swc;         // [R * L] packed positions
     uint32_t *tiles;       // [max tiles + 1]
     uint32_t *meta;        // [8]: R1, packed positions, tiles
-    uint32_t *cnt;         // [n] meet counts (caller's)
+    uint32_t *cnt;         // [n] meet counts (caller's; plain and stitched)
     double *out;           // [n] estimate or NULL
     uint32_t k0, k1;       // Philox key of the query's walks
     uint32_t T;            // continue threshold
     int32_t n, n_active, s, R, L;
     int32_t vb;            // nodes per work unit (<= MEET_VB)
     int32_t n_chunks;      // ceil(n_active / vb)
-    int32_t stitched;
+    int32_t kind;          // Kind
+    // stratified only (R = N walks per node, L = phi)
+    const StratTab *tab;
+    uint8_t *scls;         // [R] length class of walk (s, j)
+    unsigned long long *wsum;  // [n] weighted meet sums, 2^40 = weight 1 (caller's)
+    double *out_n;         // [n] estimate normalised by the N pairs, or NULL
+    double z;
+    int32_t sbits;
 };
 
 // A set of queries whose descriptors are already in device memory.
@@ -119,11 +144,14 @@ struct QuerySet {
     const QueryDesc *desc;        // device [nq]
     int32_t nq = 0;
     int32_t max_R = 0, max_n = 0;
-    bool any_plain = false, any_stitched = false;
-    int64_t units_bound_plain = 0, units_bound_stitched = 0;
-    uint32_t *units = nullptr;    // device [2 (nq + 1) + 2]: unit offsets (plain, stitched), cursors
+    int64_t units_bound[N_KINDS] = {0, 0, 0};   // work units of each kind's queries, at most
+    uint32_t *units = nullptr;    // device [units_words(nq)]: unit offsets per kind, then cursors
     unsigned long long *counters = nullptr;  // device [8]
 };
+
+// Words of a query set's unit table: N_KINDS lists of nq + 1 offsets, then
+// one cursor per kind.
+inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1) + N_KINDS; }
 
 // Per-query scratch.
 struct Workspace {
@@ -138,7 +166,11 @@ struct Workspace {
     uint32_t *meta = nullptr;      // [8]: R1, total nodes, n_tiles, ...
     unsigned long long *counters = nullptr;  // [8] stats
     QueryDesc *desc = nullptr;     // device [1]
-    uint32_t *units = nullptr;     // device [6]
+    uint32_t *units = nullptr;     // device [units_words(1)]
+    uint8_t *scls = nullptr;       // [max_R] stratified: class of walk (s, j)
+    StratTab *tab = nullptr;       // device table of the last stratified query
+    StratTab *tab_host = nullptr;  // its pinned host staging copy
+    hipEvent_t ev_tab = nullptr;   // after the copy of tab_host
     int32_t max_tiles = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;     // around the whole query
     hipEvent_t evm0 = nullptr, evm1 = nullptr;   // around the meet kernel
@@ -169,6 +201,8 @@ int scan_inclusive_max_u32(uint32_t *data, int64_t n, hipStream_t st);
 
 // Queries (query.hip).
 int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mode);
+// Stratified estimator: z, N, phi, shuffle width and (if tab) the class table.
+int strat_params(const simrank_query *q, int32_t n, StratParams *sp, StratTab *tab);
 int32_t max_tiles_for(int32_t R, int32_t L);
 int32_t default_unit_nodes(const Graph *g);
 IndexView index_view(const Graph *g);
@@ -181,6 +215,8 @@ void describe_query(const Graph *g, const simrank_query *q, const simrank_params
 int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hipEvent_t ev_meet1);
 int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
                   Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st);
+int enqueue_stratified(const Graph *g, const simrank_query *q, Workspace *ws, double *out_dev,
+                       double *out_n_dev, unsigned long long *wsum_dev, hipStream_t st);
 int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws);
 void workspace_release(Workspace *ws);
 

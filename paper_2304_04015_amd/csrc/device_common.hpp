@@ -67,9 +67,67 @@ struct Slot {
     bool busy;
     bool in_tail;    // stitched: the private head is complete
     uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position, segment, its length
+    uint32_t aux;    // stratified: class of walk (s, j) << 8 | class of walk (v, j)
 };
 
 constexpr uint32_t ITEM_CHUNK = 64;
+
+// ------------------------------------------------- walk shuffle (stratified)
+//
+// Node v's N fixed-length walks are generated class by class (slots
+// [ccum[l], ccum[l+1]) hold the walks of length l) and then shuffled: walk j
+// is the walk generated in slot pi_v(j).  pi_v is a four-round Feistel
+// network on [0, 2^bits), 2^bits >= N, restricted to [0, N) by cycle walking
+// (Black and Rogaway, CT-RSA 2002); its round keys are the four words of
+// Philox(v, 0, 0, DOM_SHUFFLE).
+
+// MurmurHash3's 32-bit finalizer (A. Appleby, public domain), the round function.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Bijection of [0, 2^bits): high part of bits - bits/2 bits, low part of
+// bits/2 bits; each round XORs one part with the round function of the other.
+__device__ __forceinline__ uint32_t feistel4(uint32_t x, uint32_t bits, uint4 k) {
+    const uint32_t a = bits >> 1, h = bits - a;
+    const uint32_t ma = (1u << a) - 1u, mh = (1u << h) - 1u;
+    uint32_t hi = x >> a, lo = x & ma;
+    hi ^= fmix32(lo ^ k.x) & mh;
+    lo ^= fmix32(hi ^ k.y) & ma;
+    hi ^= fmix32(lo ^ k.z) & mh;
+    lo ^= fmix32(hi ^ k.w) & ma;
+    return (hi << a) | lo;
+}
+
+// pi_v(j) for j < N.  The orbit of j under the bijection is a cycle through
+// j, so a value below N comes back within 2^bits applications; the loop is
+// bounded by that.
+__device__ __forceinline__ uint32_t shuffle_slot(uint32_t j, uint32_t N, uint32_t bits, uint4 k) {
+    uint32_t y = feistel4(j, bits, k);
+    for (uint32_t it = 1; y >= N && it < (1u << bits); ++it) y = feistel4(y, bits, k);
+    return y;
+}
+
+// Length class of slot r: the largest l <= phi with ccum[l] <= r.
+__device__ __forceinline__ uint32_t slot_class(uint32_t r, const uint32_t *ccum, int32_t phi) {
+    int32_t lo = 0, hi = phi + 1;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (ccum[mid] <= r) lo = mid; else hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+// Meet weight of classes (l1, l2) in units of 2^-40 (Lemma 5's ratio
+// Z_l1 Z_l2 / (Zhat_l1 Zhat_l2), truncated).
+__device__ __forceinline__ unsigned long long strat_weight(const double *a, uint32_t l1, uint32_t l2) {
+    return (unsigned long long)((a[l1] * a[l2]) * 1099511627776.0);
+}
 
 
 }  // namespace srk

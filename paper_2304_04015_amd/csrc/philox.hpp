@@ -67,8 +67,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
-// The draws of one walk, counters (v, j, t, 0) for t = 1, 2, ...: the same
-// values as philox4x32_10(v, j, t, 0, key), with the work that does not depend
+// The draws of one walk, counters (v, j, t, dom) for t = 1, 2, ...: the same
+// values as philox4x32_10(v, j, t, dom, key), with the work that does not depend
 // on t done once per walk.  In round 1 only the product with t changes from
 // step to step (and it grows by M1 per step); round 2 multiplies one word that
 // depends on (v, key) alone.  Only words 0 and 1 of the output are formed.
@@ -78,10 +78,11 @@ struct WalkDraws {
     uint64_t mt;       // M1 * t of the last draw
 };
 
-__device__ __forceinline__ WalkDraws walk_draws_begin(uint32_t v, uint32_t j, PhiloxKey key) {
+__device__ __forceinline__ WalkDraws walk_draws_begin(uint32_t v, uint32_t j, PhiloxKey key,
+                                                      uint32_t dom = 0u) {
     WalkDraws w;
     const uint64_t p0 = (uint64_t)philox_m0() * (uint64_t)v;          // round 1, word 0 (fixed)
-    const uint32_t c2 = (uint32_t)(p0 >> 32) ^ 0u ^ round_key1(key, 0); // round-1 word 2 (domain 0)
+    const uint32_t c2 = (uint32_t)(p0 >> 32) ^ dom ^ round_key1(key, 0); // round-1 word 2
     const uint64_t q1 = (uint64_t)philox_m1() * (uint64_t)c2;         // round 2's product of word 2
     w.j = j;
     w.a = (uint32_t)(q1 >> 32) ^ round_key0(key, 1);   // round-2 word 0 = a ^ (round-1 word 1)
@@ -121,7 +122,11 @@ __device__ __forceinline__ uint64_t pick64(uint32_t x, uint64_t k) {
     return hi + (lo >> 32);
 }
 
-// Counter domains.
-enum : uint32_t { DOM_WALK = 0u, DOM_SEGMENT = 1u, DOM_ENTRY = 2u, DOM_SUCC = 3u };
+// Counter domains: plain walk steps, pool segment steps, entry-slot picks,
+// successor picks, steps of the fixed-length walks of the length-stratified
+// estimator, round keys of a node's walk shuffle.
+enum : uint32_t {
+    DOM_WALK = 0u, DOM_SEGMENT = 1u, DOM_ENTRY = 2u, DOM_SUCC = 3u, DOM_STRAT = 4u, DOM_SHUFFLE = 5u
+};
 
 }  // namespace srk

@@ -33,22 +33,37 @@ __global__ void k_init(const QueryDesc *__restrict__ qd, unsigned long long *__r
         d.meta[threadIdx.x] = 0u;
         if (blockIdx.y == 0) counters[threadIdx.x] = 0ull;
     }
-    for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.cnt[v] = 0u;
+    if (d.kind == K_STRAT) {
+        for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.wsum[v] = 0ull;
+    } else {
+        for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.cnt[v] = 0u;
+    }
 }
 
 // s_hat(s, v) = cnt[v] / R; the pair (s, s) meets at step 0 for every j.
+// Stratified (Algorithm 2): s~(s, v) = wsum[v] 2^-40 / z, and the variant
+// normalised by the N pairs, s~(s, v) N / z; both are 1 at v = s.
 // grid (x over nodes, y = query)
 __global__ void k_estimate(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.y];
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
          v += (int64_t)gridDim.x * blockDim.x) {
+        if (d.kind == K_STRAT) {
+            const double x = (double)d.wsum[v] * 9.094947017729282379150390625e-13;   // 2^-40
+            const double e = x / d.z;
+            if (d.out) d.out[v] = (v == d.s) ? 1.0 : e;
+            if (d.out_n) d.out_n[v] = (v == d.s) ? 1.0 : e * ((double)d.R / d.z);
+            continue;
+        }
         if (v == d.s) d.cnt[v] = (uint32_t)d.R;
         if (d.out) d.out[v] = (v == d.s) ? 1.0 : (double)d.cnt[v] / (double)d.R;
     }
 }
 
 // ------------------------------------------------------------ source walks
-// Walk (s, j) for j < R: positions 1..len as o() values.  grid (x over j, y = query)
+// Walk (s, j) for j < R: positions 1..len as o() values.  Stratified: walk j
+// of s is the fixed-length walk generated in slot pi_s(j); its class goes to
+// scls[j].  grid (x over j, y = query)
 __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restrict__ qd,
                                                       unsigned long long *__restrict__ counters) {
     const QueryDesc &d = qd[blockIdx.y];
@@ -58,27 +73,42 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
         const PhiloxKey key{d.k0, d.k1};
         uint32_t *row = d.sw + (size_t)j * d.L;
         uint2 cur = d.nodes[d.s];
-        const int32_t head = d.stitched ? min(d.ix.seg_len, d.L) : d.L;
         int32_t len = 0;
-        for (int32_t t = 1; t <= head; ++t) {
-            const uint4 x = philox4x32_10((uint32_t)d.s, (uint32_t)j, (uint32_t)t, DOM_WALK, key);
-            if (x.x >= d.T || cur.y == 0) break;
-            cur = d.E[cur.x + pick32(x.y, cur.y)];
-            row[t - 1] = cur.x;
-            len = t;
-        }
-        if (d.stitched && len == d.ix.seg_len && len < d.L) {
-            const uint32_t y = d.ix.node_of[cur.x];
-            const uint32_t sigma = entry_slot(d.ix, key, (uint32_t)d.s, (uint32_t)j, y);
-            for (int32_t mm = 0; mm < d.ix.width && len < d.L; ++mm) {
-                const uint32_t sg = d.ix.chain[(size_t)sigma * d.ix.width + mm];
-                if (sg == NIL) break;
-                const int32_t sl = d.ix.seg_lens[sg];
-                for (int32_t u = 0; u < sl && len < d.L; ++u) {
-                    row[len] = d.ix.seg[(size_t)sg * d.ix.seg_len + u];
-                    ++len;
+        if (d.kind == K_STRAT) {
+            const uint4 fk = philox4x32_10((uint32_t)d.s, 0u, 0u, DOM_SHUFFLE, key);
+            const uint32_t r = shuffle_slot((uint32_t)j, (uint32_t)d.R, (uint32_t)d.sbits, fk);
+            const uint32_t cls = slot_class(r, d.tab->ccum, d.L);
+            for (int32_t t = 1; t <= (int32_t)cls; ++t) {
+                if (cur.y == 0) break;
+                const uint4 x = philox4x32_10((uint32_t)d.s, r, (uint32_t)t, DOM_STRAT, key);
+                cur = d.E[cur.x + pick32(x.y, cur.y)];
+                row[t - 1] = cur.x;
+                len = t;
+            }
+            d.scls[j] = (uint8_t)cls;
+        } else {
+            const bool stitched = d.kind == K_STITCHED;
+            const int32_t head = stitched ? min(d.ix.seg_len, d.L) : d.L;
+            for (int32_t t = 1; t <= head; ++t) {
+                const uint4 x = philox4x32_10((uint32_t)d.s, (uint32_t)j, (uint32_t)t, DOM_WALK, key);
+                if (x.x >= d.T || cur.y == 0) break;
+                cur = d.E[cur.x + pick32(x.y, cur.y)];
+                row[t - 1] = cur.x;
+                len = t;
+            }
+            if (stitched && len == d.ix.seg_len && len < d.L) {
+                const uint32_t y = d.ix.node_of[cur.x];
+                const uint32_t sigma = entry_slot(d.ix, key, (uint32_t)d.s, (uint32_t)j, y);
+                for (int32_t mm = 0; mm < d.ix.width && len < d.L; ++mm) {
+                    const uint32_t sg = d.ix.chain[(size_t)sigma * d.ix.width + mm];
+                    if (sg == NIL) break;
+                    const int32_t sl = d.ix.seg_lens[sg];
+                    for (int32_t u = 0; u < sl && len < d.L; ++u) {
+                        row[len] = d.ix.seg[(size_t)sg * d.ix.seg_len + u];
+                        ++len;
+                    }
+                    if (sl < d.ix.seg_len) break;
                 }
-                if (sl < d.ix.seg_len) break;
             }
         }
         d.slen[j] = (uint8_t)len;
@@ -141,27 +171,27 @@ __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ 
     }
 }
 
-// Work-unit offsets of the queries (one block): units[0 .. nq] for plain
-// queries, units[nq+1 .. 2nq+1] for stitched ones (a query of the other kind
-// has no units in a list), then the two unit cursors.
+// Work-unit offsets of the queries (one block): one list of nq + 1 offsets per
+// kind (a query of another kind has no units in a list), then one cursor per
+// kind.
 __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restrict__ qd, int32_t nq,
                                                        uint32_t *__restrict__ units) {
     const int32_t per = (nq + blockDim.x - 1) / blockDim.x;
     const int32_t q0 = min(nq, (int32_t)threadIdx.x * per), q1 = min(nq, q0 + per);
-    for (int list = 0; list < 2; ++list) {
+    for (int list = 0; list < N_KINDS; ++list) {
         uint32_t sum = 0;
         for (int32_t q = q0; q < q1; ++q)
-            if (qd[q].stitched == list) sum += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
+            if (qd[q].kind == list) sum += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
         uint32_t total;
         uint32_t run = block_excl_sum(sum, &total);
         uint32_t *u = units + list * (nq + 1);
         for (int32_t q = q0; q < q1; ++q) {
             u[q] = run;
-            if (qd[q].stitched == list) run += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
+            if (qd[q].kind == list) run += qd[q].meta[2] * (uint32_t)qd[q].n_chunks;
         }
         if (threadIdx.x == 0) {
             u[nq] = total;
-            units[2 * (nq + 1) + list] = 0u;
+            units[N_KINDS * (nq + 1) + list] = 0u;
         }
     }
 }
@@ -185,19 +215,32 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 // A step: one Philox draw, a multiply-high neighbour pick, one 8-byte gather
 // of E, one LDS compare.  Meets go to an LDS counter per node, flushed to the
 // global counts once per unit.
+//
+// KIND selects the walks: K_PLAIN (sqrt(c)-walks), K_STITCHED (private head,
+// then a tail read from the segment index) or K_STRAT (the stratified
+// estimator's fixed-length walks: walk j of v has the class of slot pi_v(j),
+// takes no stop draw, and a meet adds Lemma 5's weight of the two classes).
 
-template <bool STITCHED, int NS>
+template <int KIND, int NS>
 __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t *__restrict__ cursor,
                                                      unsigned long long *__restrict__ counters) {
+    constexpr bool STITCHED = KIND == K_STITCHED;
+    constexpr bool STRAT = KIND == K_STRAT;
     __shared__ uint32_t s_nodes[TILE_NODES];
     __shared__ uint32_t s_j[TILE_J];
     __shared__ uint16_t s_off[TILE_J + 1];
-    __shared__ uint32_t s_cnt[MEET_VB];
+    __shared__ uint32_t s_cnt[STRAT ? 1 : MEET_VB];
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
     __shared__ uint32_t s_unit, s_item;
+    // stratified: classes of the tile's source walks, class starts, the
+    // shuffle keys of the unit's nodes, weighted sums
+    __shared__ uint8_t s_cls[STRAT ? TILE_J : 1];
+    __shared__ uint32_t s_ccum[STRAT ? MAX_CAP + 2 : 1];
+    __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
+    __shared__ unsigned long long s_w[STRAT ? MEET_VB : 1];
 
     const int lane = threadIdx.x & 63;
     const uint32_t n_units = ustart[nq];
@@ -226,27 +269,35 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
         const PhiloxKey key{uni(d.k0), uni(d.k1)};
         const uint32_t T = uni(d.T);
         const int32_t src = (int32_t)uni((uint32_t)d.s);
+        const uint32_t NN = uni((uint32_t)d.R), sbits = uni((uint32_t)d.sbits);
+        const int32_t phi = (int32_t)uni((uint32_t)d.L);
         if ((uint32_t)q != cur_q || tile != cur_tile) {
             const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
             const uint32_t nb = d.joff[k0], ne = d.joff[k1];
             K = k1 - k0;
             for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
-                s_j[i] = d.jj[k0 + i];
+                const uint32_t jw = d.jj[k0 + i];
+                s_j[i] = jw;
                 s_off[i] = (uint16_t)(d.joff[k0 + i] - nb);
+                if (STRAT) s_cls[i] = d.scls[jw];
             }
             if (threadIdx.x == 0) s_off[K] = (uint16_t)(ne - nb);
             for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.swc[nb + i];
+            if (STRAT)
+                for (uint32_t i = threadIdx.x; i < (uint32_t)phi + 2; i += blockDim.x)
+                    s_ccum[i] = d.tab->ccum[i];
             cur_q = (uint32_t)q;
             cur_tile = tile;
         }
         const int32_t vbase = (int32_t)chunk * vb;
         const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
         for (uint32_t i = threadIdx.x; i < MEET_VB; i += blockDim.x) {
-            s_cnt[i] = 0u;
+            if (STRAT) s_w[i] = 0ull; else s_cnt[i] = 0u;
             if (i < nv) {
                 const uint32_t id = (uint32_t)d.active[vbase + (int32_t)i];
                 s_vid[i] = id;
                 s_vrow[i] = d.nodes[id];
+                if (STRAT) s_fk[i] = philox4x32_10(id, 0u, 0u, DOM_SHUFFLE, key);
             }
         }
         if (threadIdx.x == 0) s_item = 0u;
@@ -266,7 +317,9 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
         }
 
         for (;;) {
-            // ---- refill idle slots from the block's cursor
+            // ---- refill idle slots from the block's cursor; a lane whose item
+            // has nothing to walk (the source's own pair, or a stratified walk
+            // of length 0) takes the next item
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 uint64_t need = __ballot(!sl[qq].busy);
@@ -290,6 +343,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
                     const uint32_t take = avail < want ? avail : want;
                     const uint32_t rank = lane_rank(need);
                     const bool mine = ((need >> lane) & 1ull) && rank < take;
+                    bool filled = false;
                     if (mine) {
                         uint32_t k = ck + rank, vl = cvl;
                         while (k >= K) {
@@ -299,19 +353,30 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
                         const uint32_t id = s_vid[vl];
                         if ((int32_t)id != src) {   // the source's own pairs are not walked
                             const uint32_t base = s_off[k];
-                            const uint32_t len = (uint32_t)s_off[k + 1] - base;
-                            const uint2 row = s_vrow[vl];
-                            sl[qq].pos = base | (len << 16) | (vl << 24);
-                            sl[qq].rng = walk_draws_begin(id, s_j[k], key);
-                            sl[qq].t = 0;
-                            sl[qq].o = row.x;
-                            sl[qq].d = row.y;
-                            sl[qq].busy = true;
-                            sl[qq].in_tail = false;
-                            ++st_pairs;
+                            uint32_t len = (uint32_t)s_off[k + 1] - base;
+                            if (STRAT) {
+                                const uint32_t r = shuffle_slot(s_j[k], NN, sbits, s_fk[vl]);
+                                const uint32_t cv = slot_class(r, s_ccum, phi);
+                                len = min(len, cv);
+                                sl[qq].aux = ((uint32_t)s_cls[k] << 8) | cv;
+                                sl[qq].rng = walk_draws_begin(id, r, key, DOM_STRAT);
+                            } else {
+                                sl[qq].rng = walk_draws_begin(id, s_j[k], key);
+                            }
+                            if (len > 0) {
+                                const uint2 row = s_vrow[vl];
+                                sl[qq].pos = base | (len << 16) | (vl << 24);
+                                sl[qq].t = 0;
+                                sl[qq].o = row.x;
+                                sl[qq].d = row.y;
+                                sl[qq].busy = true;
+                                sl[qq].in_tail = false;
+                                filled = true;
+                                ++st_pairs;
+                            }
                         }
                     }
-                    need &= ~__ballot(mine);
+                    need &= ~__ballot(filled);
                     ci += take;
                     ck += take;
                     while (ck >= K && K > 0) {
@@ -323,8 +388,8 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
             bool any = false;
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) any |= sl[qq].busy;
-            // A refill round can hand out only the source's own pairs, which are
-            // skipped: a wave leaves only once the block's cursor is drained.
+            // A refill round can hand out only pairs with nothing to walk: a
+            // wave leaves only once the block's cursor is drained.
             if (__ballot(any) == 0ull) {
                 if (drained) break;
                 continue;
@@ -341,7 +406,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
                     ++sl[qq].t;
                     const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
-                    if (x.x >= T) {
+                    if (!STRAT && x.x >= T) {
                         sl[qq].busy = false;
                     } else {
                         go[qq] = true;
@@ -362,7 +427,10 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
                 w.d = e[qq].y;
                 const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
                 if (w.o == s_nodes[base + w.t - 1]) {
-                    atomicAdd(&s_cnt[w.pos >> 24], 1u);
+                    if (STRAT)
+                        atomicAdd(&s_w[w.pos >> 24], strat_weight(d.tab->a, w.aux >> 8, w.aux & 0xffu));
+                    else
+                        atomicAdd(&s_cnt[w.pos >> 24], 1u);
                     ++st_meets;
                     w.busy = false;
                 } else if (w.t == len || w.d == 0u) {
@@ -415,8 +483,13 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
-            const uint32_t c = s_cnt[i];
-            if (c) atomicAdd(&d.cnt[s_vid[i]], c);
+            if (STRAT) {
+                const unsigned long long c = s_w[i];
+                if (c) atomicAdd(&d.wsum[s_vid[i]], c);
+            } else {
+                const uint32_t c = s_cnt[i];
+                if (c) atomicAdd(&d.cnt[s_vid[i]], c);
+            }
         }
     }
 
@@ -487,6 +560,50 @@ __global__ __launch_bounds__(256) void k_walks(WalkArgs a) {
     a.lens[i] = len;
 }
 
+// Stratified: walk j of v after the shuffle (the fixed-length walk of slot
+// pi_v(j)); paths hold node ids, row[0] = v.
+struct StratWalkArgs {
+    const uint2 *nodes;
+    const uint2 *E;
+    const uint32_t *node_of;
+    const StratTab *tab;
+    const int32_t *vs;
+    const uint32_t *js;
+    int64_t count;
+    int32_t *paths;   // [count][phi+1] or NULL
+    int32_t *lens;    // or NULL
+    uint32_t *slots;  // or NULL
+    int32_t *classes; // or NULL
+    PhiloxKey key;
+    uint32_t N, bits;
+    int32_t phi;
+};
+
+__global__ __launch_bounds__(256) void k_walks_strat(StratWalkArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    const uint32_t v = (uint32_t)a.vs[i], j = a.js[i];
+    const uint4 fk = philox4x32_10(v, 0u, 0u, DOM_SHUFFLE, a.key);
+    const uint32_t r = shuffle_slot(j, a.N, a.bits, fk);
+    const uint32_t cls = slot_class(r, a.tab->ccum, a.phi);
+    if (a.slots) a.slots[i] = r;
+    if (a.classes) a.classes[i] = (int32_t)cls;
+    if (!a.paths) return;
+    int32_t *row = a.paths + (size_t)i * (a.phi + 1);
+    row[0] = (int32_t)v;
+    uint2 cur = a.nodes[v];
+    int32_t len = 0;
+    for (int32_t t = 1; t <= (int32_t)cls; ++t) {
+        if (cur.y == 0) break;
+        const uint4 x = philox4x32_10(v, r, (uint32_t)t, DOM_STRAT, a.key);
+        cur = a.E[cur.x + pick32(x.y, cur.y)];
+        row[t] = (int32_t)a.node_of[cur.x];
+        len = t;
+    }
+    for (int32_t t = len + 1; t <= a.phi; ++t) row[t] = -1;
+    a.lens[i] = len;
+}
+
 #ifndef SRK_MEET_SLOTS
 #define SRK_MEET_SLOTS 2
 #endif
@@ -494,19 +611,32 @@ __global__ __launch_bounds__(256) void k_walks(WalkArgs a) {
 #define SRK_MEET_SLOTS_STITCHED 1
 #endif
 
+#ifndef SRK_MEET_SLOTS_STRAT
+#define SRK_MEET_SLOTS_STRAT 2
+#endif
+
+// Resident blocks of a meet-kernel instance on the whole device.
+template <int KIND, int NS>
 int meet_grid_blocks() {
     static int blocks = 0;
     if (blocks == 0) {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<false, SRK_MEET_SLOTS>,
-                                                           MEET_BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<KIND, NS>, MEET_BLOCK, 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
         blocks = cus * per;
     }
     return blocks;
+}
+
+template <int KIND, int NS>
+void launch_meet(const QuerySet &qs, hipStream_t st) {
+    const int blocks = (int)std::min<int64_t>(qs.units_bound[KIND], meet_grid_blocks<KIND, NS>());
+    const uint32_t *ustart = qs.units + (size_t)KIND * (qs.nq + 1);
+    uint32_t *cursor = qs.units + (size_t)N_KINDS * (qs.nq + 1) + KIND;
+    k_meet<KIND, NS><<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, ustart, cursor, qs.counters);
 }
 
 }  // namespace
@@ -558,7 +688,8 @@ void describe_query(const Graph *g, const simrank_query *q, const simrank_params
     d->L = p.L;
     d->vb = vb;
     d->n_chunks = (g->n_active + vb - 1) / vb;
-    d->stitched = mode == SIMRANK_MODE_STITCHED ? 1 : 0;
+    d->kind = mode == SIMRANK_MODE_STITCHED ? K_STITCHED
+              : mode == SIMRANK_MODE_STRATIFIED ? K_STRAT : K_PLAIN;
 }
 
 int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hipEvent_t ev_meet1) {
@@ -570,18 +701,9 @@ int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hi
     k_compact<<<nq, 1024, 0, st>>>(qs.desc);
     k_unit_offsets<<<1, 1024, 0, st>>>(qs.desc, qs.nq, qs.units);
     if (ev_meet0) SRK_HIP(hipEventRecord(ev_meet0, st));
-    const uint32_t *u_plain = qs.units, *u_st = qs.units + (qs.nq + 1);
-    uint32_t *c_plain = qs.units + 2 * (qs.nq + 1), *c_st = c_plain + 1;
-    if (qs.any_plain && qs.units_bound_plain > 0) {
-        const int blocks = (int)std::min<int64_t>(qs.units_bound_plain, meet_grid_blocks());
-        k_meet<false, SRK_MEET_SLOTS>
-            <<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, u_plain, c_plain, qs.counters);
-    }
-    if (qs.any_stitched && qs.units_bound_stitched > 0) {
-        const int blocks = (int)std::min<int64_t>(qs.units_bound_stitched, meet_grid_blocks());
-        k_meet<true, SRK_MEET_SLOTS_STITCHED>
-            <<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, u_st, c_st, qs.counters);
-    }
+    if (qs.units_bound[K_PLAIN] > 0) launch_meet<K_PLAIN, SRK_MEET_SLOTS>(qs, st);
+    if (qs.units_bound[K_STITCHED] > 0) launch_meet<K_STITCHED, SRK_MEET_SLOTS_STITCHED>(qs, st);
+    if (qs.units_bound[K_STRAT] > 0) launch_meet<K_STRAT, SRK_MEET_SLOTS_STRAT>(qs, st);
     if (ev_meet1) SRK_HIP(hipEventRecord(ev_meet1, st));
     k_estimate<<<dim3(gx_n, nq), 256, 0, st>>>(qs.desc);
     SRK_HIP(hipGetLastError());
@@ -595,13 +717,25 @@ int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mo
     if (!(q->c > 0.0 && q->c < 1.0)) return fail(SIMRANK_EINVAL, "c must lie in (0, 1)");
     if (!(q->delta > 0.0 && q->delta < 1.0)) return fail(SIMRANK_EINVAL, "delta must lie in (0, 1)");
     if (!(q->eps > 0.0 && q->eps < 1.0)) return fail(SIMRANK_EINVAL, "eps must lie in (0, 1)");
-    if (q->mode != SIMRANK_MODE_PLAIN && q->mode != SIMRANK_MODE_STITCHED)
+    if (q->mode != SIMRANK_MODE_PLAIN && q->mode != SIMRANK_MODE_STITCHED &&
+        q->mode != SIMRANK_MODE_STRATIFIED)
         return fail(SIMRANK_EINVAL, "unknown mode");
+    if (q->R_override < 0) return fail(SIMRANK_EINVAL, "R_override must be >= 0");
+    if (q->mode == SIMRANK_MODE_STRATIFIED) {
+        StratParams sp;
+        const int rc = strat_params(q, n, &sp, nullptr);
+        if (rc) return rc;
+        out->R = sp.N;
+        out->L = sp.phi;
+        out->T = 0;
+        out->reserved = 0;
+        if (mode) *mode = q->mode;
+        return SIMRANK_OK;
+    }
     const int32_t L = q->walk_cap == 0 ? 64 : q->walk_cap;
     if (L < 1 || L > MAX_CAP) return fail(SIMRANK_EINVAL, "walk_cap must lie in [1, 255]");
     if (q->mode == SIMRANK_MODE_STITCHED && L > MAX_STITCH_CAP)
         return fail(SIMRANK_EINVAL, "stitched walks are capped at 64 steps");
-    if (q->R_override < 0) return fail(SIMRANK_EINVAL, "R_override must be >= 0");
     int64_t R;
     if (q->R_override > 0) {
         R = q->R_override;
@@ -624,6 +758,55 @@ int query_params(const simrank_query *q, int32_t n, simrank_params *out, int *mo
     return SIMRANK_OK;
 }
 
+// Algorithm 1 caps walks at phi = log_{1/sqrt c} n steps (floor) and draws
+// N_l = ceil(Z_l) walks of length l from every node, Z_l = z sqrt(c)^l
+// (1 - sqrt(c)), with Algorithm 2's z = ln(2n) / (2 (eps - 3/n)^2).  A query
+// may fix phi (walk_cap > 0, the longer cap of the error-threshold extension)
+// and z (R_override > 0).  sqrt(c)^l is formed by repeated multiplication.
+int strat_params(const simrank_query *q, int32_t n, StratParams *sp, StratTab *tab) {
+    if (n < 1) return fail(SIMRANK_EINVAL, "n must be >= 1");
+    double z;
+    if (q->R_override > 0) {
+        z = (double)q->R_override;
+    } else {
+        const double gap = q->eps - 3.0 / (double)n;
+        if (!(gap > 0.0)) return fail(SIMRANK_EINVAL, "stratified estimator needs eps > 3/n");
+        z = log(2.0 * (double)n) / (2.0 * gap * gap);
+    }
+    const double r = sqrt(q->c);
+    int32_t phi;
+    if (q->walk_cap > 0) {
+        phi = q->walk_cap;
+    } else {
+        const double f = floor(log((double)n) / log(1.0 / r));
+        if (!(f >= 0.0 && f <= (double)MAX_CAP)) return fail(SIMRANK_EINVAL, "phi beyond 255");
+        phi = (int32_t)f;
+    }
+    if (phi < 1 || phi > MAX_CAP) return fail(SIMRANK_EINVAL, "walk cap phi must lie in [1, 255]");
+    double g = 1.0;
+    double N = 0.0;
+    for (int32_t l = 0; l <= phi; ++l) {
+        const double Zl = (z * g) * (1.0 - r);
+        const double Zh = ceil(Zl);
+        if (tab) {
+            tab->ccum[l] = (uint32_t)N;
+            tab->a[l] = Zl / Zh;
+        }
+        N += Zh;
+        if (!(N <= (double)MAX_STRAT_N))
+            return fail(SIMRANK_EINVAL, "stratified estimator needs fewer than 2^24 walks per node");
+        g = g * r;
+    }
+    if (tab) tab->ccum[phi + 1] = (uint32_t)N;
+    sp->z = z;
+    sp->N = (int32_t)N;
+    sp->phi = phi;
+    int32_t bits = 2;
+    while ((1 << bits) < sp->N) ++bits;
+    sp->bits = bits;
+    return SIMRANK_OK;
+}
+
 int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws) {
     if (max_R < 1 || max_R > MAX_R) return fail(SIMRANK_EINVAL, "max_R must lie in [1, 2^24]");
     if (max_L < 1 || max_L > MAX_CAP) return fail(SIMRANK_EINVAL, "max_L must lie in [1, 255]");
@@ -642,7 +825,11 @@ int workspace_init(const Graph *g, int32_t max_R, int32_t max_L, Workspace *ws) 
     if ((rc = device_alloc((void **)&ws->meta, 4 * 8, nullptr))) return rc;
     if ((rc = device_alloc((void **)&ws->counters, 8 * 8, nullptr))) return rc;
     if ((rc = device_alloc((void **)&ws->desc, sizeof(QueryDesc), nullptr))) return rc;
-    if ((rc = device_alloc((void **)&ws->units, 4 * 8, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->units, 4 * units_words(1), nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->scls, (size_t)max_R, nullptr))) return rc;
+    if ((rc = device_alloc((void **)&ws->tab, sizeof(StratTab), nullptr))) return rc;
+    SRK_HIP(hipHostMalloc((void **)&ws->tab_host, sizeof(StratTab), hipHostMallocDefault));
+    SRK_HIP(hipEventCreate(&ws->ev_tab));
     SRK_HIP(hipEventCreate(&ws->ev0));
     SRK_HIP(hipEventCreate(&ws->ev1));
     SRK_HIP(hipEventCreate(&ws->evm0));
@@ -662,6 +849,10 @@ void workspace_release(Workspace *ws) {
     device_free(ws->counters);
     device_free(ws->desc);
     device_free(ws->units);
+    device_free(ws->scls);
+    device_free(ws->tab);
+    if (ws->tab_host) (void)hipHostFree(ws->tab_host);
+    if (ws->ev_tab) (void)hipEventDestroy(ws->ev_tab);
     if (ws->ev0) (void)hipEventDestroy(ws->ev0);
     if (ws->ev1) (void)hipEventDestroy(ws->ev1);
     if (ws->evm0) (void)hipEventDestroy(ws->evm0);
@@ -669,41 +860,18 @@ void workspace_release(Workspace *ws) {
     *ws = Workspace{};
 }
 
-int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
-                  Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st) {
-    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
-    if (p.R > ws->max_R || p.L > ws->max_L)
-        return fail(SIMRANK_EINVAL, "query needs R or L beyond the workspace's size");
-    if (!counts_dev) return fail(SIMRANK_EINVAL, "counts buffer is NULL");
-    const bool stitched = mode == SIMRANK_MODE_STITCHED;
-    if (stitched && !g->index) return fail(SIMRANK_ESTATE, "stitched query without an index");
-    if (stitched && g->index->T != p.T)
-        return fail(SIMRANK_EINVAL, "stitched query's c differs from the index's c");
-    const int32_t vb = default_unit_nodes(g);
-    QueryDesc d;
-    describe_query(g, q, p, mode, vb, &d);
+// One query on a workspace: its descriptor, then the whole launch sequence.
+static int launch_single(const Graph *g, Workspace *ws, const QueryDesc &d, hipStream_t st) {
     // the meet kernel counts work units (tile x node chunk) in 32 bits
-    const int64_t units_bound = (int64_t)max_tiles_for(p.R, p.L) * d.n_chunks;
+    const int64_t units_bound = (int64_t)max_tiles_for(d.R, d.L) * d.n_chunks;
     if (units_bound >= (int64_t)0xffffffffu - (1 << 20))
         return fail(SIMRANK_EINVAL, "R * L * n too large for one launch");
-    d.sw = ws->sw;
-    d.slen = ws->slen;
-    d.jj = ws->jj;
-    d.joff = ws->joff;
-    d.swc = ws->swc;
-    d.tiles = ws->tiles;
-    d.meta = ws->meta;
-    d.cnt = counts_dev;
-    d.out = out_dev;
     QuerySet qs;
     qs.desc = ws->desc;
     qs.nq = 1;
-    qs.max_R = p.R;
+    qs.max_R = d.R;
     qs.max_n = g->n;
-    qs.any_plain = !stitched;
-    qs.any_stitched = stitched;
-    qs.units_bound_plain = stitched ? 0 : units_bound;
-    qs.units_bound_stitched = stitched ? units_bound : 0;
+    qs.units_bound[d.kind] = units_bound;
     qs.units = ws->units;
     qs.counters = ws->counters;
     SRK_HIP(hipEventRecord(ws->ev0, st));
@@ -712,10 +880,71 @@ int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &
     if (rc) return rc;
     SRK_HIP(hipEventRecord(ws->ev1, st));
     ws->last_stream = st;
-    ws->last_params = p;
+    ws->last_params.R = d.R;
+    ws->last_params.L = d.L;
+    ws->last_params.T = d.T;
+    ws->last_params.reserved = 0;
     ws->last_n = g->n;
     ws->pending = true;
     return SIMRANK_OK;
+}
+
+static void attach_buffers(Workspace *ws, QueryDesc *d) {
+    d->sw = ws->sw;
+    d->slen = ws->slen;
+    d->jj = ws->jj;
+    d->joff = ws->joff;
+    d->swc = ws->swc;
+    d->tiles = ws->tiles;
+    d->meta = ws->meta;
+    d->scls = ws->scls;
+    d->tab = ws->tab;
+}
+
+int enqueue_query(const Graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                  Workspace *ws, double *out_dev, uint32_t *counts_dev, hipStream_t st) {
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (mode == SIMRANK_MODE_STRATIFIED)
+        return fail(SIMRANK_EINVAL, "stratified queries return weighted sums: use the stratified calls");
+    if (p.R > ws->max_R || p.L > ws->max_L)
+        return fail(SIMRANK_EINVAL, "query needs R or L beyond the workspace's size");
+    if (!counts_dev) return fail(SIMRANK_EINVAL, "counts buffer is NULL");
+    const bool stitched = mode == SIMRANK_MODE_STITCHED;
+    if (stitched && !g->index) return fail(SIMRANK_ESTATE, "stitched query without an index");
+    if (stitched && g->index->T != p.T)
+        return fail(SIMRANK_EINVAL, "stitched query's c differs from the index's c");
+    QueryDesc d;
+    describe_query(g, q, p, mode, default_unit_nodes(g), &d);
+    attach_buffers(ws, &d);
+    d.cnt = counts_dev;
+    d.out = out_dev;
+    return launch_single(g, ws, d, st);
+}
+
+int enqueue_stratified(const Graph *g, const simrank_query *q, Workspace *ws, double *out_dev,
+                       double *out_n_dev, unsigned long long *wsum_dev, hipStream_t st) {
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (q->mode != SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "not a stratified query");
+    if (!wsum_dev) return fail(SIMRANK_EINVAL, "weighted-sum buffer is NULL");
+    // the staging copy of the class table may still be read by the previous call
+    if (ws->pending) SRK_HIP(hipEventSynchronize(ws->ev_tab));
+    StratParams sp;
+    int rc = strat_params(q, g->n, &sp, ws->tab_host);
+    if (rc) return rc;
+    if (sp.N > ws->max_R || sp.phi > ws->max_L)
+        return fail(SIMRANK_EINVAL, "query needs N or phi beyond the workspace's size");
+    simrank_params p{sp.N, sp.phi, 0u, 0};
+    QueryDesc d;
+    describe_query(g, q, p, SIMRANK_MODE_STRATIFIED, default_unit_nodes(g), &d);
+    attach_buffers(ws, &d);
+    d.wsum = wsum_dev;
+    d.out = out_dev;
+    d.out_n = out_n_dev;
+    d.z = sp.z;
+    d.sbits = sp.bits;
+    SRK_HIP(hipMemcpyAsync(ws->tab, ws->tab_host, sizeof(StratTab), hipMemcpyHostToDevice, st));
+    SRK_HIP(hipEventRecord(ws->ev_tab, st));
+    return launch_single(g, ws, d, st);
 }
 
 static int read_stats(Workspace *ws, simrank_stats *st) {
@@ -816,6 +1045,8 @@ extern "C" int simrank_single_source_ex(const simrank_graph *g, const simrank_qu
     int rc = query_params(q, g->n, &p, &mode);
     if (rc) return rc;
     if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (mode == SIMRANK_MODE_STRATIFIED)
+        return fail(SIMRANK_EINVAL, "stratified queries: use simrank_single_source_stratified");
     if (mode == SIMRANK_MODE_STITCHED && !g->index)
         return fail(SIMRANK_ESTATE, "stitched query without an index");
     if (mode == SIMRANK_MODE_STITCHED && g->index->T != p.T)
@@ -870,6 +1101,8 @@ extern "C" int simrank_walks(const simrank_graph *g, const simrank_query *q, con
     int mode;
     int rc = query_params(q, g->n, &p, &mode);
     if (rc) return rc;
+    if (mode == SIMRANK_MODE_STRATIFIED)
+        return fail(SIMRANK_EINVAL, "stratified walks: use simrank_stratified_walks");
     for (int64_t i = 0; i < count; ++i)
         if (v[i] < 0 || v[i] >= g->n) return fail(SIMRANK_EINVAL, "walk start out of range");
     const bool stitched = mode == SIMRANK_MODE_STITCHED;
@@ -907,6 +1140,135 @@ extern "C" int simrank_walks(const simrank_graph *g, const simrank_query *q, con
     }
     device_free(dv);
     device_free(dj);
+    device_free(dpaths);
+    device_free(dlens);
+    return rc;
+}
+
+// ------------------------------------------------ length-stratified estimator
+
+extern "C" int simrank_derive_stratified(const simrank_query *q, int32_t n,
+                                         simrank_strat_params *out) {
+    clear_error();
+    if (!q || !out) return fail(SIMRANK_EINVAL, "NULL argument");
+    simrank_query qq = *q;
+    qq.mode = SIMRANK_MODE_STRATIFIED;
+    simrank_params p;
+    int rc = query_params(&qq, n, &p, nullptr);
+    if (rc) return rc;
+    StratParams sp;
+    rc = strat_params(&qq, n, &sp, nullptr);
+    if (rc) return rc;
+    *out = simrank_strat_params{sp.z, sp.N, sp.phi, sp.bits, 0};
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_stratified_async(const simrank_graph *g, const simrank_query *q,
+                                        simrank_workspace *ws, double *out_dev, double *out_n_dev,
+                                        uint64_t *wsum_dev, void *stream) {
+    clear_error();
+    if (!g || !q || !ws) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (ws->g != g) return fail(SIMRANK_EINVAL, "workspace belongs to another graph");
+    simrank_params p;
+    int rc = query_params(q, g->n, &p, nullptr);
+    if (rc) return rc;
+    SRK_HIP(hipSetDevice(g->device));
+    return enqueue_stratified(g, q, ws, out_dev, out_n_dev, (unsigned long long *)wsum_dev,
+                              (hipStream_t)stream);
+}
+
+extern "C" int simrank_single_source_stratified(const simrank_graph *g, const simrank_query *q,
+                                                double *out, double *out_n, uint64_t *wsum,
+                                                simrank_stats *st_opt) {
+    clear_error();
+    if (!g || !q) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (q->mode != SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "not a stratified query");
+    simrank_params p;
+    int rc = query_params(q, g->n, &p, nullptr);
+    if (rc) return rc;
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    SRK_HIP(hipSetDevice(g->device));
+    Workspace ws;
+    double *out_dev = nullptr, *out_n_dev = nullptr;
+    unsigned long long *w_dev = nullptr;
+    const size_t n = (size_t)g->n;
+    rc = workspace_init(g, p.R, p.L, &ws);
+    if (!rc) rc = device_alloc((void **)&w_dev, 8 * n, nullptr);
+    if (!rc && out) rc = device_alloc((void **)&out_dev, 8 * n, nullptr);
+    if (!rc && out_n) rc = device_alloc((void **)&out_n_dev, 8 * n, nullptr);
+    if (!rc) rc = enqueue_stratified(g, q, &ws, out_dev, out_n_dev, w_dev, g->stream);
+    if (!rc) rc = read_stats(&ws, st_opt);
+    hipError_t e = hipSuccess;
+    if (!rc && out) e = hipMemcpy(out, out_dev, 8 * n, hipMemcpyDeviceToHost);
+    if (!rc && e == hipSuccess && out_n) e = hipMemcpy(out_n, out_n_dev, 8 * n, hipMemcpyDeviceToHost);
+    if (!rc && e == hipSuccess && wsum) e = hipMemcpy(wsum, w_dev, 8 * n, hipMemcpyDeviceToHost);
+    if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    device_free(out_dev);
+    device_free(out_n_dev);
+    device_free(w_dev);
+    workspace_release(&ws);
+    return rc;
+}
+
+extern "C" int simrank_stratified_walks(const simrank_graph *g, const simrank_query *q,
+                                        const int32_t *v, const uint32_t *j, int64_t count,
+                                        uint32_t *slot, int32_t *cls, int32_t *paths,
+                                        int32_t *lens) {
+    clear_error();
+    if (!g || !q || (count > 0 && (!v || !j || !slot || !cls)))
+        return fail(SIMRANK_EINVAL, "NULL argument");
+    if ((paths == nullptr) != (lens == nullptr))
+        return fail(SIMRANK_EINVAL, "paths and lens go together");
+    if (count < 0) return fail(SIMRANK_EINVAL, "count < 0");
+    if (q->mode != SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "not a stratified query");
+    simrank_params p;
+    int rc = query_params(q, g->n, &p, nullptr);
+    if (rc) return rc;
+    StratTab tab;
+    StratParams sp;
+    rc = strat_params(q, g->n, &sp, &tab);
+    if (rc) return rc;
+    for (int64_t i = 0; i < count; ++i) {
+        if (v[i] < 0 || v[i] >= g->n) return fail(SIMRANK_EINVAL, "walk start out of range");
+        if (j[i] >= (uint32_t)sp.N) return fail(SIMRANK_EINVAL, "walk index beyond N");
+    }
+    if (count == 0) return SIMRANK_OK;
+    SRK_HIP(hipSetDevice(g->device));
+    int32_t *dv = nullptr, *dpaths = nullptr, *dlens = nullptr, *dcls = nullptr;
+    uint32_t *dj = nullptr, *dslot = nullptr;
+    StratTab *dtab = nullptr;
+    const size_t rowb = 4 * (size_t)(sp.phi + 1), c4 = 4 * (size_t)count;
+    rc = device_alloc((void **)&dv, c4, nullptr);
+    if (!rc) rc = device_alloc((void **)&dj, c4, nullptr);
+    if (!rc) rc = device_alloc((void **)&dslot, c4, nullptr);
+    if (!rc) rc = device_alloc((void **)&dcls, c4, nullptr);
+    if (!rc) rc = device_alloc((void **)&dtab, sizeof(StratTab), nullptr);
+    if (!rc && paths) rc = device_alloc((void **)&dpaths, rowb * (size_t)count, nullptr);
+    if (!rc && paths) rc = device_alloc((void **)&dlens, c4, nullptr);
+    hipStream_t st = g->stream;
+    if (!rc) {
+        hipError_t e = hipMemcpy(dv, v, c4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dj, j, c4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dtab, &tab, sizeof(StratTab), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            StratWalkArgs wa{g->nodes, g->E, g->node_of, dtab, dv, dj, count, dpaths, dlens,
+                             dslot, dcls, make_key(q->seed), (uint32_t)sp.N, (uint32_t)sp.bits,
+                             sp.phi};
+            k_walks_strat<<<grid_for(count, 256), 256, 0, st>>>(wa);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpy(slot, dslot, c4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(cls, dcls, c4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && paths) e = hipMemcpy(paths, dpaths, rowb * (size_t)count, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && paths) e = hipMemcpy(lens, dlens, c4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
+    device_free(dv);
+    device_free(dj);
+    device_free(dslot);
+    device_free(dcls);
+    device_free(dtab);
     device_free(dpaths);
     device_free(dlens);
     return rc;

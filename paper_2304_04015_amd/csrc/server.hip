@@ -241,6 +241,8 @@ extern "C" int simrank_server_submit(simrank_server *S, const simrank_query *q, 
     r->q = *q;
     int rc = query_params(q, S->g->n, &r->p, &r->mode);
     if (!rc && (q->s < 0 || q->s >= S->g->n)) rc = fail(SIMRANK_EINVAL, "source out of range");
+    if (!rc && r->mode == SIMRANK_MODE_STRATIFIED)
+        rc = fail(SIMRANK_EINVAL, "stratified queries are not served");
     if (!rc && (r->p.R > S->prm.max_R || r->p.L > S->prm.max_L))
         rc = fail(SIMRANK_EINVAL, "query needs R or L beyond the server's slots");
     if (!rc && r->mode == SIMRANK_MODE_STITCHED && (!S->g->index || S->g->index->T != r->p.T))

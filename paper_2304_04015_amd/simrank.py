@@ -23,7 +23,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HEADER = os.path.join(INCLUDE, "simrank.h")
 
 SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
-MODE_PLAIN, MODE_STITCHED = 0, 1
+MODE_PLAIN, MODE_STITCHED, MODE_STRATIFIED = 0, 1, 2
 _ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE"}
 
 
@@ -52,6 +52,11 @@ class simrank_stats(C.Structure):
 
     def asdict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class simrank_strat_params(C.Structure):
+    _fields_ = [("z", C.c_double), ("N", C.c_int32), ("phi", C.c_int32),
+                ("shuffle_bits", C.c_int32), ("reserved", C.c_int32)]
 
 
 class simrank_index_params(C.Structure):
@@ -118,6 +123,10 @@ def lib() -> C.CDLL:
         "simrank_single_source_async": [vp, P(simrank_query), vp, vp, vp, vp],
         "simrank_workspace_stats": [vp, P(simrank_stats)],
         "simrank_walks": [vp, P(simrank_query), vp, vp, i64, vp, vp],
+        "simrank_derive_stratified": [P(simrank_query), i32, P(simrank_strat_params)],
+        "simrank_single_source_stratified": [vp, P(simrank_query), vp, vp, vp, P(simrank_stats)],
+        "simrank_stratified_async": [vp, P(simrank_query), vp, vp, vp, vp, vp],
+        "simrank_stratified_walks": [vp, P(simrank_query), vp, vp, i64, vp, vp, vp, vp],
         "simrank_build_index": [vp, P(simrank_index_params)],
         "simrank_index_info": [vp, P(simrank_index_summary)],
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
@@ -301,6 +310,59 @@ def simrank_walks(g: Graph, q: simrank_query, vs, js):
     _check(lib().simrank_walks(g.handle, C.byref(q), _ptr(vs), _ptr(js), vs.size, _ptr(paths),
                                _ptr(lens)))
     return paths, lens
+
+
+def make_stratified_query(s: int, c: float = 0.6, eps: float = 0.02, seed: int = 0, phi: int = 0,
+                          z: int = 0, delta: float = 1e-3, graph: int = 0) -> simrank_query:
+    """A query for the length-stratified estimator; phi = 0 and z = 0 select
+    Algorithm 1's cap and Algorithm 2's z (z, when given, is an integer)."""
+    return simrank_query(s=s, graph=graph, c=c, eps=eps, delta=delta, seed=seed, walk_cap=phi,
+                         R_override=z, mode=MODE_STRATIFIED, union_bound=0)
+
+
+def simrank_derive_stratified(q: simrank_query, n: int) -> simrank_strat_params:
+    p = simrank_strat_params()
+    _check(lib().simrank_derive_stratified(C.byref(q), n, C.byref(p)))
+    return p
+
+
+def simrank_single_source_stratified(g: Graph, q: simrank_query, want_out: bool = True):
+    """(Algorithm 2's estimate, the N-normalised estimate, weighted sums, stats)."""
+    out = np.empty(g.n, np.float64) if want_out else None
+    out_n = np.empty(g.n, np.float64) if want_out else None
+    wsum = np.empty(g.n, np.uint64)
+    st = simrank_stats()
+    _check(lib().simrank_single_source_stratified(
+        g.handle, C.byref(q), _ptr(out) if want_out else None, _ptr(out_n) if want_out else None,
+        _ptr(wsum), C.byref(st)))
+    return out, out_n, wsum, st
+
+
+def simrank_stratified_async(g: Graph, q: simrank_query, ws: Workspace, out_dev, out_n_dev,
+                             wsum_dev, stream=None) -> None:
+    """Device buffers (torch tensors or raw pointers): out_dev, out_n_dev float64[n]
+    or None, wsum_dev uint64/int64[n]."""
+    sp = None
+    if stream is not None:
+        sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+    _check(lib().simrank_stratified_async(g.handle, C.byref(q), ws.handle, _dev_ptr(out_dev),
+                                          _dev_ptr(out_n_dev), _dev_ptr(wsum_dev), sp))
+
+
+def simrank_stratified_walks(g: Graph, q: simrank_query, vs, js, with_paths: bool = True):
+    """(slots, classes, paths [count][phi+1] or None, lens or None)."""
+    vs = np.ascontiguousarray(vs, np.int32)
+    js = np.ascontiguousarray(js, np.uint32)
+    p = simrank_derive_stratified(q, g.n)
+    slots = np.empty(vs.size, np.uint32)
+    cls = np.empty(vs.size, np.int32)
+    paths = np.empty((vs.size, p.phi + 1), np.int32) if with_paths else None
+    lens = np.empty(vs.size, np.int32) if with_paths else None
+    _check(lib().simrank_stratified_walks(g.handle, C.byref(q), _ptr(vs), _ptr(js), vs.size,
+                                          _ptr(slots), _ptr(cls),
+                                          _ptr(paths) if with_paths else None,
+                                          _ptr(lens) if with_paths else None))
+    return slots, cls, paths, lens
 
 
 def simrank_build_index(g: Graph, seg_log2: int = 3, kappa: float = 1.0, c: float = 0.6,

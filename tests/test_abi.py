@@ -102,3 +102,34 @@ def test_union_bound_grows_R():
     r2 = S.simrank_derive_params(q2, n).R
     assert r2 > r1
     assert r2 == math.ceil(math.log(2 * n / 1e-3) / (2 * (0.02 - 0.6 ** 65) ** 2))
+
+
+# ------------------------------------------------ length-stratified estimator
+
+@pytest.mark.parametrize("n,c,eps,z,phi", [(500, 0.6, 0.05, 0, 0), (1 << 20, 0.6, 0.02, 0, 0),
+                                           (1 << 24, 0.6, 0.02, 0, 0), (1000, 0.8, 0.03, 0, 0),
+                                           (300, 0.6, 0.05, 2000, 9), (2, 0.6, 0.9, 100, 0),
+                                           (4096, 0.5, 0.1, 0, 40)])
+def test_derive_stratified_matches_oracle(n, c, eps, z, phi):
+    q = S.make_stratified_query(0, c=c, eps=eps, z=z, phi=phi)
+    p = S.simrank_derive_stratified(q, n)
+    want = oracle.strat_params(n, c, eps, z=float(z), phi=phi)
+    assert p.z == want.z
+    assert (p.N, p.phi) == (want.N, want.phi)
+    assert 2 ** p.shuffle_bits >= p.N and (p.shuffle_bits == 2 or 2 ** (p.shuffle_bits - 1) < p.N)
+    # the generic parameter call reports N and phi as R and L
+    gp = S.simrank_derive_params(q, n)
+    assert (gp.R, gp.L) == (p.N, p.phi)
+
+
+@pytest.mark.parametrize("kw", [dict(eps=0.006, n=500),           # eps <= 3/n
+                                dict(eps=0.05, n=1),              # phi = 0
+                                dict(eps=0.05, n=500, phi=256),
+                                dict(eps=0.0001, n=1 << 30),      # N >= 2^24
+                                dict(eps=0.05, n=500, z=-3)])
+def test_derive_stratified_rejects(kw):
+    n = kw.pop("n")
+    q = S.make_stratified_query(0, c=0.6, **kw)
+    with pytest.raises(S.SimRankError) as e:
+        S.simrank_derive_stratified(q, n)
+    assert e.value.code == S.SIMRANK_EINVAL

@@ -1,0 +1,160 @@
+"""GPU parity of the length-stratified estimator (Algorithms 1 and 2) against
+the CPU oracle: shuffle slots, classes and fixed-length walks bit for bit;
+weighted meet sums (fixed point) bit for bit; estimates equal.  Every call
+goes through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_04015_amd import inputs
+from paper_2304_04015_amd import simrank as S
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x2304040150000031
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_params(g, q):
+    return O.strat_params(g.n, q.c, q.eps, z=float(q.R_override), phi=q.walk_cap)
+
+
+@pytest.fixture(scope="module")
+def small():
+    g = inputs.rmat_in(11, 10 << 11, seed=71)          # has nodes without in-edges
+    return g, S.load_csr(g)
+
+
+@pytest.mark.parametrize("z,phi", [(0, 0), (3000, 12), (40, 6)])
+def test_slots_classes_and_walks_bit_exact(small, z, phi):
+    g, G = small
+    q = S.make_stratified_query(0, c=0.6, eps=0.08, seed=SEED, z=z, phi=phi)
+    P = _oracle_params(g, q)
+    rng = np.random.default_rng(z + phi)
+    cnt = 30000
+    vs = rng.integers(0, g.n, cnt).astype(np.int32)
+    js = rng.integers(0, P.N, cnt).astype(np.uint32)
+    _say(f"stratified walks: N={P.N} phi={P.phi}")
+    slots, cls, paths, lens = S.simrank_stratified_walks(G, q, vs, js)
+    opaths, olens, oslots, ocls = O.walk_table_strat(g, SEED, P, vs, js)
+    assert np.array_equal(slots, oslots)
+    assert np.array_equal(cls, ocls)
+    assert np.array_equal(lens, olens)
+    assert np.array_equal(paths, opaths)
+    assert (lens < cls).any() and (lens == cls).any()      # dead ends and full walks both seen
+
+
+def test_shuffle_is_a_permutation_on_device(small):
+    g, G = small
+    for z in (40, 3000):
+        q = S.make_stratified_query(0, c=0.6, eps=0.08, seed=SEED, z=z, phi=10)
+        N = S.simrank_derive_stratified(q, g.n).N
+        for v in (0, 5, g.n - 1):
+            slots, cls, _, _ = S.simrank_stratified_walks(G, q, np.full(N, v), np.arange(N),
+                                                          with_paths=False)
+            assert np.array_equal(np.sort(slots), np.arange(N))
+
+
+@pytest.mark.parametrize("z,phi,s_rank", [(2500, 0, 3), (800, 9, 0), (30, 5, 10)])
+def test_weighted_sums_bit_exact(small, z, phi, s_rank):
+    """All nodes; N above one tile of 1024 walks for z = 2500 (several tiles,
+    ragged last tile); a tiny z where rounding dominates the class sizes."""
+    g, G = small
+    s = int(np.argsort(g.in_degree())[-1 - s_rank])
+    q = S.make_stratified_query(s, c=0.6, eps=0.08, seed=SEED + z, z=z, phi=phi)
+    P = _oracle_params(g, q)
+    _say(f"stratified sums: s={s} N={P.N} phi={P.phi}")
+    out, out_n, wsum, st = S.simrank_single_source_stratified(G, q)
+    want, meets, work = O.strat_sums(g, s, SEED + z, P, with_stats=True)
+    assert np.array_equal(wsum, want)
+    o_out, o_out_n = O.strat_estimates(want, s, P)
+    assert np.array_equal(out, o_out)
+    assert np.array_equal(out_n, o_out_n)
+    assert out[s] == 1.0 and wsum[s] == 0
+    assert st.meets == int(meets.sum())
+    assert st.moves == int(work.sum())
+    assert st.moves == st.draws              # fixed-length walks draw only to move
+    assert st.R == P.N and st.L == P.phi
+    assert st.meets > 0 or z < 100
+
+
+def test_paper_parameters_medium_graph_sampled():
+    """Algorithm 2's own z and Algorithm 1's cap on a 2^16-node R-MAT graph:
+    N = 14,825 walks per node, phi = 43; about 40 sampled nodes (with the 8 of
+    highest in-degree) against the oracle."""
+    g = inputs.rmat_in(16, 16 << 16, seed=72)
+    G = S.load_csr(g)
+    s = int(inputs.sources_with_in_edges(g, 1, 73)[0])
+    q = S.make_stratified_query(s, c=0.6, eps=0.02, seed=SEED)
+    P = _oracle_params(g, q)
+    assert (P.phi, P.N) == (43, 14825)
+    _say(f"paper parameters: n={g.n} N={P.N} phi={P.phi}")
+    out, out_n, wsum, st = S.simrank_single_source_stratified(G, q)
+    rng = np.random.default_rng(5)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    smp = np.union1d(rng.choice(act, 32, replace=False), np.argsort(g.in_degree())[-8:])
+    smp = np.union1d(smp, [s]).astype(np.int32)
+    want = O.strat_sums(g, s, SEED, P, vs=smp)
+    assert np.array_equal(wsum[smp], want)
+    o_out, o_out_n = O.strat_estimates(want, s, P, vs=smp)
+    assert np.array_equal(out[smp], o_out) and np.array_equal(out_n[smp], o_out_n)
+    # estimates are probabilities up to the weights' z / N factor
+    assert np.all(out_n >= 0) and np.all(out_n <= 1.0 + 1e-12)
+
+
+def test_edge_cases():
+    # source without in-edges: no walk of s moves, no pair can meet
+    g = inputs.from_edges(5, [1, 2, 3], [0, 0, 1])
+    G = S.load_csr(g)
+    q = S.make_stratified_query(4, c=0.6, eps=0.5, seed=SEED, z=500, phi=4)
+    out, out_n, wsum, st = S.simrank_single_source_stratified(G, q)
+    assert wsum.sum() == 0 and out[4] == 1.0 and st.moves == 0
+    # every node's only in-neighbour is node 2 (a self-loop at 2): walks of s and
+    # of u, both of length >= 1, meet at step 1
+    g = inputs.from_edges(3, [2, 2, 2], [0, 1, 2], drop_self_loops=False)
+    G = S.load_csr(g)
+    q = S.make_stratified_query(0, c=0.6, eps=0.5, seed=SEED, z=700, phi=5)
+    P = _oracle_params(g, q)
+    out, out_n, wsum, st = S.simrank_single_source_stratified(G, q)
+    assert np.array_equal(wsum, O.strat_sums(g, 0, SEED, P))
+    cls = [S.simrank_stratified_walks(G, q, np.full(P.N, u), np.arange(P.N), False)[1]
+           for u in range(3)]
+    assert st.meets == sum(int(((cls[0] >= 1) & (cls[u] >= 1)).sum()) for u in (1, 2))
+    # rejects
+    with pytest.raises(S.SimRankError):
+        S.simrank_single_source_stratified(G, S.make_stratified_query(3, eps=0.5, z=10))
+    with pytest.raises(S.SimRankError):
+        S.simrank_single_source_ex(G, S.make_stratified_query(0, eps=0.5, z=10))
+    with pytest.raises(S.SimRankError):
+        S.simrank_single_source_stratified(G, S.make_query(0, eps=0.5, R=10))
+
+
+def test_async_matches_sync_and_repeats(small):
+    import torch
+    g, G = small
+    s = int(np.argmax(g.in_degree()))
+    q = S.make_stratified_query(s, c=0.6, eps=0.08, seed=SEED, z=1500, phi=10)
+    P = _oracle_params(g, q)
+    _, _, w_sync, _ = S.simrank_single_source_stratified(G, q)
+    ws = S.Workspace(G, P.N, P.phi)
+    stream = torch.cuda.Stream()
+    wsum = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        S.simrank_stratified_async(G, q, ws, out, None, wsum, stream)
+        st = S.simrank_workspace_stats(ws)
+        assert np.array_equal(wsum.cpu().numpy().view(np.uint64), w_sync), rep
+    # a plain query on the same workspace afterwards is unaffected
+    qp = S.make_query(s, c=0.6, seed=SEED, walk_cap=10, R=min(P.N, 2000))
+    cnt = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    S.simrank_single_source_async(G, qp, ws, None, cnt, stream)
+    S.simrank_workspace_stats(ws)
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint32), S.simrank_single_source_ex(G, qp)[1])
+    assert st.moves > 0
+    ws.free()
