@@ -59,11 +59,13 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "stitching", "batching", "serving"],
+                    choices=["medium", "stitching", "batching", "serving", "stratified"],
                     help="medium: the default line; stitching: R-MAT n=2^24 index build "
                          "and stitched query; batching: 512 queries over 16 graphs, "
                          "one captured batch vs one query at a time; serving: Poisson "
-                         "arrivals on R-MAT n=2^22 at fractions of the plain capacity")
+                         "arrivals on R-MAT n=2^22 at fractions of the plain capacity; "
+                         "stratified: the medium graph and sources with the paper's "
+                         "length-stratified estimator (Algorithms 1-2)")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
     ap.add_argument("--steps", type=int, default=3)
@@ -97,6 +99,8 @@ def main():
         return bench_batching(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "stratified":
+        return bench_stratified(args)
 
     import numpy as np
     import torch
@@ -236,6 +240,113 @@ def main():
                       f"({pairs} pairs, {dt:.1f}s single-threaded); counts equal to the GPU's: {same}",
             "queries_per_s": pairs / dt / ((g.n - 1) * R),
         }
+    print(json.dumps(result))
+    for ws in wss:
+        ws.free()
+    G.free()
+
+
+def bench_stratified(args):
+    """The medium graph and its 8 sources with the length-stratified estimator
+    at Algorithm 2's own z for eps = 0.02 (N = 18,234 walks per node) and
+    Algorithm 1's cap phi = 54, against the plain estimator on the same
+    queries (R = 9,502, L = 64)."""
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = dict(inputs.C2)
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = inputs.workload_graph(cfg)
+    sources = inputs.sources_with_in_edges(g, cfg["n_sources"], cfg["source_seed"])
+    print(f"# graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s", file=sys.stderr)
+    G = S.load_csr(g)
+    sq = [S.make_stratified_query(int(s), c=cfg["c"], eps=cfg["eps"], seed=cfg["walk_seed"])
+          for s in sources]
+    pq = [S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
+                       seed=cfg["walk_seed"], walk_cap=cfg["L"]) for s in sources]
+    sp = S.simrank_derive_stratified(sq[0], g.n)
+    R = S.simrank_derive_params(pq[0], g.n).R
+    stream = torch.cuda.Stream()
+    wss = [S.simrank_workspace_create(G, max(sp.N, R), max(sp.phi, cfg["L"])) for _ in sources]
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in sources]
+    outn = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in sources]
+    wsum = [torch.empty(g.n, dtype=torch.int64, device="cuda") for _ in sources]
+    pout = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in sources]
+    pcnt = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in sources]
+
+    def run(stratified: bool):
+        for i, ws in enumerate(wss):
+            if stratified:
+                S.simrank_stratified_async(G, sq[i], ws, outs[i], outn[i], wsum[i], stream)
+            else:
+                S.simrank_single_source_async(G, pq[i], ws, pout[i], pcnt[i], stream)
+        return [S.simrank_workspace_stats(ws) for ws in wss]
+
+    res = {}
+    for kind in (True, False):
+        ref = run(kind)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        meet_ms = []
+        for _ in range(args.steps):
+            sts = run(kind)
+            for st, r in zip(sts, ref):
+                assert st.moves == r.moves and st.meets == r.meets
+            meet_ms += [st.meet_ms for st in sts]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        steps = sum(st.moves + st.source_moves for st in ref) * args.steps
+        res[kind] = dict(elapsed=el, steps=steps, q=len(sources) * args.steps,
+                         meet_ms=float(np.mean(meet_ms)),
+                         moves=float(np.mean([st.moves for st in ref])),
+                         meets=float(np.mean([st.meets for st in ref])),
+                         pairs_walked=float(np.mean([st.pairs_walked for st in ref])))
+    st_, pl = res[True], res[False]
+    diffs = [float((outn[i] - pout[i]).abs().max()) for i in range(len(sources))]
+    value = st_["steps"] / st_["elapsed"]
+    achieved = BYTES_PER_MOVE * st_["moves"] / (st_["meet_ms"] / 1e3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": 1e3 * st_["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "stratified: R-MAT n=2^20 (the medium graph), 8 sources; "
+                        "length-stratified estimator at eps=0.02: z=ln(2n)/(2(eps-3/n)^2), "
+                        f"N={sp.N} walks per node in classes l=0..{sp.phi}, shuffled; "
+                        "Lemma 5 weights",
+            "n": g.n, "m": g.m, "N": sp.N, "phi": sp.phi, "z": sp.z,
+        },
+        "queries_per_s": st_["q"] / st_["elapsed"],
+        "plain_queries_per_s": pl["q"] / pl["elapsed"],
+        "plain_walk_steps_per_s": pl["steps"] / pl["elapsed"],
+        "moves_per_query": st_["moves"],
+        "plain_moves_per_query": pl["moves"],
+        "meet_kernel_ms": st_["meet_ms"],
+        "plain_meet_kernel_ms": pl["meet_ms"],
+        "max_abs_diff_vs_plain_estimate": max(diffs),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_meet<stratified> (fused walk + meet + weighted count)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
     print(json.dumps(result))
     for ws in wss:
         ws.free()

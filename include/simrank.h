@@ -106,8 +106,8 @@ typedef struct simrank_strat_params {
     double z;            /* ln(2n) / (2 (eps - 3/n)^2), the expected number of walks */
     int32_t N;           /* walks per node: sum over l of ceil(z sqrt(c)^l (1 - sqrt(c))) */
     int32_t phi;         /* walk length cap: floor(log_{1/sqrt c} n) */
-    int32_t shuffle_bits;/* the shuffle permutes [0, 2^bits), 2^bits >= N */
-    int32_t reserved;
+    int32_t shuffle_b;   /* the shuffle permutes the grid [0, shuffle_A) x [0, 2^shuffle_b), */
+    int32_t shuffle_A;   /* b = ceil(ceil(log2 N) / 2), A = ceil(N / 2^b) */
 } simrank_strat_params;
 
 /* Stitched-walk index parameters. */
@@ -204,8 +204,8 @@ int simrank_walks(const simrank_graph *g, const simrank_query *q, const int32_t 
  * by class into slots 0..N-1 (slot r of class l walks l uniform steps keyed
  * (v, r, t, 4); a walk that reaches a node without in-neighbours ends there),
  * and the shuffle maps walk j to slot pi_v(j), a keyed permutation of [0, N)
- * (a four-round Feistel network with round keys Philox(v, 0, 0, 5), cycle
- * walked into [0, N)).  Weights are summed in fixed point, 2^40 per unit
+ * (a four-round mixed-radix Feistel network on a grid of A 2^b >= N points
+ * with round keys Philox(v, 0, 0, 5), cycle walked into [0, N)).  Weights are summed in fixed point, 2^40 per unit
  * weight, each weight truncated: the sums are exact and order independent.
  * Query fields used: s, c, eps (z, unless R_override > 0 gives z), walk_cap
  * (0: phi from n), seed; delta is checked but not used by the method.

@@ -366,36 +366,41 @@ static uint32_t fmix32(uint32_t h)
     return h;
 }
 
-/* A keyed bijection of [0, 2^bits): split x into a high part of
- * bits - bits/2 bits and a low part of bits/2 bits, then four rounds that
- * alternately XOR one part with the round function of the other part (each
- * round is invertible, so the whole map is). */
-static uint32_t feistel4(uint32_t x, int bits, const uint32_t k[4])
+/* A keyed bijection of the grid [0, A) x [0, B), B = 2^b: four rounds that
+ * alternately add to the high coordinate, modulo A, a round-function value
+ * scaled into [0, A), and XOR the low coordinate with the round-function
+ * value's low b bits.  Each round is invertible when the other coordinate is
+ * held, so the whole map is (a Feistel network over mixed radix, as in the
+ * FF1 mode of NIST SP 800-38G).  The grid point (hi, lo) is the integer
+ * hi * B + lo. */
+static uint32_t feistel4(uint32_t x, uint32_t A, int b, const uint32_t k[4])
 {
-    int a = bits / 2, h = bits - a;
-    uint32_t ma = (1u << a) - 1u, mh = (1u << h) - 1u;
-    uint32_t hi = x >> a, lo = x & ma;
-    hi ^= fmix32(lo ^ k[0]) & mh;
-    lo ^= fmix32(hi ^ k[1]) & ma;
-    hi ^= fmix32(lo ^ k[2]) & mh;
-    lo ^= fmix32(hi ^ k[3]) & ma;
-    return (hi << a) | lo;
+    uint32_t B = 1u << b;
+    uint32_t hi = x >> b, lo = x & (B - 1u);
+    hi = (uint32_t)(((uint64_t)hi + pick(fmix32(lo ^ k[0]), A)) % A);
+    lo ^= fmix32(hi ^ k[1]) & (B - 1u);
+    hi = (uint32_t)(((uint64_t)hi + pick(fmix32(lo ^ k[2]), A)) % A);
+    lo ^= fmix32(hi ^ k[3]) & (B - 1u);
+    return (hi << b) | lo;
 }
 
 /* Shuffle of node v's N walks (Section 4.2; the paper leaves the method
- * open): walk j after the shuffle is the walk generated in slot pi_v(j), where
- * pi_v is the Feistel bijection above on the smallest power of two >= N (at
- * least 4), restricted to [0, N) by cycle walking (Black and Rogaway, "Ciphers
- * with Arbitrary Finite Domains", CT-RSA 2002): apply it again while the value
- * is >= N.  Round keys: Philox(ctr = (v, 0, 0, 5)). */
+ * open): walk j after the shuffle is the walk generated in slot pi_v(j).
+ * pi_v is the bijection above on the grid of A * B >= N points with
+ * B = 2^ceil(ceil(log2 N) / 2) and A = ceil(N / B), restricted to [0, N) by
+ * cycle walking (Black and Rogaway, "Ciphers with Arbitrary Finite Domains",
+ * CT-RSA 2002): apply it again while the value is >= N.  Fewer than 2/sqrt(N)
+ * of the grid's points lie beyond N.  Round keys: Philox(ctr = (v, 0, 0, 5)). */
 uint32_t oracle_shuffle_slot(uint64_t seed, int32_t v, uint32_t j, int64_t N)
 {
-    int bits = 2;
+    int bits = 0;
     while (((int64_t)1 << bits) < N) ++bits;
+    int b = (bits + 1) / 2;
+    uint32_t A = (uint32_t)((N + ((int64_t)1 << b) - 1) >> b);
     uint32_t k[4];
     draw(seed, (uint32_t)v, 0u, 0u, 5u, k);
-    uint32_t y = feistel4(j, bits, k);
-    while ((int64_t)y >= N) y = feistel4(y, bits, k);
+    uint32_t y = feistel4(j, A, b, k);
+    while ((int64_t)y >= N) y = feistel4(y, A, b, k);
     return y;
 }
 

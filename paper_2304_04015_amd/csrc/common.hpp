@@ -106,7 +106,8 @@ struct StratParams {
     double z = 0;                 // Algorithm 2's normaliser
     int32_t N = 0;                // walks per node, sum of Zhat_l
     int32_t phi = 0;              // walk length cap
-    int32_t bits = 2;             // shuffle domain 2^bits >= N
+    int32_t sb = 0;               // shuffle grid [0, sa) x [0, 2^sb), sa 2^sb >= N
+    int32_t sa = 1;
 };
 
 // One query as the device kernels see it (one entry per query of a launch).
@@ -136,7 +137,7 @@ struct QueryDesc {
     unsigned long long *wsum;  // [n] weighted meet sums, 2^40 = weight 1 (caller's)
     double *out_n;         // [n] estimate normalised by the N pairs, or NULL
     double z;
-    int32_t sbits;
+    int32_t sa, sb;        // shuffle grid
 };
 
 // A set of queries whose descriptors are already in device memory.

@@ -77,9 +77,11 @@ constexpr uint32_t ITEM_CHUNK = 64;
 // Node v's N fixed-length walks are generated class by class (slots
 // [ccum[l], ccum[l+1]) hold the walks of length l) and then shuffled: walk j
 // is the walk generated in slot pi_v(j).  pi_v is a four-round Feistel
-// network on [0, 2^bits), 2^bits >= N, restricted to [0, N) by cycle walking
-// (Black and Rogaway, CT-RSA 2002); its round keys are the four words of
-// Philox(v, 0, 0, DOM_SHUFFLE).
+// network over the grid [0, A) x [0, 2^b) (A 2^b >= N, 2^b about sqrt(N)),
+// restricted to [0, N) by cycle walking (Black and Rogaway, CT-RSA 2002); its
+// round keys are the four words of Philox(v, 0, 0, DOM_SHUFFLE).  Fewer than
+// 2/sqrt(N) of the grid's points lie beyond N, so a lane almost never walks a
+// second time.
 
 // MurmurHash3's 32-bit finalizer (A. Appleby, public domain), the round function.
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
@@ -91,25 +93,29 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 
-// Bijection of [0, 2^bits): high part of bits - bits/2 bits, low part of
-// bits/2 bits; each round XORs one part with the round function of the other.
-__device__ __forceinline__ uint32_t feistel4(uint32_t x, uint32_t bits, uint4 k) {
-    const uint32_t a = bits >> 1, h = bits - a;
-    const uint32_t ma = (1u << a) - 1u, mh = (1u << h) - 1u;
-    uint32_t hi = x >> a, lo = x & ma;
-    hi ^= fmix32(lo ^ k.x) & mh;
-    lo ^= fmix32(hi ^ k.y) & ma;
-    hi ^= fmix32(lo ^ k.z) & mh;
-    lo ^= fmix32(hi ^ k.w) & ma;
-    return (hi << a) | lo;
+// Bijection of the grid, point (hi, lo) = hi 2^b + lo: rounds alternately add
+// a round-function value scaled into [0, A) to hi modulo A, and XOR lo with
+// its low b bits (a mixed-radix Feistel network, as in NIST SP 800-38G FF1).
+__device__ __forceinline__ uint32_t feistel4(uint32_t x, uint32_t A, uint32_t b, uint4 k) {
+    const uint32_t mb = (1u << b) - 1u;
+    uint32_t hi = x >> b, lo = x & mb;
+    hi += __umulhi(fmix32(lo ^ k.x), A);
+    hi = hi >= A ? hi - A : hi;
+    lo ^= fmix32(hi ^ k.y) & mb;
+    hi += __umulhi(fmix32(lo ^ k.z), A);
+    hi = hi >= A ? hi - A : hi;
+    lo ^= fmix32(hi ^ k.w) & mb;
+    return (hi << b) | lo;
 }
 
 // pi_v(j) for j < N.  The orbit of j under the bijection is a cycle through
-// j, so a value below N comes back within 2^bits applications; the loop is
+// j, so a value below N comes back within A 2^b applications; the loop is
 // bounded by that.
-__device__ __forceinline__ uint32_t shuffle_slot(uint32_t j, uint32_t N, uint32_t bits, uint4 k) {
-    uint32_t y = feistel4(j, bits, k);
-    for (uint32_t it = 1; y >= N && it < (1u << bits); ++it) y = feistel4(y, bits, k);
+__device__ __forceinline__ uint32_t shuffle_slot(uint32_t j, uint32_t N, uint32_t A, uint32_t b,
+                                                 uint4 k) {
+    uint32_t y = feistel4(j, A, b, k);
+    const uint32_t cap = A << b;
+    for (uint32_t it = 1; y >= N && it < cap; ++it) y = feistel4(y, A, b, k);
     return y;
 }
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
         int32_t len = 0;
         if (d.kind == K_STRAT) {
             const uint4 fk = philox4x32_10((uint32_t)d.s, 0u, 0u, DOM_SHUFFLE, key);
-            const uint32_t r = shuffle_slot((uint32_t)j, (uint32_t)d.R, (uint32_t)d.sbits, fk);
+            const uint32_t r = shuffle_slot((uint32_t)j, (uint32_t)d.R, (uint32_t)d.sa, (uint32_t)d.sb, fk);
             const uint32_t cls = slot_class(r, d.tab->ccum, d.L);
             for (int32_t t = 1; t <= (int32_t)cls; ++t) {
                 if (cur.y == 0) break;
@@ -221,8 +221,15 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 // estimator's fixed-length walks: walk j of v has the class of slot pi_v(j),
 // takes no stop draw, and a meet adds Lemma 5's weight of the two classes).
 
+// Waves per SIMD the register allocation must allow: the stratified kind,
+// with its shuffle and class search at every refill, needs the full 8 to hide
+// its ALU latency; the others fit 8 by themselves and run best unconstrained.
+#ifndef SRK_MEET_MIN_WAVES_STRAT
+#define SRK_MEET_MIN_WAVES_STRAT 8
+#endif
+
 template <int KIND, int NS>
-__global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
+__global__ __launch_bounds__(MEET_BLOCK, KIND == K_STRAT ? SRK_MEET_MIN_WAVES_STRAT : 1) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t *__restrict__ cursor,
                                                      unsigned long long *__restrict__ counters) {
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
         const PhiloxKey key{uni(d.k0), uni(d.k1)};
         const uint32_t T = uni(d.T);
         const int32_t src = (int32_t)uni((uint32_t)d.s);
-        const uint32_t NN = uni((uint32_t)d.R), sbits = uni((uint32_t)d.sbits);
+        const uint32_t NN = uni((uint32_t)d.R), sa = uni((uint32_t)d.sa), sb = uni((uint32_t)d.sb);
         const int32_t phi = (int32_t)uni((uint32_t)d.L);
         if ((uint32_t)q != cur_q || tile != cur_tile) {
             const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
@@ -355,7 +362,7 @@ __global__ __launch_bounds__(MEET_BLOCK) void k_meet(const QueryDesc *__restrict
                             const uint32_t base = s_off[k];
                             uint32_t len = (uint32_t)s_off[k + 1] - base;
                             if (STRAT) {
-                                const uint32_t r = shuffle_slot(s_j[k], NN, sbits, s_fk[vl]);
+                                const uint32_t r = shuffle_slot(s_j[k], NN, sa, sb, s_fk[vl]);
                                 const uint32_t cv = slot_class(r, s_ccum, phi);
                                 len = min(len, cv);
                                 sl[qq].aux = ((uint32_t)s_cls[k] << 8) | cv;
@@ -575,7 +582,7 @@ struct StratWalkArgs {
     uint32_t *slots;  // or NULL
     int32_t *classes; // or NULL
     PhiloxKey key;
-    uint32_t N, bits;
+    uint32_t N, sa, sb;
     int32_t phi;
 };
 
@@ -584,7 +591,7 @@ __global__ __launch_bounds__(256) void k_walks_strat(StratWalkArgs a) {
     if (i >= a.count) return;
     const uint32_t v = (uint32_t)a.vs[i], j = a.js[i];
     const uint4 fk = philox4x32_10(v, 0u, 0u, DOM_SHUFFLE, a.key);
-    const uint32_t r = shuffle_slot(j, a.N, a.bits, fk);
+    const uint32_t r = shuffle_slot(j, a.N, a.sa, a.sb, fk);
     const uint32_t cls = slot_class(r, a.tab->ccum, a.phi);
     if (a.slots) a.slots[i] = r;
     if (a.classes) a.classes[i] = (int32_t)cls;
@@ -801,9 +808,10 @@ int strat_params(const simrank_query *q, int32_t n, StratParams *sp, StratTab *t
     sp->z = z;
     sp->N = (int32_t)N;
     sp->phi = phi;
-    int32_t bits = 2;
+    int32_t bits = 0;
     while ((1 << bits) < sp->N) ++bits;
-    sp->bits = bits;
+    sp->sb = (bits + 1) / 2;
+    sp->sa = (sp->N + (1 << sp->sb) - 1) >> sp->sb;
     return SIMRANK_OK;
 }
 
@@ -941,7 +949,8 @@ int enqueue_stratified(const Graph *g, const simrank_query *q, Workspace *ws, do
     d.out = out_dev;
     d.out_n = out_n_dev;
     d.z = sp.z;
-    d.sbits = sp.bits;
+    d.sa = sp.sa;
+    d.sb = sp.sb;
     SRK_HIP(hipMemcpyAsync(ws->tab, ws->tab_host, sizeof(StratTab), hipMemcpyHostToDevice, st));
     SRK_HIP(hipEventRecord(ws->ev_tab, st));
     return launch_single(g, ws, d, st);
@@ -1159,7 +1168,7 @@ extern "C" int simrank_derive_stratified(const simrank_query *q, int32_t n,
     StratParams sp;
     rc = strat_params(&qq, n, &sp, nullptr);
     if (rc) return rc;
-    *out = simrank_strat_params{sp.z, sp.N, sp.phi, sp.bits, 0};
+    *out = simrank_strat_params{sp.z, sp.N, sp.phi, sp.sb, sp.sa};
     return SIMRANK_OK;
 }
 
@@ -1252,8 +1261,8 @@ extern "C" int simrank_stratified_walks(const simrank_graph *g, const simrank_qu
         if (e == hipSuccess) e = hipMemcpy(dtab, &tab, sizeof(StratTab), hipMemcpyHostToDevice);
         if (e == hipSuccess) {
             StratWalkArgs wa{g->nodes, g->E, g->node_of, dtab, dv, dj, count, dpaths, dlens,
-                             dslot, dcls, make_key(q->seed), (uint32_t)sp.N, (uint32_t)sp.bits,
-                             sp.phi};
+                             dslot, dcls, make_key(q->seed), (uint32_t)sp.N, (uint32_t)sp.sa,
+                             (uint32_t)sp.sb, sp.phi};
             k_walks_strat<<<grid_for(count, 256), 256, 0, st>>>(wa);
             e = hipGetLastError();
         }

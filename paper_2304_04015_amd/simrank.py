@@ -56,7 +56,7 @@ class simrank_stats(C.Structure):
 
 class simrank_strat_params(C.Structure):
     _fields_ = [("z", C.c_double), ("N", C.c_int32), ("phi", C.c_int32),
-                ("shuffle_bits", C.c_int32), ("reserved", C.c_int32)]
+                ("shuffle_b", C.c_int32), ("shuffle_A", C.c_int32)]
 
 
 class simrank_index_params(C.Structure):

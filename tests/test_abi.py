@@ -116,7 +116,9 @@ def test_derive_stratified_matches_oracle(n, c, eps, z, phi):
     want = oracle.strat_params(n, c, eps, z=float(z), phi=phi)
     assert p.z == want.z
     assert (p.N, p.phi) == (want.N, want.phi)
-    assert 2 ** p.shuffle_bits >= p.N and (p.shuffle_bits == 2 or 2 ** (p.shuffle_bits - 1) < p.N)
+    # the shuffle grid: A * 2^b >= N, 2^b about sqrt(N), fewer than 2 sqrt(N) points to spare
+    assert p.shuffle_A * 2 ** p.shuffle_b >= p.N > (p.shuffle_A - 1) * 2 ** p.shuffle_b
+    assert 2 ** p.shuffle_b <= 2 * math.sqrt(p.N) + 1 and p.shuffle_A <= math.sqrt(p.N) + 1
     # the generic parameter call reports N and phi as R and L
     gp = S.simrank_derive_params(q, n)
     assert (gp.R, gp.L) == (p.N, p.phi)
