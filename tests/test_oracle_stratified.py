@@ -246,3 +246,42 @@ def test_estimate_within_eps_at_paper_z():
     out, out_n = O.strat_estimates(w, s, P)
     assert np.max(np.abs(out - S[s])) < eps
     assert np.max(np.abs(out_n - S[s])) < eps
+
+
+# ---------------------------------------------------------------- tuple form
+
+def test_tuple_form_equals_pairwise_plain():
+    """Algorithm 2's sort + PREDECESSOR detection and the direct pairwise
+    comparison are two statements of the same counts."""
+    from oracle import tuples as TU
+    for seed, gg in [(1, _no_dead_ends(40, 3.0, 11)), (2, inputs.rmat_in(7, 5 << 7, seed=12)),
+                     (3, _star(9))]:
+        for s in (0, 3):
+            want = O.meet_counts_plain(gg, s, SEED + seed, 0.6, 16, 300)
+            got = TU.counts_plain(gg, s, SEED + seed, 0.6, 16, 300)
+            assert np.array_equal(got, want), (seed, s)
+
+
+def test_tuple_form_equals_pairwise_stratified():
+    from oracle import tuples as TU
+    for seed, gg in [(4, _no_dead_ends(30, 2.5, 13)), (5, inputs.rmat_in(7, 4 << 7, seed=14))]:
+        P = O.strat_params(gg.n, 0.6, 0.0, z=250.0, phi=9)
+        for s in (1, 6):
+            want = O.strat_sums(gg, s, SEED + seed, P)
+            got = TU.sums_stratified(gg, s, SEED + seed, P)
+            assert np.array_equal(got, want), (seed, s)
+
+
+def test_tuple_form_counts_a_pair_once():
+    """On the star every pair of walks of length >= 2 coincides at steps 1 and
+    2 (both at node 0): two linked tuples, one meet."""
+    from oracle import tuples as TU
+    g = _star(5)
+    js = np.arange(4, dtype=np.uint32)
+    paths = np.array([[1, 0, 0, -1], [1, 0, -1, -1], [2, 0, 0, 0], [2, -1, -1, -1]], np.int32)
+    lens = np.array([2, 1, 3, 0])
+    starts = np.array([1, 1, 2, 2])
+    jj = np.array([0, 1, 0, 1], np.uint32)
+    met = TU.link_meets(*TU.decompose(paths, lens, starts, jj), 1)
+    assert met.tolist() == [[2, 0]]
+    assert js.size == 4 and g.n == 5
