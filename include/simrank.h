@@ -237,6 +237,27 @@ int simrank_stratified_walks(const simrank_graph *g, const simrank_query *q, con
                              const uint32_t *j, int64_t count, uint32_t *slot, int32_t *cls,
                              int32_t *paths, int32_t *lens);
 
+/* ------------------------------------------------ Algorithm 2's tuple form */
+/*
+ * Meet detection in the paper's own form (Section 3.2; Algorithm 2) for k
+ * queries (1 <= k <= 32) on one graph that share mode (plain or stratified),
+ * seed, c, walk cap and walk count (R; or z, N and phi).  Every walk is
+ * decomposed into one tuple (j, i, node, start) per step after its start; all
+ * tuples are sorted with the sources' tuples first among equal (j, i, node);
+ * each other tuple is linked to the closest source tuple before it
+ * (PREDECESSOR); an equal key is a meet, counted once per pair.  Walks are the
+ * fused path's walks followed to their full length.
+ * sums: host uint64[k][n].  Plain queries: meet counts, sums[q][s_q] = R (equal
+ * to simrank_single_source_ex's counts).  Stratified queries: weighted sums in
+ * units of 2^-40, sums[q][s_q] = 0 (equal to simrank_single_source_stratified's
+ * wsum).  Nodes are processed in chunks whose tuples fit a 2^28-entry buffer.
+ * st_opt: moves = steps of the nodes' walks (= tuples), meets = meeting pairs,
+ * ms = device time.  EINVAL for stitched queries, k outside [1, 32], queries
+ * that differ in anything but s, or a source out of range.
+ */
+int simrank_tuple_meets(const simrank_graph *g, const simrank_query *qs, int32_t k,
+                        uint64_t *sums, simrank_stats *st_opt);
+
 /* ----------------------------------------------------------------- index */
 
 /* Builds the stitched-walk index on the graph (replacing any earlier one):

@@ -127,6 +127,7 @@ def lib() -> C.CDLL:
         "simrank_single_source_stratified": [vp, P(simrank_query), vp, vp, vp, P(simrank_stats)],
         "simrank_stratified_async": [vp, P(simrank_query), vp, vp, vp, vp, vp],
         "simrank_stratified_walks": [vp, P(simrank_query), vp, vp, i64, vp, vp, vp, vp],
+        "simrank_tuple_meets": [vp, P(simrank_query), i32, vp, P(simrank_stats)],
         "simrank_build_index": [vp, P(simrank_index_params)],
         "simrank_index_info": [vp, P(simrank_index_summary)],
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
@@ -363,6 +364,17 @@ def simrank_stratified_walks(g: Graph, q: simrank_query, vs, js, with_paths: boo
                                           _ptr(paths) if with_paths else None,
                                           _ptr(lens) if with_paths else None))
     return slots, cls, paths, lens
+
+
+def simrank_tuple_meets(g: Graph, queries: list):
+    """Algorithm 2's tuple form for up to 32 queries sharing everything but the
+    source: (sums uint64[k][n], stats)."""
+    k = len(queries)
+    arr = (simrank_query * k)(*queries)
+    sums = np.empty((k, g.n), np.uint64)
+    st = simrank_stats()
+    _check(lib().simrank_tuple_meets(g.handle, arr, k, _ptr(sums), C.byref(st)))
+    return sums, st
 
 
 def simrank_build_index(g: Graph, seg_log2: int = 3, kappa: float = 1.0, c: float = 0.6,
