@@ -71,13 +71,14 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "stitching", "batching", "serving", "stratified"],
+                    choices=["medium", "stitching", "batching", "serving", "stratified", "tuples"],
                     help="medium: the default line; stitching: R-MAT n=2^24 index build "
                          "and stitched query; batching: 512 queries over 16 graphs, "
                          "one captured batch vs one query at a time; serving: Poisson "
                          "arrivals on R-MAT n=2^22 at fractions of the plain capacity; "
                          "stratified: the medium graph and sources with the paper's "
-                         "length-stratified estimator (Algorithms 1-2)")
+                         "length-stratified estimator (Algorithms 1-2); tuples: the medium "
+                         "graph's 8 sources (and 32) through Algorithm 2's tuple form")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
     ap.add_argument("--steps", type=int, default=3)
@@ -113,6 +114,8 @@ def main():
         return bench_serving(args)
     if args.workload == "stratified":
         return bench_stratified(args)
+    if args.workload == "tuples":
+        return bench_tuples(args)
 
     import numpy as np
     import torch
@@ -358,6 +361,64 @@ def bench_stratified(args):
     print(json.dumps(result))
     for ws in wss:
         ws.free()
+    G.free()
+
+
+def bench_tuples(args):
+    """Algorithm 2's tuple form (decompose, sort, PREDECESSOR) on the medium
+    graph: the workload's 8 sources in one call, and 32 sources (the 8 plus 24
+    more, same seed and R), against the fused kernel on the same queries."""
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = dict(inputs.C2)
+    torch.cuda.set_device(0)
+    g = inputs.workload_graph(cfg)
+    sources = [int(s) for s in inputs.sources_with_in_edges(g, 32, cfg["source_seed"])]
+    G = S.load_csr(g)
+    mk = lambda s: S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
+                                seed=cfg["walk_seed"], walk_cap=cfg["L"])
+    res = {}
+    for k in (8, 32):
+        qs = [mk(s) for s in sources[:k]]
+        t0 = time.perf_counter()
+        sums, st = S.simrank_tuple_meets(G, qs)
+        el = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        same = True
+        for q in range(k):
+            fused = S.simrank_single_source_ex(G, qs[q], want_out=False)[1]
+            same &= bool(np.array_equal(sums[q], fused.astype(np.uint64)))
+        fel = time.perf_counter() - t1
+        res[k] = dict(seconds=el, device_ms=st.ms, tuples=st.moves, meets=st.meets,
+                      queries_per_s=k / el, fused_queries_per_s=k / fel,
+                      tuples_per_s=st.moves / (st.ms / 1e3), equal_to_fused=same)
+    r8 = res[8]
+    result = {
+        "metric": METRIC,
+        "value": r8["tuples_per_s"],
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * r8["seconds"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "tuples: R-MAT n=2^20 (the medium graph); c=0.6 eps=0.02 R=9502 L=64; "
+                        "Algorithm 2's tuple form for 8 and for 32 sources sharing the walks' key",
+            "n": g.n, "m": g.m, "R": S.simrank_derive_params(mk(sources[0]), g.n).R,
+        },
+        "k8": res[8],
+        "k32": res[32],
+    }
+    print(json.dumps(result))
     G.free()
 
 

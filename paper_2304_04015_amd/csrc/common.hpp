@@ -33,11 +33,45 @@ constexpr int64_t MAX_STRAT_N = (1 << 24) - 1;  // weighted sums stay below 2^64
 // Query kinds (one meet-kernel instance each).
 enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 
-// Meet-kernel tiling of the compacted source walks (see query.hip).
-constexpr int TILE_J = 1024;            // source walks per tile, at most
-constexpr int TILE_NODES = 4096;        // LDS node slots per tile
-constexpr int MEET_BLOCK = 512;         // threads per block of the meet kernel
-constexpr int MEET_VB = 256;            // nodes v per work unit, at most
+
+// Meet-kernel tiling of the compacted source walks (see query.hip), per kind.
+// The plain kind is bound by L1 misses on a graph that sits in the Infinity
+// Cache: a tile of up to 8192 walks and 24576 positions (148 KB of LDS with
+// the kernel's other arrays: one 1024-thread block per CU) keeps about 5,600
+// walks of one node in a block, whose early steps then share rows in the L1;
+// on the medium workload it measured 50.7 ms per query against 58.9 ms with
+// 1024 / 4096 tiles and 512-thread blocks.  The stitched kind (graphs beyond
+// the Infinity Cache, tails read from the index) needs more pairs in flight
+// per CU instead, and the stratified kind is bound by its per-pair ALU work:
+// both keep 1024 / 4096 tiles and 512-thread blocks (four blocks per CU).
+#ifndef SRK_TILE_J
+#define SRK_TILE_J 8192
+#endif
+#ifndef SRK_TILE_NODES
+#define SRK_TILE_NODES 24576
+#endif
+#ifndef SRK_MEET_BLOCK
+#define SRK_MEET_BLOCK 1024
+#endif
+#ifndef SRK_SMALL_TILE_J
+#define SRK_SMALL_TILE_J 1024
+#endif
+#ifndef SRK_SMALL_TILE_NODES
+#define SRK_SMALL_TILE_NODES 4096
+#endif
+#ifndef SRK_SMALL_MEET_BLOCK
+#define SRK_SMALL_MEET_BLOCK 512
+#endif
+constexpr int MEET_VB = 256;                // nodes v per work unit, at most
+__host__ __device__ constexpr int tile_j_of(int kind) {
+    return kind == K_PLAIN ? SRK_TILE_J : SRK_SMALL_TILE_J;
+}
+__host__ __device__ constexpr int tile_nodes_of(int kind) {   // < 2^16
+    return kind == K_PLAIN ? SRK_TILE_NODES : SRK_SMALL_TILE_NODES;
+}
+__host__ __device__ constexpr int meet_block_of(int kind) {
+    return kind == K_PLAIN ? SRK_MEET_BLOCK : SRK_SMALL_MEET_BLOCK;
+}
 
 // ------------------------------------------------------------ device graph
 // Gather layout of the reversed graph.  Every node v owns the edge slots

@@ -123,14 +123,15 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
 // One block per query.  Keeps the walks with at least one step (a walk of
 // length 0 can only meet at step 0, i.e. only the source itself), packs their
 // positions back to back (swc), and cuts the packed list into tiles that fit
-// the meet kernel's LDS: a tile boundary falls wherever the entry index crosses
-// a multiple of TILE_J or the packed offset crosses a multiple of
-// NW = TILE_NODES - L, so a tile holds at most TILE_J walks and at most
-// NW - 1 + L <= TILE_NODES positions.
+// the meet kernel's LDS: with the kind's shape (TJ walks, TN positions), a tile
+// boundary falls wherever the entry index crosses a multiple of TJ or the
+// packed offset crosses a multiple of NW = TN - L, so a tile holds at most TJ
+// walks and at most NW - 1 + L <= TN positions.
 __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.x];
     const int32_t R = d.R, L = d.L;
-    const uint32_t NW = (uint32_t)(TILE_NODES - L);
+    const uint32_t TJ = (uint32_t)tile_j_of(d.kind);
+    const uint32_t NW = (uint32_t)(tile_nodes_of(d.kind) - L);
     const int32_t per = (R + blockDim.x - 1) / blockDim.x;
     const int32_t j0 = min(R, (int32_t)threadIdx.x * per), j1 = min(R, j0 + per);
     uint32_t cnt = 0, nodes = 0;
@@ -157,11 +158,11 @@ __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ 
     __syncthreads();
     uint32_t nbound = 0;
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        nbound += (e == 0) || (e % TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
+        nbound += (e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
     uint32_t n_tiles;
     uint32_t tb = block_excl_sum(nbound, &n_tiles);
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        if ((e == 0) || (e % TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
+        if ((e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
             d.tiles[tb++] = e;
     if (threadIdx.x == 0) {
         d.tiles[n_tiles] = R1;
@@ -229,22 +230,23 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 #endif
 
 template <int KIND, int NS>
-__global__ __launch_bounds__(MEET_BLOCK, KIND == K_STRAT ? SRK_MEET_MIN_WAVES_STRAT : 1) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
+__global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN_WAVES_STRAT : 1) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t *__restrict__ cursor,
                                                      unsigned long long *__restrict__ counters) {
     constexpr bool STITCHED = KIND == K_STITCHED;
     constexpr bool STRAT = KIND == K_STRAT;
-    __shared__ uint32_t s_nodes[TILE_NODES];
-    __shared__ uint32_t s_j[TILE_J];
-    __shared__ uint16_t s_off[TILE_J + 1];
+    constexpr int TJ = tile_j_of(KIND), TN = tile_nodes_of(KIND);
+    __shared__ uint32_t s_nodes[TN];
+    __shared__ uint32_t s_j[TJ];
+    __shared__ uint16_t s_off[TJ + 1];
     __shared__ uint32_t s_cnt[STRAT ? 1 : MEET_VB];
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
     __shared__ uint32_t s_unit, s_item;
     // stratified: classes of the tile's source walks, class starts, the
     // shuffle keys of the unit's nodes, weighted sums
-    __shared__ uint8_t s_cls[STRAT ? TILE_J : 1];
+    __shared__ uint8_t s_cls[STRAT ? TJ : 1];
     __shared__ uint32_t s_ccum[STRAT ? MAX_CAP + 2 : 1];
     __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
     __shared__ unsigned long long s_w[STRAT ? MEET_VB : 1];
@@ -630,7 +632,8 @@ int meet_grid_blocks() {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<KIND, NS>, MEET_BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<KIND, NS>,
+                                                           meet_block_of(KIND), 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
         blocks = cus * per;
@@ -643,7 +646,8 @@ void launch_meet(const QuerySet &qs, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(qs.units_bound[KIND], meet_grid_blocks<KIND, NS>());
     const uint32_t *ustart = qs.units + (size_t)KIND * (qs.nq + 1);
     uint32_t *cursor = qs.units + (size_t)N_KINDS * (qs.nq + 1) + KIND;
-    k_meet<KIND, NS><<<blocks, MEET_BLOCK, 0, st>>>(qs.desc, qs.nq, ustart, cursor, qs.counters);
+    k_meet<KIND, NS><<<blocks, meet_block_of(KIND), 0, st>>>(qs.desc, qs.nq, ustart, cursor,
+                                                             qs.counters);
 }
 
 }  // namespace
@@ -662,9 +666,11 @@ IndexView index_view(const Graph *g) {
     return v;
 }
 
+// Tiles of R walks of cap L, at most, for any kind (the smallest shape).
 int32_t max_tiles_for(int32_t R, int32_t L) {
-    const int64_t NW = TILE_NODES - L;
-    return (int32_t)(2 + R / TILE_J + ((int64_t)R * L) / NW);
+    const int64_t TJ = std::min(tile_j_of(K_PLAIN), tile_j_of(K_STITCHED));
+    const int64_t NW = std::min(tile_nodes_of(K_PLAIN), tile_nodes_of(K_STITCHED)) - L;
+    return (int32_t)(2 + R / TJ + ((int64_t)R * L) / NW);
 }
 
 // Nodes per work unit: small graphs use small chunks so that their units
