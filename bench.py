@@ -556,6 +556,22 @@ def bench_batching(args):
     same = all(np.array_equal(plan.read(i, want_out=False)[1], c) for i, c in check.items())
     walk_steps = st.moves + st.tail_steps + st.source_moves
     nq = len(queries)
+    # per graph: up to 4 of its queries alone (untimed above), the meet kernel's
+    # moves per second and algorithmic bytes (8 B per move) against the HBM peak
+    per_graph = []
+    for gi, G in enumerate(Gs):
+        mine = [q for q in queries if q.graph == gi][:4]
+        moves = ms = 0.0
+        for q in mine:
+            S.simrank_single_source_async(G, q, wss[gi], outs[gi], cnts[gi], stream)
+            qs_ = S.simrank_workspace_stats(wss[gi])
+            moves += qs_.moves
+            ms += qs_.meet_ms
+        rate = moves / (ms / 1e3) if ms > 0 else 0.0
+        per_graph.append({"n": gs[gi].n, "m": gs[gi].m, "queries": sum(q.graph == gi for q in queries),
+                          "unit_nodes": tuned[gi], "moves_per_s": rate,
+                          "achieved_GBps": BYTES_PER_MOVE * rate / 1e9,
+                          "frac": BYTES_PER_MOVE * rate / 1e9 / HBM_PEAK_GBS})
     result = {
         "metric": METRIC,
         "value": walk_steps / t_batch,
@@ -573,6 +589,7 @@ def bench_batching(args):
         "batch_results_equal_plain": same,
         "tuned_unit_nodes": tuned,
         "batch": {"moves": st.moves, "draws": st.draws, "device_ms": st.ms, "pairs": st.pairs},
+        "per_graph": per_graph,
     }
     print(json.dumps(result))
     plan.free()
