@@ -222,15 +222,8 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 // estimator's fixed-length walks: walk j of v has the class of slot pi_v(j),
 // takes no stop draw, and a meet adds Lemma 5's weight of the two classes).
 
-// Waves per SIMD the register allocation must allow: the stratified kind,
-// with its shuffle and class search at every refill, needs the full 8 to hide
-// its ALU latency; the others fit 8 by themselves and run best unconstrained.
-#ifndef SRK_MEET_MIN_WAVES_STRAT
-#define SRK_MEET_MIN_WAVES_STRAT 8
-#endif
-
 template <int KIND, int NS>
-__global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN_WAVES_STRAT : 1) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
+__global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t *__restrict__ cursor,
                                                      unsigned long long *__restrict__ counters) {
@@ -250,8 +243,9 @@ __global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN
     __shared__ uint32_t s_ccum[STRAT ? MAX_CAP + 2 : 1];
     __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
     __shared__ unsigned long long s_w[STRAT ? MEET_VB : 1];
+    __shared__ uint2 s_q[STRAT ? meet_block_of(KIND) : 1];   // 64 prepared pairs per wave
 
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n_units = ustart[nq];
     uint32_t cur_q = 0xffffffffu, cur_tile = 0xffffffffu;
     uint32_t K = 0;
@@ -317,6 +311,7 @@ __global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN
         // wave-uniform chunk of items [ci, ce) and the (node, walk) of item ci
         uint32_t ci = 0, ce = 0, cvl = 0, ck = 0;
         bool drained = false;
+        uint32_t qh = 0, qn = 0;   // stratified: the wave's queue of prepared pairs [qh, qn)
 
         Slot sl[NS];
 #pragma unroll
@@ -329,51 +324,104 @@ __global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN
             // ---- refill idle slots from the block's cursor; a lane whose item
             // has nothing to walk (the source's own pair, or a stratified walk
             // of length 0) takes the next item
+            if constexpr (STRAT) {
+                // A pair's shuffle and class search cost about a hundred
+                // instructions: they are done for 64 items at once by all
+                // lanes of the wave, and the pairs with steps to walk wait in
+                // the wave's queue in LDS until slots free up.
 #pragma unroll
-            for (int qq = 0; qq < NS; ++qq) {
-                uint64_t need = __ballot(!sl[qq].busy);
-                while (need != 0ull) {
-                    if (ci == ce) {
-                        if (drained) break;
-                        uint32_t x = 0;
-                        if (lane == 0) x = atomicAdd(&s_item, ITEM_CHUNK);
-                        x = __builtin_amdgcn_readfirstlane(x);
-                        if (x >= total) {
-                            drained = true;
-                            break;
-                        }
-                        ci = x;
-                        ce = min(x + ITEM_CHUNK, total);
-                        cvl = x / K;
-                        ck = x - cvl * K;
-                    }
-                    const uint32_t want = (uint32_t)__popcll(need);
-                    const uint32_t avail = ce - ci;
-                    const uint32_t take = avail < want ? avail : want;
-                    const uint32_t rank = lane_rank(need);
-                    const bool mine = ((need >> lane) & 1ull) && rank < take;
-                    bool filled = false;
-                    if (mine) {
-                        uint32_t k = ck + rank, vl = cvl;
-                        while (k >= K) {
-                            k -= K;
-                            ++vl;
-                        }
-                        const uint32_t id = s_vid[vl];
-                        if ((int32_t)id != src) {   // the source's own pairs are not walked
-                            const uint32_t base = s_off[k];
-                            uint32_t len = (uint32_t)s_off[k + 1] - base;
-                            if (STRAT) {
-                                const uint32_t r = shuffle_slot(s_j[k], NN, sa, sb, s_fk[vl]);
-                                const uint32_t cv = slot_class(r, s_ccum, phi);
-                                len = min(len, cv);
-                                sl[qq].aux = ((uint32_t)s_cls[k] << 8) | cv;
-                                sl[qq].rng = walk_draws_begin(id, r, key, DOM_STRAT);
-                            } else {
-                                sl[qq].rng = walk_draws_begin(id, s_j[k], key);
+                for (int qq = 0; qq < NS; ++qq) {
+                    uint64_t need = __ballot(!sl[qq].busy);
+                    while (need != 0ull) {
+                        if (qh == qn) {
+                            if (drained) break;
+                            uint32_t x = 0;
+                            if (lane == 0) x = atomicAdd(&s_item, ITEM_CHUNK);
+                            x = __builtin_amdgcn_readfirstlane(x);
+                            if (x >= total) {
+                                drained = true;
+                                break;
                             }
-                            if (len > 0) {
+                            const uint32_t item = x + (uint32_t)lane;
+                            bool ok = item < total;
+                            uint32_t vl = 0, k = 0, r = 0, cv = 0;
+                            if (ok) {
+                                vl = item / K;
+                                k = item - vl * K;
+                                ok = (int32_t)s_vid[vl] != src;
+                            }
+                            if (ok) {
+                                r = shuffle_slot(s_j[k], NN, sa, sb, s_fk[vl]);
+                                cv = slot_class(r, s_ccum, phi);
+                                ok = cv > 0u;
+                            }
+                            const uint64_t m = __ballot(ok);
+                            if (ok) s_q[wave * 64 + lane_rank(m)] = make_uint2((vl << 24) | (k << 8) | cv, r);
+                            qn = (uint32_t)__popcll(m);
+                            qh = 0;
+                            continue;
+                        }
+                        const uint32_t want = (uint32_t)__popcll(need);
+                        const uint32_t avail = qn - qh;
+                        const uint32_t take = avail < want ? avail : want;
+                        const uint32_t rank = lane_rank(need);
+                        const bool mine = ((need >> lane) & 1ull) && rank < take;
+                        if (mine) {
+                            const uint2 e = s_q[wave * 64 + qh + rank];
+                            const uint32_t vl = e.x >> 24, k = (e.x >> 8) & 0xffffu, cv = e.x & 0xffu;
+                            const uint32_t base = s_off[k];
+                            const uint32_t len = min((uint32_t)s_off[k + 1] - base, cv);
+                            const uint2 row = s_vrow[vl];
+                            sl[qq].aux = ((uint32_t)s_cls[k] << 8) | cv;
+                            sl[qq].rng = walk_draws_begin(s_vid[vl], e.y, key, DOM_STRAT);
+                            sl[qq].pos = base | (len << 16) | (vl << 24);
+                            sl[qq].t = 0;
+                            sl[qq].o = row.x;
+                            sl[qq].d = row.y;
+                            sl[qq].busy = true;
+                            ++st_pairs;
+                        }
+                        need &= ~__ballot(mine);
+                        qh += take;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < NS; ++qq) {
+                    uint64_t need = __ballot(!sl[qq].busy);
+                    while (need != 0ull) {
+                        if (ci == ce) {
+                            if (drained) break;
+                            uint32_t x = 0;
+                            if (lane == 0) x = atomicAdd(&s_item, ITEM_CHUNK);
+                            x = __builtin_amdgcn_readfirstlane(x);
+                            if (x >= total) {
+                                drained = true;
+                                break;
+                            }
+                            ci = x;
+                            ce = min(x + ITEM_CHUNK, total);
+                            cvl = x / K;
+                            ck = x - cvl * K;
+                        }
+                        const uint32_t want = (uint32_t)__popcll(need);
+                        const uint32_t avail = ce - ci;
+                        const uint32_t take = avail < want ? avail : want;
+                        const uint32_t rank = lane_rank(need);
+                        const bool mine = ((need >> lane) & 1ull) && rank < take;
+                        bool filled = false;
+                        if (mine) {
+                            uint32_t k = ck + rank, vl = cvl;
+                            while (k >= K) {
+                                k -= K;
+                                ++vl;
+                            }
+                            const uint32_t id = s_vid[vl];
+                            if ((int32_t)id != src) {   // the source's own pairs are not walked
+                                const uint32_t base = s_off[k];
+                                const uint32_t len = (uint32_t)s_off[k + 1] - base;
                                 const uint2 row = s_vrow[vl];
+                                sl[qq].rng = walk_draws_begin(id, s_j[k], key);
                                 sl[qq].pos = base | (len << 16) | (vl << 24);
                                 sl[qq].t = 0;
                                 sl[qq].o = row.x;
@@ -384,13 +432,13 @@ __global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN
                                 ++st_pairs;
                             }
                         }
-                    }
-                    need &= ~__ballot(filled);
-                    ci += take;
-                    ck += take;
-                    while (ck >= K && K > 0) {
-                        ck -= K;
-                        ++cvl;
+                        need &= ~__ballot(filled);
+                        ci += take;
+                        ck += take;
+                        while (ck >= K && K > 0) {
+                            ck -= K;
+                            ++cvl;
+                        }
                     }
                 }
             }
@@ -400,7 +448,7 @@ __global__ __launch_bounds__(meet_block_of(KIND), KIND == K_STRAT ? SRK_MEET_MIN
             // A refill round can hand out only pairs with nothing to walk: a
             // wave leaves only once the block's cursor is drained.
             if (__ballot(any) == 0ull) {
-                if (drained) break;
+                if (drained && qh == qn) break;
                 continue;
             }
 
