@@ -284,15 +284,18 @@ int simrank_index_read(const simrank_graph *g, const int64_t *sigma, int64_t cou
  * captured launch sequence (below).  outs[i]: host double[n of its graph] or
  * NULL; counts_opt (may be NULL, or entries NULL): host uint32[n].  Each
  * query's result equals what simrank_single_source_ex returns for it alone.
- * st_opt: totals over all queries; ms is device time. */
+ * Stratified queries may be mixed in: outs[i] receives Algorithm 2's estimate
+ * (as simrank_single_source_stratified's out) and counts_opt[i] is not
+ * written.  st_opt: totals over all queries; ms is device time. */
 int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs, const simrank_query *qs,
                   int32_t nq, double *const *outs, uint32_t *const *counts_opt,
                   simrank_stats *st_opt);
 
 /* A batch plan owns the device buffers of nq queries and a hipGraph of their
  * whole launch sequence: source walks of every query, compaction, one
- * persistent meet launch whose work units span all queries, estimates.  It can
- * be run any number of times.  ENOMEM if its buffers exceed free memory. */
+ * persistent meet launch per kind whose work units span all its queries,
+ * estimates.  It can be run any number of times.  ENOMEM if its buffers
+ * exceed free memory. */
 typedef struct simrank_batch_plan simrank_batch_plan;
 int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
                               const simrank_query *qs, int32_t nq, simrank_batch_plan **plan_out);
@@ -301,9 +304,15 @@ int simrank_batch_plan_run(simrank_batch_plan *plan, void *stream);
 /* Waits for the last run; st (may be NULL) receives totals and its device time. */
 int simrank_batch_plan_wait(simrank_batch_plan *plan, simrank_stats *st);
 /* Copies query i's estimate (host double[n], may be NULL) and counts (host
- * uint32[n], may be NULL) after the last run. */
+ * uint32[n], may be NULL) after the last run.  EINVAL for counts of a
+ * stratified query. */
 int simrank_batch_plan_read(simrank_batch_plan *plan, int32_t i, double *out_host,
                             uint32_t *counts_host);
+/* A stratified query's results after the last run, as
+ * simrank_single_source_stratified returns them (each host pointer may be
+ * NULL): out double[n], out_n double[n], wsum uint64[n]. */
+int simrank_batch_plan_read_stratified(simrank_batch_plan *plan, int32_t i, double *out_host,
+                                       double *out_n_host, uint64_t *wsum_host);
 int simrank_batch_plan_free(simrank_batch_plan *plan);
 
 /* Measures the meet kernel of query q on g for each work-unit size (nodes per

@@ -3,7 +3,8 @@
 // A plan holds the device buffers of a set of queries (carved from one
 // allocation) and a hipGraph of the whole launch sequence: init, source walks
 // of every query, compaction, work-unit offsets, one persistent meet launch
-// whose work units span all queries (per kind: plain, stitched), estimate.
+// whose work units span all queries (per kind: plain, stitched, stratified),
+// estimate.
 // Queries on graphs of very different sizes share the launch and its tail.
 // Each query's result is exactly the one a lone simrank_single_source_ex call
 // returns: results depend only on (graph, query).
@@ -19,13 +20,19 @@ constexpr size_t ARENA_ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1); }
 
-// Device bytes one query needs in a plan.
-size_t query_bytes(const simrank_params &p, int32_t n) {
+// Device bytes one query needs in a plan (stratified queries: class table,
+// walk classes, weighted sums and the second estimate instead of counts).
+size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
     const size_t RL = (size_t)p.R * (size_t)p.L;
-    return align_up(4 * RL) + align_up((size_t)p.R) + align_up(4 * (size_t)p.R) +
-           align_up(4 * ((size_t)p.R + 1)) + align_up(4 * RL) +
-           align_up(4 * ((size_t)max_tiles_for(p.R, p.L) + 1)) + align_up(32) +
-           align_up(4 * (size_t)n) + align_up(8 * (size_t)n);
+    size_t b = align_up(4 * RL) + align_up((size_t)p.R) + align_up(4 * (size_t)p.R) +
+               align_up(4 * ((size_t)p.R + 1)) + align_up(4 * RL) +
+               align_up(4 * ((size_t)max_tiles_for(p.R, p.L) + 1)) + align_up(32) +
+               align_up(8 * (size_t)n);
+    if (mode == SIMRANK_MODE_STRATIFIED)
+        b += align_up(sizeof(StratTab)) + align_up((size_t)p.R) + 2 * align_up(8 * (size_t)n);
+    else
+        b += align_up(4 * (size_t)n);
+    return b;
 }
 
 }  // namespace
@@ -77,9 +84,6 @@ static int check_queries(simrank_graph *const *graphs, int32_t ngraphs, const si
         const simrank_graph *g = graphs[q.graph];
         int rc = query_params(&q, g->n, &ps[i], &modes[i]);
         if (rc) return fail(rc, "query " + std::to_string(i) + ": " + simrank_last_error());
-        if (modes[i] == SIMRANK_MODE_STRATIFIED)
-            return fail(SIMRANK_EINVAL, "query " + std::to_string(i) +
-                                            ": stratified queries are not batched");
         if (q.s < 0 || q.s >= g->n)
             return fail(SIMRANK_EINVAL, "query " + std::to_string(i) + ": source out of range");
         if (modes[i] == SIMRANK_MODE_STITCHED && (!g->index || g->index->T != ps[i].T))
@@ -116,7 +120,7 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
     size_t total = 0;
-    for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], graphs[qs[i].graph]->n);
+    for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], modes[i], graphs[qs[i].graph]->n);
     size_t free_b = 0, tot_b = 0;
     if (hipMemGetInfo(&free_b, &tot_b) == hipSuccess && total > free_b)
         return bail(fail(SIMRANK_ENOMEM, "batch needs " + std::to_string(total) +
@@ -149,8 +153,23 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
         d.swc = (uint32_t *)take(4 * RL);
         d.tiles = (uint32_t *)take(4 * ((size_t)max_tiles_for(pp.R, pp.L) + 1));
         d.meta = (uint32_t *)take(32);
-        d.cnt = (uint32_t *)take(4 * (size_t)g->n);
         d.out = (double *)take(8 * (size_t)g->n);
+        if (modes[i] == SIMRANK_MODE_STRATIFIED) {
+            StratParams sp;
+            StratTab tab{};
+            if ((rc = strat_params(&qs[i], g->n, &sp, &tab))) return bail(rc);
+            d.tab = (const StratTab *)take(sizeof(StratTab));
+            d.scls = (uint8_t *)take((size_t)pp.R);
+            d.wsum = (unsigned long long *)take(8 * (size_t)g->n);
+            d.out_n = (double *)take(8 * (size_t)g->n);
+            d.z = sp.z;
+            d.sa = sp.sa;
+            d.sb = sp.sb;
+            e = hipMemcpy((void *)d.tab, &tab, sizeof(StratTab), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+        } else {
+            d.cnt = (uint32_t *)take(4 * (size_t)g->n);
+        }
         p->graphs[i] = g;
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
@@ -236,8 +255,28 @@ extern "C" int simrank_batch_plan_read(simrank_batch_plan *p, int32_t i, double 
     SRK_HIP(hipSetDevice(p->device));
     SRK_HIP(hipEventSynchronize(p->ev1));
     const size_t n = (size_t)p->graphs[i]->n;
+    if (counts_host && p->desc[i].kind == K_STRAT)
+        return fail(SIMRANK_EINVAL, "a stratified query has weighted sums, not counts: "
+                                    "use simrank_batch_plan_read_stratified");
     if (out_host) SRK_HIP(hipMemcpy(out_host, p->desc[i].out, 8 * n, hipMemcpyDeviceToHost));
     if (counts_host) SRK_HIP(hipMemcpy(counts_host, p->desc[i].cnt, 4 * n, hipMemcpyDeviceToHost));
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_read_stratified(simrank_batch_plan *p, int32_t i,
+                                                  double *out_host, double *out_n_host,
+                                                  uint64_t *wsum_host) {
+    clear_error();
+    if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
+    if (i < 0 || i >= p->nq) return fail(SIMRANK_EINVAL, "query index out of range");
+    if (p->desc[i].kind != K_STRAT) return fail(SIMRANK_EINVAL, "not a stratified query");
+    if (!p->ran) return fail(SIMRANK_ESTATE, "plan has not run");
+    SRK_HIP(hipSetDevice(p->device));
+    SRK_HIP(hipEventSynchronize(p->ev1));
+    const size_t n = (size_t)p->graphs[i]->n;
+    if (out_host) SRK_HIP(hipMemcpy(out_host, p->desc[i].out, 8 * n, hipMemcpyDeviceToHost));
+    if (out_n_host) SRK_HIP(hipMemcpy(out_n_host, p->desc[i].out_n, 8 * n, hipMemcpyDeviceToHost));
+    if (wsum_host) SRK_HIP(hipMemcpy(wsum_host, p->desc[i].wsum, 8 * n, hipMemcpyDeviceToHost));
     return SIMRANK_OK;
 }
 
@@ -274,7 +313,8 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         size_t used = 0;
         int32_t i1 = i0;
         while (i1 < nq) {
-            const size_t b = query_bytes(ps[i1], graphs[qs[i1].graph]->n) + sizeof(QueryDesc) + 64;
+            const size_t b =
+                query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) + sizeof(QueryDesc) + 64;
             if (i1 > i0 && used + b > budget) break;
             used += b;
             ++i1;
@@ -288,9 +328,10 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         simrank_stats s1{};
         if (!rc) rc = simrank_batch_plan_run(p, st);
         if (!rc) rc = simrank_batch_plan_wait(p, &s1);
-        for (int32_t i = i0; i < i1 && !rc; ++i)
+        for (int32_t i = i0; i < i1 && !rc; ++i)   // stratified queries have no counts
             rc = simrank_batch_plan_read(p, i - i0, outs ? outs[i] : nullptr,
-                                         counts_opt ? counts_opt[i] : nullptr);
+                                         counts_opt && modes[i] != SIMRANK_MODE_STRATIFIED
+                                             ? counts_opt[i] : nullptr);
         if (st) (void)hipStreamDestroy(st);
         simrank_batch_plan_free(p);
         tot.pairs += s1.pairs;

@@ -136,6 +136,7 @@ def lib() -> C.CDLL:
         "simrank_batch_plan_run": [vp, vp],
         "simrank_batch_plan_wait": [vp, P(simrank_stats)],
         "simrank_batch_plan_read": [vp, i32, vp, vp],
+        "simrank_batch_plan_read_stratified": [vp, i32, vp, vp, vp],
         "simrank_batch_plan_free": [vp],
         "simrank_tune": [vp, P(simrank_query), P(i32)],
         "simrank_server_create": [vp, P(simrank_server_params), P(vp)],
@@ -405,6 +406,7 @@ def simrank_index_read(g: Graph, sigma, with_chain: bool = True):
 
 
 def simrank_batch(graphs: list[Graph], queries: list[simrank_query], want_counts: bool = True):
+    """(outs, counts, stats); a stratified query's counts entry is left unwritten."""
     ng = len(graphs)
     nq = len(queries)
     garr = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
@@ -472,6 +474,14 @@ class BatchPlan:
                                              _ptr(out) if out is not None else None,
                                              _ptr(cnt) if cnt is not None else None))
         return out, cnt
+
+    def read_stratified(self, i: int):
+        """(out, out_n, wsum) of stratified query i after the last run."""
+        n = self.graphs[self.queries[i].graph].n
+        out, out_n, wsum = np.empty(n), np.empty(n), np.empty(n, np.uint64)
+        _check(lib().simrank_batch_plan_read_stratified(self.handle, i, _ptr(out), _ptr(out_n),
+                                                        _ptr(wsum)))
+        return out, out_n, wsum
 
     def free(self) -> None:
         if self.handle and self.handle.value:

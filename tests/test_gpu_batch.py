@@ -112,3 +112,30 @@ def test_batch_rejects_bad_queries(graphs):
     q = S.make_query(1, graph=2, mode=S.MODE_STITCHED)       # graph 2 has no index
     with pytest.raises(S.SimRankError):
         S.simrank_batch(Gs, [q])
+
+
+def test_batch_with_stratified_queries(graphs):
+    """Stratified queries mixed into a batch (and a captured plan) give what
+    the lone stratified call gives, bit for bit."""
+    gs, Gs = graphs
+    mix = _mix(gs, 12, 5)
+    strat = [S.make_stratified_query(q.s, c=0.6, eps=0.2, seed=2000 + i, z=700 + 50 * i, phi=12,
+                                     graph=q.graph) for i, q in enumerate(mix[:6])]
+    qs = [x for pair in zip(mix[6:], strat) for x in pair]
+    outs, cnts, st = S.simrank_batch(Gs, qs)
+    plan = S.BatchPlan(Gs, qs)
+    plan.run()
+    plan.wait()
+    for i, q in enumerate(qs):
+        if q.mode == S.MODE_STRATIFIED:
+            o1, on1, w1, _ = S.simrank_single_source_stratified(Gs[q.graph], q)
+            assert np.array_equal(outs[i], o1), i
+            o, on, w = plan.read_stratified(i)
+            assert np.array_equal(w, w1) and np.array_equal(on, on1) and np.array_equal(o, o1), i
+            with pytest.raises(S.SimRankError):
+                plan.read(i, want_out=False, want_counts=True)
+        else:
+            o1, c1, _ = S.simrank_single_source_ex(Gs[q.graph], q)
+            assert np.array_equal(cnts[i], c1) and np.array_equal(outs[i], o1), i
+            assert np.array_equal(plan.read(i)[1], c1), i
+    plan.free()
