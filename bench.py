@@ -463,8 +463,18 @@ def bench_stitching(args):
     torch.cuda.synchronize()
     qs = time.perf_counter() - t1
     assert st.moves == st0.moves
+    # the same source with plain walks (no index), and the machine's random
+    # 8-byte gather rate over a buffer of the graph's size (HBM-bound here)
+    qp = S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
+                      walk_cap=cfg["L"])
+    S.simrank_single_source_async(G, qp, ws, out, cnt, stream)
+    stp = S.simrank_workspace_stats(ws)
+    gi = G.info()
+    footprint = 8 * (gi["m"] + gi["n"] - gi["n_active"])
+    gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
     build_ms = float(np.mean([b["build_ms"] for b in builds]))
     walk_steps = st.moves + st.tail_steps + st.source_moves
+    steps_per_s = (st.moves + st.tail_steps) / (st.meet_ms / 1e3)
     result = {
         "metric": METRIC,
         "value": walk_steps / qs,
@@ -485,6 +495,20 @@ def bench_stitching(args):
         },
         "query": {"moves": st.moves, "tail_steps": st.tail_steps, "draws": st.draws,
                   "meet_ms": st.meet_ms, "ms": st.ms, "pairs_walked": st.pairs_walked},
+        "plain_query": {"moves": stp.moves, "meet_ms": stp.meet_ms, "ms": stp.ms},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_meet<stitched> (fused walk + meet + count)",
+            "achieved": BYTES_PER_MOVE * steps_per_s / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": BYTES_PER_MOVE * steps_per_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "measured_roofs": {"footprint_bytes": footprint,
+                           "random_gather_8B_per_s": gather["per_s"],
+                           "kernel_steps_per_s": steps_per_s,
+                           "steps_vs_random_gather": steps_per_s / gather["per_s"]},
     }
     print(json.dumps(result))
     ws.free()
@@ -643,14 +667,21 @@ def bench_serving(args):
         S.simrank_workspace_stats(ws)
     t1 = time.perf_counter()
     steps = 0
+    kmoves, kms = 0, 0.0
     for q in cap_q:
         S.simrank_single_source_async(G, q, ws, out, cnt, stream)
         st = S.simrank_workspace_stats(ws)
         steps += st.moves + st.tail_steps + st.source_moves
+        kmoves += st.moves + st.tail_steps
+        kms += st.meet_ms
         _ = out.cpu()                       # results to host, as a served request has
     plain_s = time.perf_counter() - t1
     capacity = len(cap_q) / plain_s
     ws.free()
+    gi = G.info()
+    footprint = 8 * (gi["m"] + gi["n"] - gi["n_active"])
+    gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
+    kernel_rate = kmoves / (kms / 1e3)
     srv = S.Server(G, max_slots=4, max_R=9502, max_L=cfg["L"])
     levels = []
     k = 1000
@@ -699,6 +730,19 @@ def bench_serving(args):
         "plain_queries_per_s": capacity,
         "served_vs_plain": top["achieved_qps"] / capacity,
         "levels": levels,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_meet<stitched> (fused walk + meet + count), requests one at a time",
+            "achieved": BYTES_PER_MOVE * kernel_rate / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": BYTES_PER_MOVE * kernel_rate / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "measured_roofs": {"footprint_bytes": footprint,
+                           "random_gather_8B_per_s": gather["per_s"],
+                           "kernel_steps_per_s": kernel_rate,
+                           "steps_vs_random_gather": kernel_rate / gather["per_s"]},
     }
     print(json.dumps(result))
     srv.destroy()
