@@ -62,15 +62,26 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 #ifndef SRK_SMALL_MEET_BLOCK
 #define SRK_SMALL_MEET_BLOCK 512
 #endif
+#ifndef SRK_STITCH_TILE_J
+#define SRK_STITCH_TILE_J SRK_SMALL_TILE_J
+#endif
+#ifndef SRK_STITCH_TILE_NODES
+#define SRK_STITCH_TILE_NODES SRK_SMALL_TILE_NODES
+#endif
+#ifndef SRK_STITCH_MEET_BLOCK
+#define SRK_STITCH_MEET_BLOCK SRK_SMALL_MEET_BLOCK
+#endif
 constexpr int MEET_VB = 256;                // nodes v per work unit, at most
 __host__ __device__ constexpr int tile_j_of(int kind) {
-    return kind == K_PLAIN ? SRK_TILE_J : SRK_SMALL_TILE_J;
+    return kind == K_PLAIN ? SRK_TILE_J : kind == K_STITCHED ? SRK_STITCH_TILE_J : SRK_SMALL_TILE_J;
 }
 __host__ __device__ constexpr int tile_nodes_of(int kind) {   // < 2^16
-    return kind == K_PLAIN ? SRK_TILE_NODES : SRK_SMALL_TILE_NODES;
+    return kind == K_PLAIN ? SRK_TILE_NODES
+           : kind == K_STITCHED ? SRK_STITCH_TILE_NODES : SRK_SMALL_TILE_NODES;
 }
 __host__ __device__ constexpr int meet_block_of(int kind) {
-    return kind == K_PLAIN ? SRK_MEET_BLOCK : SRK_SMALL_MEET_BLOCK;
+    return kind == K_PLAIN ? SRK_MEET_BLOCK
+           : kind == K_STITCHED ? SRK_STITCH_MEET_BLOCK : SRK_SMALL_MEET_BLOCK;
 }
 
 // ------------------------------------------------------------ device graph

@@ -65,7 +65,8 @@ struct Slot {
     uint32_t o, d;   // current node: slot offset in E and in-degree
     WalkDraws rng;
     bool busy;
-    bool in_tail;    // stitched: the private head is complete
+    uint32_t ph;     // stitched: 0 head; entering the tail: 1 node id, 2 pool offsets,
+                     // 3 segment length; 4 tail step; next segment: 5 chain, 6 its length
     uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position, segment, its length
     uint32_t aux;    // stratified: class of walk (s, j) << 8 | class of walk (v, j)
 };

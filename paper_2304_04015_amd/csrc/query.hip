@@ -317,7 +317,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
 #pragma unroll
         for (int qq = 0; qq < NS; ++qq) {
             sl[qq].busy = false;
-            sl[qq].in_tail = false;
+            sl[qq].ph = 0;
         }
 
         for (;;) {
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                                 sl[qq].o = row.x;
                                 sl[qq].d = row.y;
                                 sl[qq].busy = true;
-                                sl[qq].in_tail = false;
+                                sl[qq].ph = 0;
                                 filled = true;
                                 ++st_pairs;
                             }
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             for (int qq = 0; qq < NS; ++qq) {
                 go[qq] = false;
                 at[qq] = 0;
-                if (sl[qq].busy && !(STITCHED && sl[qq].in_tail)) {
+                if (sl[qq].busy && !(STITCHED && sl[qq].ph)) {
                     ++sl[qq].t;
                     const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
@@ -471,10 +471,26 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                     }
                 }
             }
+            // one load per slot: a head step's gather, or the load its stitched
+            // tail phase needs, so that their latencies overlap
             uint2 e[NS];
+            uint32_t tv[NS];
+            int64_t tb[NS], te[NS];
 #pragma unroll
-            for (int qq = 0; qq < NS; ++qq)
+            for (int qq = 0; qq < NS; ++qq) {
                 if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
+                if (STITCHED && sl[qq].busy && sl[qq].ph) {
+                    const Slot &w = sl[qq];
+                    switch (w.ph) {
+                    case 1: tv[qq] = d.ix.node_of[w.o]; break;
+                    case 2: tb[qq] = d.ix.pool_off[w.tsig]; te[qq] = d.ix.pool_off[w.tsig + 1]; break;
+                    case 3:
+                    case 6: tv[qq] = d.ix.seg_lens[w.tseg]; break;
+                    case 4: tv[qq] = d.ix.seg[(size_t)w.tseg * d.ix.seg_len + w.tu]; break;
+                    default: tv[qq] = d.ix.chain[(size_t)w.tsig * d.ix.width + w.tm + 1]; break;
+                    }
+                }
+            }
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 if (!go[qq]) continue;
@@ -493,47 +509,62 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                 } else if (w.t == len || w.d == 0u) {
                     w.busy = false;
                 } else if (STITCHED && w.t == (uint32_t)d.ix.seg_len) {
-                    const uint32_t y = d.ix.node_of[w.o];
-                    w.tsig = entry_slot(d.ix, key, s_vid[w.pos >> 24], w.rng.j, y);
-                    w.tm = 0;
-                    w.tu = 0;
-                    w.tseg = w.tsig;
-                    w.tsl = d.ix.seg_lens[w.tseg];
-                    w.in_tail = true;
-                    if (w.tsl == 0u) w.busy = false;
+                    w.ph = 1;   // the head made all its moves: enter a pool slot of this node
                 }
             }
-            // ---- stitched tails: one step read from the index
+            // ---- stitched tails: entry slot, then one step read from the index
+            // per iteration, and the chain of segments
             if (STITCHED) {
 #pragma unroll
                 for (int qq = 0; qq < NS; ++qq) {
                     Slot &w = sl[qq];
-                    if (!(w.busy && w.in_tail) || go[qq]) continue;
-                    ++w.t;
-                    ++st_tail;
-                    w.o = d.ix.seg[(size_t)w.tseg * d.ix.seg_len + w.tu];
-                    ++w.tu;
-                    const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
-                    if (w.o == s_nodes[base + w.t - 1]) {
-                        atomicAdd(&s_cnt[w.pos >> 24], 1u);
-                        ++st_meets;
-                        w.busy = false;
-                    } else if (w.t == len) {
-                        w.busy = false;
-                    } else if (w.tu == w.tsl) {
-                        if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width) {
+                    if (!(w.busy && w.ph) || go[qq]) continue;
+                    switch (w.ph) {
+                    case 1:   // the end node's id
+                        w.tsig = tv[qq];
+                        w.ph = 2;
+                        break;
+                    case 2: { // its pool: slot picked by draw (v, j, 0, DOM_ENTRY)
+                        const uint4 x = philox4x32_10(s_vid[w.pos >> 24], w.rng.j, 0u, DOM_ENTRY, key);
+                        w.tsig = (uint32_t)(tb[qq] + (int64_t)pick64(x.x, (uint64_t)(te[qq] - tb[qq])));
+                        w.tseg = w.tsig;
+                        w.tm = 0;
+                        w.ph = 3;
+                        break;
+                    }
+                    case 3:
+                    case 6:   // a segment's length
+                        w.tsl = tv[qq];
+                        w.tu = 0;
+                        w.ph = 4;
+                        if (w.tsl == 0u) w.busy = false;
+                        break;
+                    case 4: { // one tail step
+                        ++w.t;
+                        ++st_tail;
+                        w.o = tv[qq];
+                        ++w.tu;
+                        const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
+                        if (w.o == s_nodes[base + w.t - 1]) {
+                            atomicAdd(&s_cnt[w.pos >> 24], 1u);
+                            ++st_meets;
                             w.busy = false;
-                        } else {
-                            ++w.tm;
-                            w.tseg = d.ix.chain[(size_t)w.tsig * d.ix.width + w.tm];
-                            w.tu = 0;
-                            if (w.tseg == NIL) {
+                        } else if (w.t == len) {
+                            w.busy = false;
+                        } else if (w.tu == w.tsl) {
+                            if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width)
                                 w.busy = false;
-                            } else {
-                                w.tsl = d.ix.seg_lens[w.tseg];
-                                if (w.tsl == 0u) w.busy = false;
-                            }
+                            else
+                                w.ph = 5;
                         }
+                        break;
+                    }
+                    default:  // the chain's next segment
+                        ++w.tm;
+                        w.tseg = tv[qq];
+                        if (w.tseg == NIL) w.busy = false;
+                        else w.ph = 6;
+                        break;
                     }
                 }
             }
@@ -716,8 +747,9 @@ IndexView index_view(const Graph *g) {
 
 // Tiles of R walks of cap L, at most, for any kind (the smallest shape).
 int32_t max_tiles_for(int32_t R, int32_t L) {
-    const int64_t TJ = std::min(tile_j_of(K_PLAIN), tile_j_of(K_STITCHED));
-    const int64_t NW = std::min(tile_nodes_of(K_PLAIN), tile_nodes_of(K_STITCHED)) - L;
+    const int64_t TJ = std::min({tile_j_of(K_PLAIN), tile_j_of(K_STITCHED), tile_j_of(K_STRAT)});
+    const int64_t NW =
+        std::min({tile_nodes_of(K_PLAIN), tile_nodes_of(K_STITCHED), tile_nodes_of(K_STRAT)}) - L;
     return (int32_t)(2 + R / TJ + ((int64_t)R * L) / NW);
 }
 
