@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the queries, copy a buffer of this many MiB once (a kernel "
                          "of known traffic that calibrates the profiler's byte counters)")
+    ap.add_argument("--tune", action="store_true",
+                    help="medium: run the work-unit tuner on the graph before timing")
     ap.add_argument("--no-roofs", action="store_true",
                     help="skip the measured gather / Philox / copy ceilings")
     ap.add_argument("--scale", type=int, default=0,
@@ -136,6 +138,7 @@ def main():
     queries = [S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
                             seed=cfg["walk_seed"], walk_cap=cfg["L"]) for s in sources]
     R = S.simrank_derive_params(queries[0], g.n).R
+    tuned = S.simrank_tune(G, queries[0]) if args.tune else None
     stream = torch.cuda.Stream()
     wss = [S.simrank_workspace_create(G, R, cfg["L"]) for _ in queries]
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in queries]
@@ -189,6 +192,7 @@ def main():
                         "permuted; c=0.6 eps=0.02 delta=1e-3 R=9502 L=64; "
                         "8 single-source queries per step",
             "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries_per_step": len(queries),
+            "unit_nodes": tuned if tuned else "default",
         },
         "queries_per_s": nq / elapsed,
         "pairs_per_s": sum(st.pairs for st in ref) * args.steps / elapsed,

@@ -703,11 +703,11 @@ __global__ __launch_bounds__(256) void k_walks_strat(StratWalkArgs a) {
 #define SRK_MEET_SLOTS_STRAT 2
 #endif
 
-// Resident blocks of a meet-kernel instance on the whole device.
+// Resident blocks of a meet-kernel instance on the whole device (computed
+// once per process; a function-local static is initialised thread-safely).
 template <int KIND, int NS>
 int meet_grid_blocks() {
-    static int blocks = 0;
-    if (blocks == 0) {
+    static const int blocks = [] {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -715,8 +715,8 @@ int meet_grid_blocks() {
                                                            meet_block_of(KIND), 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
-        blocks = cus * per;
-    }
+        return cus * per;
+    }();
     return blocks;
 }
 

@@ -419,6 +419,8 @@ def simrank_batch(graphs: list[Graph], queries: list[simrank_query], want_counts
     carr = (C.c_void_p * nq)(*[c.ctypes.data for c in cnts]) if want_counts else None
     st = simrank_stats()
     _check(lib().simrank_batch(garr, ng, qarr, nq, oarr, carr, C.byref(st)))
+    if cnts is not None:
+        cnts = [None if q.mode == MODE_STRATIFIED else c for q, c in zip(queries, cnts)]
     return outs, cnts, st
 
 
