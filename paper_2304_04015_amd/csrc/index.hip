@@ -72,6 +72,10 @@ struct SegArgs {
     int64_t segments;
 };
 
+// One segment per thread.  Consecutive slots belong to the same node y, so a
+// wave's first steps share y's row.  The segment's positions are kept in
+// registers and written four at a time (one 16-byte store per lane: a wave's
+// rows form one contiguous span) instead of one scattered word per step.
 __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
     const int64_t sigma = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t len = 0;
@@ -80,14 +84,29 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
         const uint32_t i = (uint32_t)(sigma - a.pool_off[y]);
         uint32_t *row = a.seg + (size_t)sigma * a.seg_len;
         uint2 cur = a.nodes[y];
-        for (int32_t t = 1; t <= a.seg_len; ++t) {
-            const uint4 x = philox4x32_10(y, i, (uint32_t)t, DOM_SEGMENT, a.key);
-            if (x.x >= a.T || cur.y == 0) break;
-            cur = a.E[cur.x + pick32(x.y, cur.y)];
-            row[t - 1] = cur.x;
-            len = (uint32_t)t;
+        WalkDraws w = walk_draws_begin(y, i, a.key, DOM_SEGMENT);
+        bool alive = true;
+        for (int32_t t0 = 0; t0 < a.seg_len; t0 += 4) {
+            uint32_t p[4] = {NIL, NIL, NIL, NIL};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (alive && t0 + q < a.seg_len) {
+                    const uint2 x = walk_draw_next(w, a.key);   // step t0 + q + 1
+                    if (x.x >= a.T || cur.y == 0) {
+                        alive = false;
+                    } else {
+                        cur = a.E[cur.x + pick32(x.y, cur.y)];
+                        p[q] = cur.x;
+                        ++len;
+                    }
+                }
+            }
+            if (a.seg_len >= 4) {
+                *(uint4 *)(row + t0) = make_uint4(p[0], p[1], p[2], p[3]);
+            } else {
+                for (int32_t q = 0; q < a.seg_len; ++q) row[q] = p[q];
+            }
         }
-        for (int32_t t = (int32_t)len; t < a.seg_len; ++t) row[t] = NIL;
         a.seg_lens[sigma] = (uint8_t)len;
         uint32_t nx = NIL;
         if ((int32_t)len == a.seg_len) {
@@ -98,7 +117,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
             nx = (uint32_t)(b + (int64_t)pick64(x.x, (uint64_t)P));
         }
         a.succ[sigma] = nx;
-        a.chain[(size_t)sigma * a.width] = (uint32_t)sigma;
+        if (a.width == 1) a.chain[sigma] = (uint32_t)sigma;   // no doubling round writes it
     }
     unsigned long long m = len;
     for (int d = 32; d > 0; d >>= 1) m += __shfl_xor(m, d, 64);
@@ -107,7 +126,10 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
 
 // Round r of pointer doubling: chain[s][h + i] = chain[J[s]][i] for i < h = 2^r,
 // Jn[s] = J[J[s]].  Reads touch columns < h and writes columns >= h, so the
-// round can update chain in place.
+// round can update chain in place.  Round 0 writes columns 0 and 1 together:
+// chain[s][0] = s and chain[s][1] = J[s] = succ(s) (column 0 of any row is the
+// row's own slot), without reading another row.  Columns move in 8- or 16-byte
+// pieces.
 __global__ __launch_bounds__(256) void k_double(uint32_t *__restrict__ chain,
                                                 const uint32_t *__restrict__ J,
                                                 uint32_t *__restrict__ Jn, int64_t segments,
@@ -115,15 +137,20 @@ __global__ __launch_bounds__(256) void k_double(uint32_t *__restrict__ chain,
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= segments) return;
     const uint32_t a = J[s];
-    uint32_t *dst = chain + (size_t)s * width + h;
-    if (a == NIL) {
-        for (int32_t i = 0; i < h; ++i) dst[i] = NIL;
-        if (Jn) Jn[s] = NIL;
-    } else {
-        const uint32_t *src = chain + (size_t)a * width;
-        for (int32_t i = 0; i < h; ++i) dst[i] = src[i];
-        if (Jn) Jn[s] = J[a];
+    uint32_t *row = chain + (size_t)s * width;
+    if (Jn) Jn[s] = (a == NIL) ? NIL : J[a];
+    if (h == 1) {
+        *(uint2 *)row = make_uint2((uint32_t)s, a);
+        return;
     }
+    uint32_t *dst = row + h;
+    const uint32_t *src = chain + (size_t)a * width;
+    if (h == 2) {
+        *(uint2 *)dst = (a == NIL) ? make_uint2(NIL, NIL) : *(const uint2 *)src;
+        return;
+    }
+    for (int32_t k = 0; k < h; k += 4)
+        *(uint4 *)(dst + k) = (a == NIL) ? make_uint4(NIL, NIL, NIL, NIL) : *(const uint4 *)(src + k);
 }
 
 struct ReadArgs {
