@@ -35,15 +35,17 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 
 
 // Meet-kernel tiling of the compacted source walks (see query.hip), per kind.
-// The plain kind is bound by L1 misses on a graph that sits in the Infinity
-// Cache: a tile of up to 8192 walks and 24576 positions (148 KB of LDS with
-// the kernel's other arrays: one 1024-thread block per CU) keeps about 5,600
-// walks of one node in a block, whose early steps then share rows in the L1;
-// on the medium workload it measured 50.7 ms per query against 58.9 ms with
-// 1024 / 4096 tiles and 512-thread blocks.  The stitched kind (graphs beyond
-// the Infinity Cache, tails read from the index) needs more pairs in flight
-// per CU instead, and the stratified kind is bound by its per-pair ALU work:
-// both keep 1024 / 4096 tiles and 512-thread blocks (four blocks per CU).
+// The more walks of one node a block holds, the more of their early steps
+// share rows in the CU's L1; LDS bounds the tile.  Measured per query:
+//  - plain (medium graph, in the Infinity Cache): 1024-thread blocks, tiles of
+//    up to 8192 walks / 24576 positions (148 KB of LDS, one block per CU):
+//    50.5 ms, against 58.9 ms with 512 threads and 1024 / 4096;
+//  - stratified (medium graph; its LDS also holds classes, shuffle keys and a
+//    queue of prepared pairs): 1024 threads, 6144 / 20480: 99.6 ms, against
+//    114.1 ms with 512 threads and 1024 / 4096;
+//  - stitched (n = 2^24, beyond the Infinity Cache, tails read from the index:
+//    it needs more pairs in flight per CU): 512 threads, 2048 / 8192: 963 ms,
+//    against 984 ms with 1024 / 4096 and 1200 ms with the plain kind's shape.
 #ifndef SRK_TILE_J
 #define SRK_TILE_J 8192
 #endif
@@ -53,35 +55,35 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 #ifndef SRK_MEET_BLOCK
 #define SRK_MEET_BLOCK 1024
 #endif
-#ifndef SRK_SMALL_TILE_J
-#define SRK_SMALL_TILE_J 1024
-#endif
-#ifndef SRK_SMALL_TILE_NODES
-#define SRK_SMALL_TILE_NODES 4096
-#endif
-#ifndef SRK_SMALL_MEET_BLOCK
-#define SRK_SMALL_MEET_BLOCK 512
-#endif
 #ifndef SRK_STITCH_TILE_J
-#define SRK_STITCH_TILE_J SRK_SMALL_TILE_J
+#define SRK_STITCH_TILE_J 2048
 #endif
 #ifndef SRK_STITCH_TILE_NODES
-#define SRK_STITCH_TILE_NODES SRK_SMALL_TILE_NODES
+#define SRK_STITCH_TILE_NODES 8192
 #endif
 #ifndef SRK_STITCH_MEET_BLOCK
-#define SRK_STITCH_MEET_BLOCK SRK_SMALL_MEET_BLOCK
+#define SRK_STITCH_MEET_BLOCK 512
+#endif
+#ifndef SRK_STRAT_TILE_J
+#define SRK_STRAT_TILE_J 6144
+#endif
+#ifndef SRK_STRAT_TILE_NODES
+#define SRK_STRAT_TILE_NODES 20480
+#endif
+#ifndef SRK_STRAT_MEET_BLOCK
+#define SRK_STRAT_MEET_BLOCK 1024
 #endif
 constexpr int MEET_VB = 256;                // nodes v per work unit, at most
 __host__ __device__ constexpr int tile_j_of(int kind) {
-    return kind == K_PLAIN ? SRK_TILE_J : kind == K_STITCHED ? SRK_STITCH_TILE_J : SRK_SMALL_TILE_J;
+    return kind == K_PLAIN ? SRK_TILE_J : kind == K_STITCHED ? SRK_STITCH_TILE_J : SRK_STRAT_TILE_J;
 }
 __host__ __device__ constexpr int tile_nodes_of(int kind) {   // < 2^16
     return kind == K_PLAIN ? SRK_TILE_NODES
-           : kind == K_STITCHED ? SRK_STITCH_TILE_NODES : SRK_SMALL_TILE_NODES;
+           : kind == K_STITCHED ? SRK_STITCH_TILE_NODES : SRK_STRAT_TILE_NODES;
 }
 __host__ __device__ constexpr int meet_block_of(int kind) {
     return kind == K_PLAIN ? SRK_MEET_BLOCK
-           : kind == K_STITCHED ? SRK_STITCH_MEET_BLOCK : SRK_SMALL_MEET_BLOCK;
+           : kind == K_STITCHED ? SRK_STITCH_MEET_BLOCK : SRK_STRAT_MEET_BLOCK;
 }
 
 // ------------------------------------------------------------ device graph
