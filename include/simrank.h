@@ -299,6 +299,20 @@ int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs, const simrank_q
 typedef struct simrank_batch_plan simrank_batch_plan;
 int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
                               const simrank_query *qs, int32_t nq, simrank_batch_plan **plan_out);
+/* Flags of simrank_batch_plan_create_ex. */
+#define SIMRANK_PLAN_GROUPS 1u
+/* simrank_batch_plan_create with flags (simrank_batch_plan_create and
+ * simrank_batch pass SIMRANK_PLAN_GROUPS).  SIMRANK_PLAN_GROUPS: plain queries
+ * on one graph with equal seed, c and walk cap are run in groups of up to 8
+ * that share the walks from every node (Section 3's walk (v, j) depends on the
+ * seed, c and cap only, not on the source): each walk (v, j) is taken once
+ * and compared with walk j of every member's source.  Results are bit for bit
+ * those without the flag; the stats count a shared walk's steps once.
+ * n_groups_out (may be NULL) receives the number of groups formed.  EINVAL
+ * for unknown flags. */
+int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_t ngraphs,
+                                 const simrank_query *qs, int32_t nq, uint32_t flags,
+                                 simrank_batch_plan **plan_out, int32_t *n_groups_out);
 /* Enqueues the plan's graph on `stream` (hipStream_t; NULL = default stream). */
 int simrank_batch_plan_run(simrank_batch_plan *plan, void *stream);
 /* Waits for the last run; st (may be NULL) receives totals and its device time. */

@@ -6,9 +6,13 @@
 // whose work units span all queries (per kind: plain, stitched, stratified),
 // estimate.
 // Queries on graphs of very different sizes share the launch and its tail.
+// Plain queries on one graph with the same seed, c and cap form groups that
+// walk each pair (v, j) once for all members (group.hip).
 // Each query's result is exactly the one a lone simrank_single_source_ex call
 // returns: results depend only on (graph, query).
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -35,6 +39,40 @@ size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
     return b;
 }
 
+// Device bytes of a group's compacted walks.
+size_t group_bytes(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
+    return align_up(4 * (size_t)Rmax) + align_up(4 * ((size_t)Rmax + 1)) + align_up(8 * (size_t)Rmax) +
+           align_up(4 * (size_t)sum_RL) + align_up(4 * ((size_t)group_max_tiles(Rmax, sum_RL, L, G) + 1)) +
+           align_up(32);
+}
+
+// Groups of plain queries that share (graph, seed, continue threshold, cap):
+// each such set of two or more queries is split into ceil(size / GROUP_MAX)
+// groups of nearly equal size, in query order.
+std::vector<std::vector<int32_t>> form_groups(simrank_graph *const *graphs, const simrank_query *qs,
+                                              int32_t nq, const std::vector<simrank_params> &ps,
+                                              const std::vector<int> &modes) {
+    std::map<std::tuple<const Graph *, uint64_t, uint32_t, int32_t>, std::vector<int32_t>> by;
+    for (int32_t i = 0; i < nq; ++i)
+        if (modes[i] == SIMRANK_MODE_PLAIN)
+            by[std::make_tuple((const Graph *)graphs[qs[i].graph], qs[i].seed, ps[i].T, ps[i].L)]
+                .push_back(i);
+    std::vector<std::vector<int32_t>> out;
+    for (auto &kv : by) {
+        const std::vector<int32_t> &v = kv.second;
+        const int32_t sz = (int32_t)v.size();
+        if (sz < 2) continue;
+        const int32_t ngr = (sz + GROUP_MAX - 1) / GROUP_MAX;
+        int32_t at = 0;
+        for (int32_t k = 0; k < ngr; ++k) {
+            const int32_t take = sz / ngr + (k < sz % ngr ? 1 : 0);
+            out.emplace_back(v.begin() + at, v.begin() + at + take);
+            at += take;
+        }
+    }
+    return out;
+}
+
 }  // namespace
 }  // namespace srk
 
@@ -44,11 +82,14 @@ struct simrank_batch_plan {
     int device = 0;
     int32_t nq = 0;
     std::vector<QueryDesc> desc;       // host copies (buffer addresses)
+    std::vector<GroupDesc> gdesc;
     std::vector<simrank_params> params;
     std::vector<const Graph *> graphs;
     char *arena = nullptr;
     QueryDesc *desc_dev = nullptr;
     uint32_t *units = nullptr;
+    GroupDesc *gdesc_dev = nullptr;
+    uint32_t *gunits = nullptr;
     unsigned long long *counters = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -65,6 +106,8 @@ static void plan_release(simrank_batch_plan *p) {
     device_free(p->arena);
     device_free(p->desc_dev);
     device_free(p->units);
+    device_free(p->gdesc_dev);
+    device_free(p->gunits);
     device_free(p->counters);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
@@ -98,17 +141,47 @@ static int check_queries(simrank_graph *const *graphs, int32_t ngraphs, const si
     return SIMRANK_OK;
 }
 
-extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
-                                         const simrank_query *qs, int32_t nq,
-                                         simrank_batch_plan **plan_out) {
+extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_t ngraphs,
+                                            const simrank_query *qs, int32_t nq, uint32_t flags,
+                                            simrank_batch_plan **plan_out, int32_t *n_groups_out) {
     clear_error();
     if (!plan_out) return fail(SIMRANK_EINVAL, "plan is NULL");
     *plan_out = nullptr;
+    if (n_groups_out) *n_groups_out = 0;
     if (nq < 1) return fail(SIMRANK_EINVAL, "a plan needs at least one query");
+    if (flags & ~SIMRANK_PLAN_GROUPS) return fail(SIMRANK_EINVAL, "unknown plan flags");
     std::vector<simrank_params> ps;
     std::vector<int> modes;
     int rc = check_queries(graphs, ngraphs, qs, nq, ps, modes);
     if (rc) return rc;
+    std::vector<std::vector<int32_t>> groups;
+    if (flags & SIMRANK_PLAN_GROUPS) groups = form_groups(graphs, qs, nq, ps, modes);
+    // a group's work units are counted in 32 bits, as are a kind's
+    std::vector<int32_t> group_of(nq, -1);
+    std::vector<int64_t> g_Rmax, g_RL;
+    {
+        std::vector<std::vector<int32_t>> kept;
+        int64_t units = 0;
+        for (auto &m : groups) {
+            int64_t Rmax = 0, RL = 0;
+            for (int32_t i : m) {
+                Rmax = std::max<int64_t>(Rmax, ps[i].R);
+                RL += (int64_t)ps[i].R * ps[i].L;
+            }
+            const Graph *g = graphs[qs[m[0]].graph];
+            const int64_t vb = default_unit_nodes(g);
+            const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size()) *
+                               ((g->n_active + vb - 1) / vb);
+            if (units + ub >= (int64_t)0x7fffffff) continue;   // these queries run alone
+            units += ub;
+            for (int32_t i : m) group_of[i] = (int32_t)kept.size();
+            kept.push_back(m);
+            g_Rmax.push_back(Rmax);
+            g_RL.push_back(RL);
+        }
+        groups.swap(kept);
+    }
+    const int32_t ngr = (int32_t)groups.size();
     simrank_batch_plan *p = new simrank_batch_plan();
     p->device = graphs[qs[0].graph]->device;
     p->nq = nq;
@@ -121,6 +194,8 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
     size_t total = 0;
     for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], modes[i], graphs[qs[i].graph]->n);
+    for (int32_t k = 0; k < ngr; ++k)
+        total += group_bytes(g_Rmax[k], g_RL[k], ps[groups[k][0]].L, (int32_t)groups[k].size());
     size_t free_b = 0, tot_b = 0;
     if (hipMemGetInfo(&free_b, &tot_b) == hipSuccess && total > free_b)
         return bail(fail(SIMRANK_ENOMEM, "batch needs " + std::to_string(total) +
@@ -130,6 +205,12 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
     if ((rc = device_alloc((void **)&p->units, 4 * units_words(nq), &p->bytes)))
         return bail(rc);
     if ((rc = device_alloc((void **)&p->counters, 8 * 8, &p->bytes))) return bail(rc);
+    if (ngr > 0) {
+        if ((rc = device_alloc((void **)&p->gdesc_dev, sizeof(GroupDesc) * ngr, &p->bytes)))
+            return bail(rc);
+        if ((rc = device_alloc((void **)&p->gunits, 4 * ((size_t)ngr + 2), &p->bytes)))
+            return bail(rc);
+    }
     QuerySet set;
     set.nq = nq;
     char *cur = p->arena;
@@ -173,8 +254,57 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
         p->graphs[i] = g;
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
-        const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
-        set.units_bound[d.kind] += ub;
+        if (group_of[i] >= 0) {
+            d.kind = K_GROUPED;   // walked with its group
+        } else {
+            const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
+            set.units_bound[d.kind] += ub;
+        }
+    }
+    GroupSet gset;
+    p->gdesc.resize(ngr);
+    for (int32_t k = 0; k < ngr; ++k) {
+        const std::vector<int32_t> &m = groups[k];
+        const QueryDesc &d0 = p->desc[m[0]];
+        GroupDesc &gd = p->gdesc[k];
+        gd = GroupDesc{};
+        gd.nodes = d0.nodes;
+        gd.E = d0.E;
+        gd.active = d0.active;
+        gd.n_active = d0.n_active;
+        gd.vb = d0.vb;
+        gd.n_chunks = d0.n_chunks;
+        gd.G = (int32_t)m.size();
+        gd.L = d0.L;
+        gd.Rmax = (int32_t)g_Rmax[k];
+        gd.k0 = d0.k0;
+        gd.k1 = d0.k1;
+        gd.T = d0.T;
+        for (int32_t q = 0; q < gd.G; ++q) {
+            const QueryDesc &dq = p->desc[m[q]];
+            gd.s[q] = dq.s;
+            gd.R[q] = dq.R;
+            gd.sw[q] = dq.sw;
+            gd.slen[q] = dq.slen;
+            gd.cnt[q] = dq.cnt;
+        }
+        const int32_t mt = group_max_tiles(g_Rmax[k], g_RL[k], gd.L, gd.G);
+        gd.jj = (uint32_t *)take(4 * (size_t)gd.Rmax);
+        gd.joff = (uint32_t *)take(4 * ((size_t)gd.Rmax + 1));
+        gd.glen = (uint2 *)take(8 * (size_t)gd.Rmax);
+        gd.pos = (uint32_t *)take(4 * (size_t)g_RL[k]);
+        gd.tiles = (uint32_t *)take(4 * ((size_t)mt + 1));
+        gd.meta = (uint32_t *)take(32);
+        gset.units_bound += (int64_t)mt * gd.n_chunks;
+        gset.max_Rmax = std::max(gset.max_Rmax, gd.Rmax);
+    }
+    if (ngr > 0) {
+        e = hipMemcpy(p->gdesc_dev, p->gdesc.data(), sizeof(GroupDesc) * ngr, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
+        gset.desc = p->gdesc_dev;
+        gset.ng = ngr;
+        gset.units = p->gunits;
+        set.groups = &gset;
     }
     e = hipMemcpy(p->desc_dev, p->desc.data(), sizeof(QueryDesc) * nq, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
@@ -205,7 +335,15 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
     if (e == hipSuccess) e = hipEventCreate(&p->ev1);
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
     *plan_out = p;
+    if (n_groups_out) *n_groups_out = ngr;
     return SIMRANK_OK;
+}
+
+extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
+                                         const simrank_query *qs, int32_t nq,
+                                         simrank_batch_plan **plan_out) {
+    return simrank_batch_plan_create_ex(graphs, ngraphs, qs, nq, SIMRANK_PLAN_GROUPS, plan_out,
+                                        nullptr);
 }
 
 extern "C" int simrank_batch_plan_run(simrank_batch_plan *p, void *stream) {
@@ -313,8 +451,11 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         size_t used = 0;
         int32_t i1 = i0;
         while (i1 < nq) {
-            const size_t b =
-                query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) + sizeof(QueryDesc) + 64;
+            const size_t b = query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) +
+                             sizeof(QueryDesc) + 64 +
+                             (modes[i1] == SIMRANK_MODE_PLAIN   // its share of a group's buffers
+                                  ? 4 * (size_t)ps[i1].R * ps[i1].L + 16 * (size_t)ps[i1].R + 1024
+                                  : 0);
             if (i1 > i0 && used + b > budget) break;
             used += b;
             ++i1;

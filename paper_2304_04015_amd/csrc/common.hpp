@@ -195,11 +195,62 @@ struct QuerySet {
     int64_t units_bound[N_KINDS] = {0, 0, 0};   // work units of each kind's queries, at most
     uint32_t *units = nullptr;    // device [units_words(nq)]: unit offsets per kind, then cursors
     unsigned long long *counters = nullptr;  // device [8]
+    const struct GroupSet *groups = nullptr;  // grouped plain queries, if any
 };
 
 // Words of a query set's unit table: N_KINDS lists of nq + 1 offsets, then
 // one cursor per kind.
 inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1) + N_KINDS; }
+
+// ------------------------------------------------------------ query groups
+// In a batch, plain queries on one graph with the same walk key, continue
+// threshold and cap have the same walk (v, j) from every node v: a group of up
+// to GROUP_MAX such queries follows each walk once and tests it against every
+// member's walk j of its own source (group.hip).  A member keeps its own
+// descriptor (source walks, counts, estimate) with kind K_GROUPED, which no
+// per-kind unit list takes.
+constexpr int GROUP_MAX = 8;
+constexpr int32_t K_GROUPED = N_KINDS;
+constexpr int GROUP_TILE_J = 1024;       // walks per group tile, at most
+constexpr int GROUP_TILE_NODES = 24576;  // member positions per group tile (< 2^16)
+constexpr int GROUP_BLOCK = 1024;
+
+struct GroupDesc {
+    const uint2 *nodes;
+    const uint2 *E;
+    const int32_t *active;
+    int32_t n_active, vb, n_chunks;
+    int32_t G, L, Rmax;
+    uint32_t k0, k1, T;
+    int32_t s[GROUP_MAX];                // members' sources
+    int32_t R[GROUP_MAX];
+    const uint32_t *sw[GROUP_MAX];       // members' source walks [R][L]
+    const uint8_t *slen[GROUP_MAX];      // and their lengths [R]
+    uint32_t *cnt[GROUP_MAX];            // members' meet counts [n]
+    // Compacted walks: entry e is a walk index jj[e] for which at least one
+    // member's walk has a step; the members' positions of that walk lie back
+    // to back from pos[joff[e]], member q's glen[e] byte q of them.
+    uint32_t *jj;                        // [Rmax]
+    uint32_t *joff;                      // [Rmax + 1]
+    uint2 *glen;                         // [Rmax] eight lengths, one byte each
+    uint32_t *pos;                       // [sum of R_q x L]
+    uint32_t *tiles;                     // [group_max_tiles + 1]
+    uint32_t *meta;                      // [8]: entries, positions, tiles
+};
+
+struct GroupSet {
+    const GroupDesc *desc = nullptr;     // device [ng]
+    int32_t ng = 0;
+    int32_t max_Rmax = 0;
+    int64_t units_bound = 0;
+    uint32_t *units = nullptr;           // device [ng + 2]: unit offsets, then the cursor
+};
+
+// Tiles of a group's compacted walks, at most.
+int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G);
+// Enqueues a query set's groups: compaction, unit offsets, the group meet
+// kernel (after the members' source walks, before their estimates).
+int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st);
 
 // Per-query scratch.
 struct Workspace {

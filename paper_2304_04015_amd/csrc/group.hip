@@ -1,0 +1,387 @@
+// Query groups: plain queries of one batch that share a graph, a walk key, a
+// continue threshold and a cap.
+//
+// The estimator of Section 3 pairs walk j of the source s with walk j of every
+// node v.  The walk (v, j) draws its steps from counters (v, j, t, 0) under the
+// query's key, so queries that share the key, the decay and the cap have the
+// same walk (v, j) for every v and differ only in their source walks.  A group
+// follows each walk (v, j) once and, at every step, compares its position with
+// the same step of walk j of each member's source; a member drops out of the
+// pair once it has met (counted once, as for a lone query) or its source walk
+// has no further step.  The pair ends when the walk stops, reaches a node
+// without in-neighbours, or no member is left.  Each member's counts are
+// therefore exactly those of its lone run; the walks from the nodes are paid
+// for once per group instead of once per query.
+#include <algorithm>
+
+#include "common.hpp"
+#include "device_common.hpp"
+
+namespace srk {
+namespace {
+
+// Length of member q's walk in an entry's packed lengths (byte q).
+__device__ __forceinline__ uint32_t glen_of(uint2 l, int q) {
+    return ((q < 4 ? l.x : l.y) >> (8 * (q & 3))) & 0xffu;
+}
+
+// ------------------------------------------------------------ compaction
+// One block per group.  Keeps the walk indices j for which at least one
+// member's walk j has a step, packs the members' positions of walk j back to
+// back (member 0 first), and cuts the entries into tiles of at most
+// GROUP_TILE_J entries and GROUP_TILE_NODES positions (a boundary wherever the
+// entry index crosses a multiple of GROUP_TILE_J or the packed offset a
+// multiple of NW = GROUP_TILE_NODES - G L; an entry holds at most G L
+// positions).
+__global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restrict__ gd) {
+    const GroupDesc &d = gd[blockIdx.x];
+    const int32_t Rmax = d.Rmax, L = d.L, G = d.G;
+    const uint32_t NW = (uint32_t)(GROUP_TILE_NODES - G * L);
+    const int32_t per = (Rmax + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t j0 = min(Rmax, (int32_t)threadIdx.x * per), j1 = min(Rmax, j0 + per);
+    uint32_t cnt = 0, nodes = 0;
+    for (int32_t j = j0; j < j1; ++j) {
+        uint32_t tot = 0;
+        for (int32_t q = 0; q < G; ++q) tot += j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+        cnt += tot > 0;
+        nodes += tot;
+    }
+    uint32_t E1, total;
+    const uint32_t kb = block_excl_sum(cnt, &E1);
+    const uint32_t nb = block_excl_sum(nodes, &total);
+    uint32_t k = kb, off = nb;
+    for (int32_t j = j0; j < j1; ++j) {
+        uint32_t lo = 0, hi = 0, tot = 0;
+        for (int32_t q = 0; q < G; ++q) {
+            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+            if (q < 4) lo |= l << (8 * q); else hi |= l << (8 * (q - 4));
+            tot += l;
+        }
+        if (!tot) continue;
+        d.jj[k] = (uint32_t)j;
+        d.joff[k] = off;
+        d.glen[k] = make_uint2(lo, hi);
+        for (int32_t q = 0; q < G; ++q) {
+            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+            const uint32_t *src = d.sw[q] + (size_t)j * L;
+            for (uint32_t t = 0; t < l; ++t) d.pos[off + t] = src[t];
+            off += l;
+        }
+        ++k;
+    }
+    if (threadIdx.x == 0) d.joff[E1] = total;
+    __syncthreads();
+    uint32_t nbound = 0;
+    for (uint32_t e = kb; e < kb + cnt; ++e)
+        nbound += (e == 0) || (e % GROUP_TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
+    uint32_t n_tiles;
+    uint32_t tb = block_excl_sum(nbound, &n_tiles);
+    for (uint32_t e = kb; e < kb + cnt; ++e)
+        if ((e == 0) || (e % GROUP_TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
+            d.tiles[tb++] = e;
+    if (threadIdx.x == 0) {
+        d.tiles[n_tiles] = E1;
+        d.meta[0] = E1;
+        d.meta[1] = total;
+        d.meta[2] = n_tiles;
+    }
+}
+
+// Work-unit offsets of the groups (one block): ng + 1 offsets, then the cursor.
+__global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restrict__ gd, int32_t ng,
+                                                      uint32_t *__restrict__ units) {
+    const int32_t per = (ng + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t g0 = min(ng, (int32_t)threadIdx.x * per), g1 = min(ng, g0 + per);
+    uint32_t sum = 0;
+    for (int32_t g = g0; g < g1; ++g) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+    uint32_t total;
+    uint32_t run = block_excl_sum(sum, &total);
+    for (int32_t g = g0; g < g1; ++g) {
+        units[g] = run;
+        run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+    }
+    if (threadIdx.x == 0) {
+        units[ng] = total;
+        units[ng + 1] = 0u;
+    }
+}
+
+// ------------------------------------------------------------ meet kernel
+// The single-query meet kernel's scheme with a group in place of a query:
+// persistent blocks take units (group, tile of its compacted walks, chunk of
+// vb nodes with in-edges) from a device cursor, stage the tile's positions in
+// LDS, and hand the pairs (v, entry) of a unit, v-major, to the waves in chunks
+// of 64.  A lane keeps NS pairs in flight; a pair carries the entry's member
+// lengths and the mask of members still tested.  Counts go to one LDS counter
+// per (member, node), flushed to the members' counts once per unit.
+
+struct GSlot {
+    uint32_t pos;    // LDS offset of the entry's positions (16 bits) | node index << 24
+    uint32_t live;   // members still tested (bit q)
+    uint2 len;       // the entry's member lengths, one byte each
+    uint32_t t;      // steps taken
+    uint32_t o, d;   // current node: slot offset in E and in-degree
+    WalkDraws rng;
+    bool busy;
+};
+
+template <int NS>
+__global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__restrict__ gd, int32_t ng,
+                                                            const uint32_t *__restrict__ ustart,
+                                                            uint32_t *__restrict__ cursor,
+                                                            unsigned long long *__restrict__ counters) {
+    __shared__ uint32_t s_nodes[GROUP_TILE_NODES];
+    __shared__ uint32_t s_j[GROUP_TILE_J];
+    __shared__ uint16_t s_off[GROUP_TILE_J];
+    __shared__ uint2 s_len[GROUP_TILE_J];
+    __shared__ uint32_t s_cnt[GROUP_MAX * MEET_VB];
+    __shared__ uint32_t s_vid[MEET_VB];
+    __shared__ uint2 s_vrow[MEET_VB];
+    __shared__ uint32_t s_unit, s_item;
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_units = ustart[ng];
+    uint32_t cur_g = 0xffffffffu, cur_tile = 0xffffffffu;
+    uint32_t K = 0;
+    uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_pairs = 0;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const uint32_t unit = s_unit;
+        if (unit >= n_units) break;
+        int32_t lo = 0, hi = ng;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (ustart[mid] <= unit) lo = mid; else hi = mid;
+        }
+        const int32_t gi = lo;
+        const GroupDesc &d = gd[gi];
+        const int32_t n_chunks = (int32_t)uni((uint32_t)d.n_chunks);
+        const int32_t vb = (int32_t)uni((uint32_t)d.vb);
+        const int32_t G = (int32_t)uni((uint32_t)d.G);
+        const uint32_t local = unit - ustart[gi];
+        const uint32_t tile = local / (uint32_t)n_chunks;
+        const uint32_t chunk = local - tile * (uint32_t)n_chunks;
+        const PhiloxKey key{uni(d.k0), uni(d.k1)};
+        const uint32_t T = uni(d.T);
+        int32_t src[GROUP_MAX];
+#pragma unroll
+        for (int q = 0; q < GROUP_MAX; ++q) src[q] = q < G ? (int32_t)uni((uint32_t)d.s[q]) : -1;
+        if ((uint32_t)gi != cur_g || tile != cur_tile) {
+            const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
+            const uint32_t nb = d.joff[k0], ne = d.joff[k1];
+            K = k1 - k0;
+            for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+                s_j[i] = d.jj[k0 + i];
+                s_off[i] = (uint16_t)(d.joff[k0 + i] - nb);
+                s_len[i] = d.glen[k0 + i];
+            }
+            for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.pos[nb + i];
+            cur_g = (uint32_t)gi;
+            cur_tile = tile;
+        }
+        const int32_t vbase = (int32_t)chunk * vb;
+        const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
+        for (uint32_t i = threadIdx.x; i < GROUP_MAX * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
+            const uint32_t id = (uint32_t)d.active[vbase + (int32_t)i];
+            s_vid[i] = id;
+            s_vrow[i] = d.nodes[id];
+        }
+        if (threadIdx.x == 0) s_item = 0u;
+        __syncthreads();
+
+        // item i = vl * K + k for node vl < nv and entry k < K
+        const uint32_t total = nv * K;
+        uint32_t ci = 0, ce = 0, cvl = 0, ck = 0;
+        bool drained = false;
+        GSlot sl[NS];
+#pragma unroll
+        for (int qq = 0; qq < NS; ++qq) sl[qq].busy = false;
+
+        for (;;) {
+            // ---- refill idle slots; a pair with no member to test (each
+            // member's walk j is empty or starts at v itself) is skipped
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq) {
+                uint64_t need = __ballot(!sl[qq].busy);
+                while (need != 0ull) {
+                    if (ci == ce) {
+                        if (drained) break;
+                        uint32_t x = 0;
+                        if (lane == 0) x = atomicAdd(&s_item, ITEM_CHUNK);
+                        x = __builtin_amdgcn_readfirstlane(x);
+                        if (x >= total) {
+                            drained = true;
+                            break;
+                        }
+                        ci = x;
+                        ce = min(x + ITEM_CHUNK, total);
+                        cvl = x / K;
+                        ck = x - cvl * K;
+                    }
+                    const uint32_t want = (uint32_t)__popcll(need);
+                    const uint32_t avail = ce - ci;
+                    const uint32_t take = avail < want ? avail : want;
+                    const uint32_t rank = lane_rank(need);
+                    const bool mine = ((need >> lane) & 1ull) && rank < take;
+                    bool filled = false;
+                    if (mine) {
+                        uint32_t k = ck + rank, vl = cvl;
+                        while (k >= K) {
+                            k -= K;
+                            ++vl;
+                        }
+                        const int32_t id = (int32_t)s_vid[vl];
+                        const uint2 ln = s_len[k];
+                        uint32_t live = 0;
+#pragma unroll
+                        for (int q = 0; q < GROUP_MAX; ++q)
+                            if (glen_of(ln, q) != 0u && id != src[q]) live |= 1u << q;
+                        if (live) {
+                            const uint2 row = s_vrow[vl];
+                            GSlot &w = sl[qq];
+                            w.rng = walk_draws_begin((uint32_t)id, s_j[k], key);
+                            w.pos = (uint32_t)s_off[k] | (vl << 24);
+                            w.live = live;
+                            w.len = ln;
+                            w.t = 0;
+                            w.o = row.x;
+                            w.d = row.y;
+                            w.busy = true;
+                            filled = true;
+                            ++st_pairs;
+                        }
+                    }
+                    need &= ~__ballot(filled);
+                    ci += take;
+                    ck += take;
+                    while (ck >= K && K > 0) {
+                        ck -= K;
+                        ++cvl;
+                    }
+                }
+            }
+            bool any = false;
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq) any |= sl[qq].busy;
+            if (__ballot(any) == 0ull) {
+                if (drained) break;
+                continue;
+            }
+
+            // ---- one step of every busy pair: draws, gathers, compares
+            bool go[NS];
+            uint32_t at[NS];
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq) {
+                go[qq] = false;
+                at[qq] = 0;
+                if (sl[qq].busy) {
+                    ++sl[qq].t;
+                    const uint2 x = walk_draw_next(sl[qq].rng, key);
+                    ++st_draws;
+                    if (x.x >= T) {
+                        sl[qq].busy = false;
+                    } else {
+                        go[qq] = true;
+                        at[qq] = sl[qq].o + pick32(x.y, sl[qq].d);
+                    }
+                }
+            }
+            uint2 e[NS];
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq)
+                if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq) {
+                if (!go[qq]) continue;
+                ++st_moves;
+                GSlot &w = sl[qq];
+                w.o = e[qq].x;
+                w.d = e[qq].y;
+                const uint32_t vl = w.pos >> 24;
+                // member q's position t is at its own offset within the entry
+                uint32_t off = (w.pos & 0xffffu) + w.t - 1u;
+                uint32_t live = w.live;
+#pragma unroll
+                for (int q = 0; q < GROUP_MAX; ++q) {
+                    const uint32_t lq = glen_of(w.len, q);
+                    if (live & (1u << q)) {
+                        if (w.o == s_nodes[off]) {
+                            atomicAdd(&s_cnt[q * MEET_VB + vl], 1u);
+                            ++st_meets;
+                            live &= ~(1u << q);
+                        } else if (w.t == lq) {
+                            live &= ~(1u << q);
+                        }
+                    }
+                    off += lq;
+                }
+                w.live = live;
+                if (live == 0u || w.d == 0u) w.busy = false;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < (uint32_t)G * nv; i += blockDim.x) {
+            const uint32_t q = i / nv, vi = i - q * nv;
+            const uint32_t c = s_cnt[q * MEET_VB + vi];
+            if (c) atomicAdd(&d.cnt[q][s_vid[vi]], c);
+        }
+    }
+
+    unsigned long long v0 = st_moves, v1 = st_draws, v2 = st_meets, v4 = st_pairs;
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        v0 += __shfl_xor(v0, dd, 64);
+        v1 += __shfl_xor(v1, dd, 64);
+        v2 += __shfl_xor(v2, dd, 64);
+        v4 += __shfl_xor(v4, dd, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[C_MOVES], v0);
+        atomicAdd(&counters[C_DRAWS], v1);
+        atomicAdd(&counters[C_MEETS], v2);
+        atomicAdd(&counters[C_PAIRS], v4);
+    }
+}
+
+#ifndef SRK_GROUP_SLOTS
+#define SRK_GROUP_SLOTS 2
+#endif
+
+int group_grid_blocks() {
+    static const int blocks = [] {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<SRK_GROUP_SLOTS>,
+                                                           GROUP_BLOCK, 0);
+        if (cus <= 0) cus = 256;
+        if (per <= 0) per = 1;
+        return cus * per;
+    }();
+    return blocks;
+}
+
+}  // namespace
+
+int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
+    const int64_t NW = GROUP_TILE_NODES - (int64_t)G * L;
+    return (int32_t)(2 + Rmax / GROUP_TILE_J + sum_RL / NW);
+}
+
+int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st) {
+    if (gs.ng <= 0) return SIMRANK_OK;
+    k_group_compact<<<gs.ng, 1024, 0, st>>>(gs.desc);
+    k_group_units<<<1, 1024, 0, st>>>(gs.desc, gs.ng, gs.units);
+    if (gs.units_bound > 0) {
+        const int blocks = (int)std::min<int64_t>(gs.units_bound, group_grid_blocks());
+        k_meet_group<SRK_GROUP_SLOTS><<<blocks, GROUP_BLOCK, 0, st>>>(
+            gs.desc, gs.ng, gs.units, gs.units + gs.ng + 1, counters);
+    }
+    SRK_HIP(hipGetLastError());
+    return SIMRANK_OK;
+}
+
+}  // namespace srk

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
 // walks and at most NW - 1 + L <= TN positions.
 __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.x];
+    if (d.kind == K_GROUPED) return;   // compacted with its group
     const int32_t R = d.R, L = d.L;
     const uint32_t TJ = (uint32_t)tile_j_of(d.kind);
     const uint32_t NW = (uint32_t)(tile_nodes_of(d.kind) - L);
@@ -797,6 +798,10 @@ int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hi
     if (qs.units_bound[K_PLAIN] > 0) launch_meet<K_PLAIN, SRK_MEET_SLOTS>(qs, st);
     if (qs.units_bound[K_STITCHED] > 0) launch_meet<K_STITCHED, SRK_MEET_SLOTS_STITCHED>(qs, st);
     if (qs.units_bound[K_STRAT] > 0) launch_meet<K_STRAT, SRK_MEET_SLOTS_STRAT>(qs, st);
+    if (qs.groups && qs.groups->ng > 0) {
+        const int rc = launch_groups(*qs.groups, qs.counters, st);
+        if (rc) return rc;
+    }
     if (ev_meet1) SRK_HIP(hipEventRecord(ev_meet1, st));
     k_estimate<<<dim3(gx_n, nq), 256, 0, st>>>(qs.desc);
     SRK_HIP(hipGetLastError());

@@ -24,6 +24,7 @@ HEADER = os.path.join(INCLUDE, "simrank.h")
 
 SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
 MODE_PLAIN, MODE_STITCHED, MODE_STRATIFIED = 0, 1, 2
+PLAN_GROUPS = 1                   # simrank_batch_plan_create_ex flag
 _ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE"}
 
 
@@ -133,6 +134,7 @@ def lib() -> C.CDLL:
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
         "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
         "simrank_batch_plan_create": [P(vp), i32, P(simrank_query), i32, P(vp)],
+        "simrank_batch_plan_create_ex": [P(vp), i32, P(simrank_query), i32, u32, P(vp), P(i32)],
         "simrank_batch_plan_run": [vp, vp],
         "simrank_batch_plan_wait": [vp, P(simrank_stats)],
         "simrank_batch_plan_read": [vp, i32, vp, vp],
@@ -447,12 +449,19 @@ def simrank_roofline_copy(nbytes: int) -> dict:
 class BatchPlan:
     """simrank_batch_plan_*: device buffers and a captured launch of a query set."""
 
-    def __init__(self, graphs: list, queries: list):
+    def __init__(self, graphs: list, queries: list, groups: bool = True):
+        """groups: let plain queries with equal (graph, seed, c, cap) share
+        their walks from every node (SIMRANK_PLAN_GROUPS); n_groups says how
+        many groups were formed."""
         ng, nq = len(graphs), len(queries)
         garr = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
         qarr = (simrank_query * nq)(*queries)
         h = C.c_void_p()
-        _check(lib().simrank_batch_plan_create(garr, ng, qarr, nq, C.byref(h)))
+        ngr = C.c_int32(0)
+        _check(lib().simrank_batch_plan_create_ex(garr, ng, qarr, nq,
+                                                  PLAN_GROUPS if groups else 0,
+                                                  C.byref(h), C.byref(ngr)))
+        self.n_groups = int(ngr.value)
         self.handle = h
         self.graphs = graphs
         self.queries = list(queries)

@@ -94,6 +94,17 @@ def test_null_arguments_rejected():
     assert S.lib().simrank_last_error() == b""
 
 
+def test_plan_flags_checked_before_any_device_work():
+    import ctypes as C
+    h, ng = C.c_void_p(), C.c_int32(-1)
+    q = S.make_query(0)
+    rc = S.lib().simrank_batch_plan_create_ex(None, 0, C.byref(q), 1, 2, C.byref(h), C.byref(ng))
+    assert rc == S.SIMRANK_EINVAL and h.value is None and ng.value == 0
+    assert b"flags" in S.lib().simrank_last_error()
+    rc = S.lib().simrank_batch_plan_create_ex(None, 0, C.byref(q), 0, S.PLAN_GROUPS, C.byref(h), None)
+    assert rc == S.SIMRANK_EINVAL and h.value is None
+
+
 def test_union_bound_grows_R():
     q1 = S.make_query(0, eps=0.02)
     q2 = S.make_query(0, eps=0.02, union_bound=True)

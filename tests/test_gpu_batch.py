@@ -139,3 +139,78 @@ def test_batch_with_stratified_queries(graphs):
             assert np.array_equal(cnts[i], c1) and np.array_equal(outs[i], o1), i
             assert np.array_equal(plan.read(i)[1], c1), i
     plan.free()
+
+
+def test_shared_seed_groups_equal_lone_queries(graphs):
+    """Plain queries with equal (graph, seed, c, cap) run in groups that share
+    the walks from every node: 11 on one graph (two groups, members with
+    different R spanning several group tiles with a ragged last one, a repeated
+    source, a source without in-edges), 3 on another, 2 with another cap, 2 on
+    the star graph; stitched and stratified queries with the same seed and
+    lone plain queries stay out of the groups.  Every result equals the lone
+    query's and the ungrouped plan's, bit for bit."""
+    gs, Gs = graphs
+    g2 = gs[2]
+    act = np.nonzero(g2.in_degree() > 0)[0]
+    rng = np.random.default_rng(9)
+    S1, S2 = 0x2304040150000051, 0x2304040150000052
+    srcs = [int(x) for x in rng.choice(act, 9, replace=False)]
+    srcs += [srcs[0], int(np.argmax(g2.in_degree() == 0))]
+    Rs = [3000, 4100, 2500, 1, 3000, 700, 5200, 3000, 3333, 4100, 2000]
+    qs = [S.make_query(s, c=0.6, seed=S1, walk_cap=64, R=R, graph=2) for s, R in zip(srcs, Rs)]
+    qs += [S.make_query(int(s), c=0.6, seed=S1, walk_cap=64, R=1500, graph=0)
+           for s in rng.choice(np.nonzero(gs[0].in_degree() > 0)[0], 3, replace=False)]
+    qs += [S.make_query(srcs[k], c=0.6, seed=S2, walk_cap=20, R=2048, graph=2) for k in (1, 2)]
+    qs += [S.make_query(s, c=0.6, seed=S1, walk_cap=64, R=900, graph=3) for s in (1, 0)]
+    qs += [S.make_query(srcs[3], c=0.5, seed=S1, walk_cap=64, R=3000, graph=2)]   # lone: other c
+    qs += [S.make_query(int(np.nonzero(gs[1].in_degree() > 0)[0][3]), c=0.6, seed=S1,
+                        walk_cap=64, R=3000, graph=1, mode=S.MODE_STITCHED)]
+    qs += [S.make_stratified_query(srcs[4], c=0.6, eps=0.2, seed=S1, z=700, phi=12, graph=2)]
+    order = rng.permutation(len(qs))
+    qs = [qs[i] for i in order]
+    _say(f"shared-seed batch: {len(qs)} queries")
+    plan = S.BatchPlan(Gs, qs)
+    assert plan.n_groups == 5
+    plan.run()
+    st_g = plan.wait()
+    flat = S.BatchPlan(Gs, qs, groups=False)
+    assert flat.n_groups == 0
+    flat.run()
+    st_f = flat.wait()
+    for i, q in enumerate(qs):
+        if q.mode == S.MODE_STRATIFIED:
+            assert np.array_equal(plan.read_stratified(i)[2], flat.read_stratified(i)[2]), i
+            continue
+        o1, c1, _ = S.simrank_single_source_ex(Gs[q.graph], q)
+        o, c = plan.read(i)
+        of, cf = flat.read(i)
+        assert np.array_equal(c, c1) and np.array_equal(o, o1), i
+        assert np.array_equal(cf, c1), i
+    assert st_g.meets == st_f.meets
+    assert st_g.moves < st_f.moves            # the shared walks are taken once
+    # a member on the small graph against the oracle
+    i = next(k for k, q in enumerate(qs) if q.graph == 0)
+    want = O.meet_counts_plain(gs[0], qs[i].s, S1, 0.6, 64, 1500)
+    assert np.array_equal(plan.read(i)[1], want)
+    plan.free()
+    flat.free()
+
+
+def test_shared_seed_group_full_size():
+    """Eight queries with the medium workload's shape (2^16-node R-MAT graph,
+    eps 0.02, R = 9,502, cap 64) and one seed: the group's counts equal the
+    lone queries', bit for bit."""
+    g = inputs.rmat_in(16, 16 << 16, seed=72)
+    G = S.load_csr(g)
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, 8, 74)]
+    qs = [S.make_query(s, c=0.6, eps=0.02, delta=1e-3, seed=0x2304040150000053, walk_cap=64)
+          for s in srcs]
+    assert S.simrank_derive_params(qs[0], g.n).R == 9502
+    plan = S.BatchPlan([G], qs)
+    assert plan.n_groups == 1
+    plan.run()
+    st = plan.wait()
+    _say(f"group of 8 at full size: {st.ms:.1f} ms, {st.moves} moves")
+    for i, q in enumerate(qs):
+        assert np.array_equal(plan.read(i, want_out=False)[1], S.simrank_single_source_ex(G, q)[1]), i
+    plan.free()
