@@ -33,11 +33,11 @@ BYTES_PER_MOVE = 8
 
 
 def kernel_fingerprint() -> str:
-    """sha256 (16 hex digits) of the sources the meet kernel is built from."""
+    """sha256 (16 hex digits) of the sources the meet kernels are built from."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_04015_amd", "csrc")
     h = b"".join(open(os.path.join(csrc, f), "rb").read()
-                 for f in ("query.hip", "device_common.hpp", "philox.hpp", "common.hpp"))
+                 for f in ("query.hip", "group.hip", "device_common.hpp", "philox.hpp", "common.hpp"))
     return hashlib.sha256(h).hexdigest()[:16]
 
 
@@ -71,7 +71,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "stitching", "batching", "serving", "stratified", "tuples"],
+                    choices=["medium", "stitching", "batching", "serving", "stratified", "tuples",
+                             "grouped"],
                     help="medium: the default line; stitching: R-MAT n=2^24 index build "
                          "and stitched query; batching: 512 queries over 16 graphs, "
                          "one captured batch vs one query at a time; serving: Poisson "
@@ -81,6 +82,11 @@ def parse():
                          "graph's 8 sources (and 32) through Algorithm 2's tuple form")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
+    ap.add_argument("--group-queries", type=int, default=32,
+                    help="grouped: number of same-seed queries on the medium graph")
+    ap.add_argument("--shared-seed", action="store_true",
+                    help="batching: one walk seed per graph instead of one per query, so that "
+                         "the queries of a graph share their walks from every node (query groups)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-nodes", type=int, default=6144,
@@ -118,6 +124,8 @@ def main():
         return bench_stratified(args)
     if args.workload == "tuples":
         return bench_tuples(args)
+    if args.workload == "grouped":
+        return bench_grouped(args)
 
     import numpy as np
     import torch
@@ -523,9 +531,12 @@ def bench_batching(args):
     """Batching workload: 16 R-MAT graphs with n = floor(2^U(12,22)) and average
     degree U{8..32}; queries with a uniform graph, a source drawn uniformly among
     its nodes with in-edges, eps from {0.05, 0.02, 0.01}, delta = 1e-3, L = 64 and
-    a seed of their own.  The same queries run (a) one at a time through the
-    asynchronous single-query call on one stream and (b) as one captured batch
-    plan; both after the unit-size tuner has run once per graph."""
+    a seed of their own (--shared-seed: one seed per graph).  The same queries
+    run (a) one at a time through the asynchronous single-query call on one
+    stream and (b) as one captured batch plan; both after the unit-size tuner
+    has run once per graph.  With shared seeds the plan runs the queries of a
+    graph as groups that walk each (v, j) once for all of them, and (c) the
+    same plan without groups is timed as well."""
     import numpy as np
     import torch
 
@@ -546,8 +557,9 @@ def bench_batching(args):
         gi = int(rng.integers(0, len(gs)))
         act = np.nonzero(gs[gi].in_degree() > 0)[0]
         eps = float(rng.choice(cfg["eps_choices"]))
+        seed = 0x2304040150000400 + (0x1000 + gi if args.shared_seed else i)
         queries.append(S.make_query(int(rng.choice(act)), c=cfg["c"], eps=eps, delta=cfg["delta"],
-                                    seed=0x2304040150000400 + i, walk_cap=cfg["L"], graph=gi))
+                                    seed=seed, walk_cap=cfg["L"], graph=gi))
     tuned = []
     for gi, G in enumerate(Gs):
         act = np.nonzero(gs[gi].in_degree() > 0)[0]
@@ -584,6 +596,21 @@ def bench_batching(args):
     same = all(np.array_equal(plan.read(i, want_out=False)[1], c) for i, c in check.items())
     walk_steps = st.moves + st.tail_steps + st.source_moves
     nq = len(queries)
+    flat = None
+    if plan.n_groups:   # (c) the same plan without groups
+        fplan = S.BatchPlan(Gs, queries, groups=False)
+        fplan.run(stream)
+        fplan.wait()
+        t3 = time.perf_counter()
+        fplan.run(stream)
+        fst = fplan.wait()
+        t_flat = time.perf_counter() - t3
+        fsame = all(np.array_equal(fplan.read(i, want_out=False)[1], plan.read(i, want_out=False)[1])
+                    for i in range(0, nq, 7))
+        flat = {"queries_per_s": nq / t_flat, "ms": 1e3 * t_flat,
+                "walk_steps": fst.moves + fst.tail_steps + fst.source_moves,
+                "results_equal_grouped": fsame}
+        fplan.free()
     # per graph: up to 4 of its queries alone (untimed above), the meet kernel's
     # moves per second and algorithmic bytes (8 B per move) against the HBM peak
     per_graph = []
@@ -609,12 +636,16 @@ def bench_batching(args):
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"batching: {nq} single-source queries over 16 R-MAT graphs "
                                "(n = 2^U(12,22), avg degree U{8..32}), eps in {.05,.02,.01}, "
-                               "delta=1e-3, L=64; one captured batch",
+                               "delta=1e-3, L=64; one captured batch" +
+                               ("; one walk seed per graph (query groups)" if args.shared_seed
+                                else "; one walk seed per query"),
                    "graphs": [{"n": g.n, "m": g.m} for g in gs], "queries": nq},
         "queries_per_s": nq / t_batch,
         "plain_queries_per_s": nq / t_plain,
         "batched_vs_plain": t_plain / t_batch,
         "batch_results_equal_plain": same,
+        "groups": plan.n_groups,
+        "ungrouped_batch": flat,
         "tuned_unit_nodes": tuned,
         "batch": {"moves": st.moves, "draws": st.draws, "device_ms": st.ms, "pairs": st.pairs},
         "per_graph": per_graph,
@@ -625,6 +656,83 @@ def bench_batching(args):
         ws.free()
     for G in Gs:
         G.free()
+
+
+def bench_grouped(args):
+    """Grouped workload: the medium graph (R-MAT n=2^20, 16n edge draws) and
+    --group-queries single-source queries with eps = 0.02, delta = 1e-3
+    (R = 9,502), L = 64 and the medium workload's walk seed, as one captured
+    batch plan in which they form one query group: each walk (v, j) is taken
+    once for all sources.  A step is one run of the plan.  The same plan
+    without groups is run once for comparison; results must be equal."""
+    import numpy as np
+    import torch
+
+    from paper_2304_04015_amd import inputs
+    from paper_2304_04015_amd import simrank as S
+
+    cfg = inputs.C2
+    torch.cuda.set_device(0)
+    copy_probe(args)
+    g = inputs.workload_graph(cfg)
+    G = S.load_csr(g)
+    nq = args.group_queries
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, cfg["source_seed"])]
+    qs = [S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
+                       walk_cap=cfg["L"]) for s in srcs]
+    R = S.simrank_derive_params(qs[0], g.n).R
+    plan = S.BatchPlan([G], qs)
+    stream = torch.cuda.Stream()
+    for _ in range(args.warmup):
+        plan.run(stream)
+        plan.wait()
+    torch.cuda.synchronize()
+    steps, moves, dev_ms = args.steps, 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(stream)
+        st = plan.wait()
+        moves += st.moves + st.source_moves
+        dev_ms += st.ms
+    dt = time.perf_counter() - t0
+    grouped = [plan.read(i, want_out=False)[1] for i in range(nq)]
+    flat = S.BatchPlan([G], qs, groups=False)
+    flat.run(stream)
+    fst = flat.wait()
+    same = all(np.array_equal(flat.read(i, want_out=False)[1], grouped[i]) for i in range(nq))
+    lone = np.array_equal(S.simrank_single_source_ex(G, qs[0])[1], grouped[0])
+    kernel_s = (dev_ms / steps) / 1e3
+    achieved = BYTES_PER_MOVE * st.moves / kernel_s / 1e9
+    result = {
+        "metric": METRIC,
+        "value": moves / dt,
+        "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"grouped: medium graph (R-MAT n=2^20, 16n edge draws), {nq} "
+                               "single-source queries with one walk seed, eps=0.02 delta=1e-3 "
+                               f"R={R} L=64, one captured batch plan forming one query group",
+                   "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries": nq,
+                   "groups": plan.n_groups},
+        "queries_per_s": nq * steps / dt,
+        "ungrouped_queries_per_s": nq / (fst.ms / 1e3),
+        "grouped_vs_ungrouped": (fst.ms / 1e3) / (dt / steps),
+        "moves_per_query": st.moves / nq,
+        "moves_per_query_ungrouped": fst.moves / nq,
+        "results_equal_ungrouped": same,
+        "first_equals_lone_query": lone,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_meet_group<2, 8> (whole plan's device time)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_grouped.json")),
+        },
+    }
+    print(json.dumps(result))
+    plan.free()
+    flat.free()
+    G.free()
 
 
 def bench_serving(args):

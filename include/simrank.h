@@ -303,7 +303,7 @@ int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
 #define SIMRANK_PLAN_GROUPS 1u
 /* simrank_batch_plan_create with flags (simrank_batch_plan_create and
  * simrank_batch pass SIMRANK_PLAN_GROUPS).  SIMRANK_PLAN_GROUPS: plain queries
- * on one graph with equal seed, c and walk cap are run in groups of up to 8
+ * on one graph with equal seed, c and walk cap are run in groups of up to 32
  * that share the walks from every node (Section 3's walk (v, j) depends on the
  * seed, c and cap only, not on the source): each walk (v, j) is taken once
  * and compared with walk j of every member's source.  Results are bit for bit

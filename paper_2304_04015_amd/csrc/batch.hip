@@ -41,7 +41,8 @@ size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
 
 // Device bytes of a group's compacted walks.
 size_t group_bytes(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
-    return align_up(4 * (size_t)Rmax) + align_up(4 * ((size_t)Rmax + 1)) + align_up(8 * (size_t)Rmax) +
+    return align_up(4 * (size_t)Rmax) + align_up(4 * ((size_t)Rmax + 1)) +
+           align_up(4 * (size_t)Rmax * (size_t)((G + 3) / 4)) +
            align_up(4 * (size_t)sum_RL) + align_up(4 * ((size_t)group_max_tiles(Rmax, sum_RL, L, G) + 1)) +
            align_up(32);
 }
@@ -208,7 +209,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
     if (ngr > 0) {
         if ((rc = device_alloc((void **)&p->gdesc_dev, sizeof(GroupDesc) * ngr, &p->bytes)))
             return bail(rc);
-        if ((rc = device_alloc((void **)&p->gunits, 4 * ((size_t)ngr + 2), &p->bytes)))
+        if ((rc = device_alloc((void **)&p->gunits, 4 * group_units_words(ngr), &p->bytes)))
             return bail(rc);
     }
     QuerySet set;
@@ -275,6 +276,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         gd.vb = d0.vb;
         gd.n_chunks = d0.n_chunks;
         gd.G = (int32_t)m.size();
+        gd.gw = (gd.G + 3) / 4;
         gd.L = d0.L;
         gd.Rmax = (int32_t)g_Rmax[k];
         gd.k0 = d0.k0;
@@ -291,12 +293,11 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         const int32_t mt = group_max_tiles(g_Rmax[k], g_RL[k], gd.L, gd.G);
         gd.jj = (uint32_t *)take(4 * (size_t)gd.Rmax);
         gd.joff = (uint32_t *)take(4 * ((size_t)gd.Rmax + 1));
-        gd.glen = (uint2 *)take(8 * (size_t)gd.Rmax);
+        gd.glen = (uint32_t *)take(4 * (size_t)gd.Rmax * gd.gw);
         gd.pos = (uint32_t *)take(4 * (size_t)g_RL[k]);
         gd.tiles = (uint32_t *)take(4 * ((size_t)mt + 1));
         gd.meta = (uint32_t *)take(32);
-        gset.units_bound += (int64_t)mt * gd.n_chunks;
-        gset.max_Rmax = std::max(gset.max_Rmax, gd.Rmax);
+        gset.units_bound[gd.G > 8] += (int64_t)mt * gd.n_chunks;
     }
     if (ngr > 0) {
         e = hipMemcpy(p->gdesc_dev, p->gdesc.data(), sizeof(GroupDesc) * ngr, hipMemcpyHostToDevice);

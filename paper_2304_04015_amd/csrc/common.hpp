@@ -209,11 +209,8 @@ inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1
 // member's walk j of its own source (group.hip).  A member keeps its own
 // descriptor (source walks, counts, estimate) with kind K_GROUPED, which no
 // per-kind unit list takes.
-constexpr int GROUP_MAX = 8;
+constexpr int GROUP_MAX = 32;
 constexpr int32_t K_GROUPED = N_KINDS;
-constexpr int GROUP_TILE_J = 1024;       // walks per group tile, at most
-constexpr int GROUP_TILE_NODES = 24576;  // member positions per group tile (< 2^16)
-constexpr int GROUP_BLOCK = 1024;
 
 struct GroupDesc {
     const uint2 *nodes;
@@ -221,6 +218,7 @@ struct GroupDesc {
     const int32_t *active;
     int32_t n_active, vb, n_chunks;
     int32_t G, L, Rmax;
+    int32_t gw;                          // words of member lengths per entry: ceil(G / 4)
     uint32_t k0, k1, T;
     int32_t s[GROUP_MAX];                // members' sources
     int32_t R[GROUP_MAX];
@@ -229,10 +227,11 @@ struct GroupDesc {
     uint32_t *cnt[GROUP_MAX];            // members' meet counts [n]
     // Compacted walks: entry e is a walk index jj[e] for which at least one
     // member's walk has a step; the members' positions of that walk lie back
-    // to back from pos[joff[e]], member q's glen[e] byte q of them.
+    // to back from pos[joff[e]], member q's length in byte q of the entry's
+    // gw words glen[e gw ...].
     uint32_t *jj;                        // [Rmax]
     uint32_t *joff;                      // [Rmax + 1]
-    uint2 *glen;                         // [Rmax] eight lengths, one byte each
+    uint32_t *glen;                      // [Rmax][gw]
     uint32_t *pos;                       // [sum of R_q x L]
     uint32_t *tiles;                     // [group_max_tiles + 1]
     uint32_t *meta;                      // [8]: entries, positions, tiles
@@ -241,10 +240,12 @@ struct GroupDesc {
 struct GroupSet {
     const GroupDesc *desc = nullptr;     // device [ng]
     int32_t ng = 0;
-    int32_t max_Rmax = 0;
-    int64_t units_bound = 0;
-    uint32_t *units = nullptr;           // device [ng + 2]: unit offsets, then the cursor
+    int64_t units_bound[2] = {0, 0};     // work units of the groups of up to 8 members, of more
+    uint32_t *units = nullptr;           // device [group_units_words(ng)]
 };
+// Unit offsets of a group set: two lists of ng + 1 offsets (groups of up to 8
+// members, of more), then one cursor per list.
+inline size_t group_units_words(int32_t ng) { return 2 * ((size_t)ng + 1) + 2; }
 
 // Tiles of a group's compacted walks, at most.
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G);

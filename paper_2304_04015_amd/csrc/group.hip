@@ -20,23 +20,55 @@
 namespace srk {
 namespace {
 
-// Length of member q's walk in an entry's packed lengths (byte q).
-__device__ __forceinline__ uint32_t glen_of(uint2 l, int q) {
-    return ((q < 4 ? l.x : l.y) >> (8 * (q & 3))) & 0xffu;
+// Tile shapes of the group meet kernel (walks and member positions per tile)
+// for groups of up to 8 members and of up to 32.
+#ifndef SRK_GROUP_TILE_J
+#define SRK_GROUP_TILE_J 1280
+#endif
+#ifndef SRK_GROUP_TILE_NODES
+#define SRK_GROUP_TILE_NODES 32768
+#endif
+#ifndef SRK_GROUP32_TILE_J
+#define SRK_GROUP32_TILE_J 512
+#endif
+#ifndef SRK_GROUP32_TILE_NODES
+#define SRK_GROUP32_TILE_NODES 28672
+#endif
+#ifndef SRK_GROUP_SLOTS
+#define SRK_GROUP_SLOTS 2
+#endif
+constexpr int GROUP_BLOCK = 1024;
+// GW: words of member lengths per entry the kernel instance holds (2: up to 8
+// members, 8: up to 32).
+__host__ __device__ constexpr int group_tile_j(int GW) {
+    return GW <= 2 ? SRK_GROUP_TILE_J : SRK_GROUP32_TILE_J;
 }
+__host__ __device__ constexpr int group_tile_nodes(int GW) {   // < 2^16
+    return GW <= 2 ? SRK_GROUP_TILE_NODES : SRK_GROUP32_TILE_NODES;
+}
+static_assert(group_tile_nodes(2) < 65536 && group_tile_nodes(2) > 8 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(8) < 65536 && group_tile_nodes(8) > 32 * MAX_CAP, "tile shape");
+static_assert(GROUP_MAX == 32, "length words");
+
+// The kernel instance for groups of G members.
+inline int group_gw(int32_t G) { return G <= 8 ? 2 : 8; }
+
+// Length of member q in an entry's length words (byte q).
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int q) { return (w >> (8 * (q & 3))) & 0xffu; }
 
 // ------------------------------------------------------------ compaction
 // One block per group.  Keeps the walk indices j for which at least one
 // member's walk j has a step, packs the members' positions of walk j back to
-// back (member 0 first), and cuts the entries into tiles of at most
-// GROUP_TILE_J entries and GROUP_TILE_NODES positions (a boundary wherever the
-// entry index crosses a multiple of GROUP_TILE_J or the packed offset a
-// multiple of NW = GROUP_TILE_NODES - G L; an entry holds at most G L
-// positions).
+// back (member 0 first), and cuts the entries into tiles of at most TJ
+// entries and TN positions (a boundary wherever the entry index crosses a
+// multiple of TJ or the packed offset a multiple of NW = TN - G L; an entry
+// holds at most G L positions).  (TJ, TN) is the shape of the kernel instance
+// that runs the group.
 __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restrict__ gd) {
     const GroupDesc &d = gd[blockIdx.x];
-    const int32_t Rmax = d.Rmax, L = d.L, G = d.G;
-    const uint32_t NW = (uint32_t)(GROUP_TILE_NODES - G * L);
+    const int32_t Rmax = d.Rmax, L = d.L, G = d.G, gw = d.gw;
+    const uint32_t TJ = (uint32_t)group_tile_j(G <= 8 ? 2 : 8);
+    const uint32_t NW = (uint32_t)(group_tile_nodes(G <= 8 ? 2 : 8) - G * L);
     const int32_t per = (Rmax + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t j0 = min(Rmax, (int32_t)threadIdx.x * per), j1 = min(Rmax, j0 + per);
     uint32_t cnt = 0, nodes = 0;
@@ -51,16 +83,20 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
     const uint32_t nb = block_excl_sum(nodes, &total);
     uint32_t k = kb, off = nb;
     for (int32_t j = j0; j < j1; ++j) {
-        uint32_t lo = 0, hi = 0, tot = 0;
-        for (int32_t q = 0; q < G; ++q) {
-            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
-            if (q < 4) lo |= l << (8 * q); else hi |= l << (8 * (q - 4));
-            tot += l;
-        }
+        uint32_t tot = 0;
+        for (int32_t q = 0; q < G; ++q) tot += j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
         if (!tot) continue;
         d.jj[k] = (uint32_t)j;
         d.joff[k] = off;
-        d.glen[k] = make_uint2(lo, hi);
+        for (int32_t wd = 0; wd < gw; ++wd) {
+            uint32_t w = 0;
+            for (int32_t b = 0; b < 4; ++b) {
+                const int32_t q = 4 * wd + b;
+                const uint32_t l = (q < G && j < d.R[q]) ? (uint32_t)d.slen[q][j] : 0u;
+                w |= l << (8 * b);
+            }
+            d.glen[(size_t)k * gw + wd] = w;
+        }
         for (int32_t q = 0; q < G; ++q) {
             const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
             const uint32_t *src = d.sw[q] + (size_t)j * L;
@@ -73,11 +109,11 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
     __syncthreads();
     uint32_t nbound = 0;
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        nbound += (e == 0) || (e % GROUP_TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
+        nbound += (e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
     uint32_t n_tiles;
     uint32_t tb = block_excl_sum(nbound, &n_tiles);
     for (uint32_t e = kb; e < kb + cnt; ++e)
-        if ((e == 0) || (e % GROUP_TILE_J == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
+        if ((e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
             d.tiles[tb++] = e;
     if (threadIdx.x == 0) {
         d.tiles[n_tiles] = E1;
@@ -87,22 +123,28 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
     }
 }
 
-// Work-unit offsets of the groups (one block): ng + 1 offsets, then the cursor.
+// Work-unit offsets of the groups (one block), one list per kernel instance
+// (groups of up to 8 members, then of up to 32): ng + 1 offsets each, then
+// one cursor each.
 __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restrict__ gd, int32_t ng,
                                                       uint32_t *__restrict__ units) {
     const int32_t per = (ng + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t g0 = min(ng, (int32_t)threadIdx.x * per), g1 = min(ng, g0 + per);
-    uint32_t sum = 0;
-    for (int32_t g = g0; g < g1; ++g) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
-    uint32_t total;
-    uint32_t run = block_excl_sum(sum, &total);
-    for (int32_t g = g0; g < g1; ++g) {
-        units[g] = run;
-        run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
-    }
-    if (threadIdx.x == 0) {
-        units[ng] = total;
-        units[ng + 1] = 0u;
+    for (int list = 0; list < 2; ++list) {
+        uint32_t sum = 0;
+        for (int32_t g = g0; g < g1; ++g)
+            if ((gd[g].G > 8) == (list == 1)) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+        uint32_t total;
+        uint32_t run = block_excl_sum(sum, &total);
+        uint32_t *u = units + list * (ng + 1);
+        for (int32_t g = g0; g < g1; ++g) {
+            u[g] = run;
+            if ((gd[g].G > 8) == (list == 1)) run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+        }
+        if (threadIdx.x == 0) {
+            u[ng] = total;
+            units[2 * (ng + 1) + list] = 0u;
+        }
     }
 }
 
@@ -112,31 +154,38 @@ __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restric
 // vb nodes with in-edges) from a device cursor, stage the tile's positions in
 // LDS, and hand the pairs (v, entry) of a unit, v-major, to the waves in chunks
 // of 64.  A lane keeps NS pairs in flight; a pair carries the entry's member
-// lengths and the mask of members still tested.  Counts go to one LDS counter
-// per (member, node), flushed to the members' counts once per unit.
+// lengths and the mask of members still tested.  A step reads the members'
+// positions of that step, then compares.  Counts go to 16-bit LDS counters per (member, node)
+// (a unit holds at most TJ < 2^16 walks), flushed to the members' counts once
+// per unit.
 
+template <int GW>
 struct GSlot {
-    uint32_t pos;    // LDS offset of the entry's positions (16 bits) | node index << 24
-    uint32_t live;   // members still tested (bit q)
-    uint2 len;       // the entry's member lengths, one byte each
-    uint32_t t;      // steps taken
-    uint32_t o, d;   // current node: slot offset in E and in-degree
+    uint32_t pos;      // LDS offset of the entry's positions (16 bits) | its longest
+                       // member walk << 16 | node index << 24
+    uint32_t live;     // members still tested (bit q)
+    uint32_t len[GW];  // the entry's member lengths, one byte each
+    uint32_t t;        // steps taken
+    uint32_t o, d;     // current node: slot offset in E and in-degree
     WalkDraws rng;
     bool busy;
 };
 
-template <int NS>
+template <int NS, int GW>
 __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__restrict__ gd, int32_t ng,
                                                             const uint32_t *__restrict__ ustart,
                                                             uint32_t *__restrict__ cursor,
                                                             unsigned long long *__restrict__ counters) {
-    __shared__ uint32_t s_nodes[GROUP_TILE_NODES];
-    __shared__ uint32_t s_j[GROUP_TILE_J];
-    __shared__ uint16_t s_off[GROUP_TILE_J];
-    __shared__ uint2 s_len[GROUP_TILE_J];
-    __shared__ uint32_t s_cnt[GROUP_MAX * MEET_VB];
+    constexpr int TJ = group_tile_j(GW), TN = group_tile_nodes(GW), GM = 4 * GW;
+    __shared__ uint32_t s_nodes[TN];
+    __shared__ uint32_t s_j[TJ];
+    __shared__ uint16_t s_off[TJ];
+    __shared__ uint32_t s_len[TJ * GW];
+    __shared__ uint32_t s_cnt[GM / 2 * MEET_VB];   // members 2i, 2i+1 in the low, high half
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
+    __shared__ uint32_t s_srcm[MEET_VB];   // members whose source is the node
+    __shared__ uint8_t s_maxl[TJ];         // longest member walk of the entry
     __shared__ uint32_t s_unit, s_item;
 
     const int lane = threadIdx.x & 63;
@@ -160,14 +209,13 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         const int32_t n_chunks = (int32_t)uni((uint32_t)d.n_chunks);
         const int32_t vb = (int32_t)uni((uint32_t)d.vb);
         const int32_t G = (int32_t)uni((uint32_t)d.G);
+        const int32_t gw = (int32_t)uni((uint32_t)d.gw);
         const uint32_t local = unit - ustart[gi];
         const uint32_t tile = local / (uint32_t)n_chunks;
         const uint32_t chunk = local - tile * (uint32_t)n_chunks;
         const PhiloxKey key{uni(d.k0), uni(d.k1)};
         const uint32_t T = uni(d.T);
-        int32_t src[GROUP_MAX];
-#pragma unroll
-        for (int q = 0; q < GROUP_MAX; ++q) src[q] = q < G ? (int32_t)uni((uint32_t)d.s[q]) : -1;
+        const uint32_t gmask = G >= 32 ? 0xffffffffu : (1u << G) - 1u;
         if ((uint32_t)gi != cur_g || tile != cur_tile) {
             const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
             const uint32_t nb = d.joff[k0], ne = d.joff[k1];
@@ -175,7 +223,16 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
             for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
                 s_j[i] = d.jj[k0 + i];
                 s_off[i] = (uint16_t)(d.joff[k0 + i] - nb);
-                s_len[i] = d.glen[k0 + i];
+                uint32_t mx = 0;
+                for (int32_t wd = 0; wd < gw; ++wd) {
+                    const uint32_t lw = d.glen[(size_t)(k0 + i) * gw + wd];
+                    mx = max(mx, max(max(byte_of(lw, 0), byte_of(lw, 1)), max(byte_of(lw, 2), byte_of(lw, 3))));
+                }
+                s_maxl[i] = (uint8_t)mx;
+            }
+            for (uint32_t i = threadIdx.x; i < K * GW; i += blockDim.x) {
+                const uint32_t k = i / GW, wd = i - k * GW;
+                s_len[i] = (int32_t)wd < gw ? d.glen[(size_t)(k0 + k) * gw + wd] : 0u;
             }
             for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.pos[nb + i];
             cur_g = (uint32_t)gi;
@@ -183,11 +240,14 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         }
         const int32_t vbase = (int32_t)chunk * vb;
         const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
-        for (uint32_t i = threadIdx.x; i < GROUP_MAX * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < GM / 2 * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
             const uint32_t id = (uint32_t)d.active[vbase + (int32_t)i];
             s_vid[i] = id;
             s_vrow[i] = d.nodes[id];
+            uint32_t m = 0;
+            for (int32_t q = 0; q < G; ++q) m |= (uint32_t)((uint32_t)d.s[q] == id) << q;
+            s_srcm[i] = m;
         }
         if (threadIdx.x == 0) s_item = 0u;
         __syncthreads();
@@ -196,7 +256,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         const uint32_t total = nv * K;
         uint32_t ci = 0, ce = 0, cvl = 0, ck = 0;
         bool drained = false;
-        GSlot sl[NS];
+        GSlot<GW> sl[NS];
 #pragma unroll
         for (int qq = 0; qq < NS; ++qq) sl[qq].busy = false;
 
@@ -233,19 +293,17 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                             k -= K;
                             ++vl;
                         }
-                        const int32_t id = (int32_t)s_vid[vl];
-                        const uint2 ln = s_len[k];
-                        uint32_t live = 0;
-#pragma unroll
-                        for (int q = 0; q < GROUP_MAX; ++q)
-                            if (glen_of(ln, q) != 0u && id != src[q]) live |= 1u << q;
+                        // members tested: all but those whose source is v (a
+                        // member whose walk j is empty never reads a position)
+                        const uint32_t live = gmask & ~s_srcm[vl];
                         if (live) {
                             const uint2 row = s_vrow[vl];
-                            GSlot &w = sl[qq];
-                            w.rng = walk_draws_begin((uint32_t)id, s_j[k], key);
-                            w.pos = (uint32_t)s_off[k] | (vl << 24);
+                            GSlot<GW> &w = sl[qq];
+                            w.rng = walk_draws_begin(s_vid[vl], s_j[k], key);
+                            w.pos = (uint32_t)s_off[k] | ((uint32_t)s_maxl[k] << 16) | (vl << 24);
                             w.live = live;
-                            w.len = ln;
+#pragma unroll
+                            for (int wd = 0; wd < GW; ++wd) w.len[wd] = s_len[k * GW + wd];
                             w.t = 0;
                             w.o = row.x;
                             w.d = row.y;
@@ -298,35 +356,66 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
             for (int qq = 0; qq < NS; ++qq) {
                 if (!go[qq]) continue;
                 ++st_moves;
-                GSlot &w = sl[qq];
+                GSlot<GW> &w = sl[qq];
                 w.o = e[qq].x;
                 w.d = e[qq].y;
                 const uint32_t vl = w.pos >> 24;
-                // member q's position t is at its own offset within the entry
-                uint32_t off = (w.pos & 0xffffu) + w.t - 1u;
-                uint32_t live = w.live;
+                // Member q's positions lie at [B_q, B_q + len_q) within the
+                // tile, B_0 the entry's offset and B_{q+1} = B_q + len_q;
+                // position t of member q is read only if t <= len_q (else a
+                // harmless word).  A hit on any member sends the lane to an
+                // exact pass that keeps the members still tested; meets are
+                // rare, so the common step is reads and compares only.
+                const uint32_t t1 = w.t - 1u;
+                uint32_t B = w.pos & 0xffffu;
+                bool hit = false;
 #pragma unroll
-                for (int q = 0; q < GROUP_MAX; ++q) {
-                    const uint32_t lq = glen_of(w.len, q);
-                    if (live & (1u << q)) {
-                        if (w.o == s_nodes[off]) {
-                            atomicAdd(&s_cnt[q * MEET_VB + vl], 1u);
-                            ++st_meets;
-                            live &= ~(1u << q);
-                        } else if (w.t == lq) {
-                            live &= ~(1u << q);
+                for (int wd = 0; wd < GW; ++wd) {
+                    if (wd >= gw) break;   // the group's last length word (uniform)
+                    const uint32_t lw = w.len[wd];
+                    uint32_t pv[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const uint32_t l = byte_of(lw, b);
+                        pv[b] = s_nodes[t1 < l ? B + t1 : 0u];
+                        B += l;
+                    }
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) hit |= pv[b] == w.o;
+                }
+                if (hit) {
+                    uint32_t met = 0;
+                    B = w.pos & 0xffffu;
+#pragma unroll
+                    for (int wd = 0; wd < GW; ++wd) {
+                        if (wd >= gw) break;
+                        const uint32_t lw = w.len[wd];
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const uint32_t l = byte_of(lw, b);
+                            if (t1 < l && s_nodes[B + t1] == w.o) met |= 1u << (4 * wd + b);
+                            B += l;
                         }
                     }
-                    off += lq;
+                    met &= w.live;
+                    if (met) {
+                        st_meets += (uint32_t)__popc(met);
+                        w.live &= ~met;
+                        for (uint32_t m = met; m; m &= m - 1u) {
+                            const uint32_t q = (uint32_t)__builtin_ctz(m);
+                            atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
+                        }
+                    }
                 }
-                w.live = live;
-                if (live == 0u || w.d == 0u) w.busy = false;
+                // the pair ends with its last member walk, when every member
+                // tested has met, or at a node without in-neighbours
+                if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu)) w.busy = false;
             }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < (uint32_t)G * nv; i += blockDim.x) {
             const uint32_t q = i / nv, vi = i - q * nv;
-            const uint32_t c = s_cnt[q * MEET_VB + vi];
+            const uint32_t c = (s_cnt[(q >> 1) * MEET_VB + vi] >> (16 * (q & 1u))) & 0xffffu;
             if (c) atomicAdd(&d.cnt[q][s_vid[vi]], c);
         }
     }
@@ -346,16 +435,13 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
     }
 }
 
-#ifndef SRK_GROUP_SLOTS
-#define SRK_GROUP_SLOTS 2
-#endif
-
+template <int GW>
 int group_grid_blocks() {
     static const int blocks = [] {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<SRK_GROUP_SLOTS>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<SRK_GROUP_SLOTS, GW>,
                                                            GROUP_BLOCK, 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
@@ -367,18 +453,25 @@ int group_grid_blocks() {
 }  // namespace
 
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
-    const int64_t NW = GROUP_TILE_NODES - (int64_t)G * L;
-    return (int32_t)(2 + Rmax / GROUP_TILE_J + sum_RL / NW);
+    const int GW = group_gw(G);
+    const int64_t NW = group_tile_nodes(GW) - (int64_t)G * L;
+    return (int32_t)(2 + Rmax / group_tile_j(GW) + sum_RL / NW);
 }
 
 int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st) {
     if (gs.ng <= 0) return SIMRANK_OK;
     k_group_compact<<<gs.ng, 1024, 0, st>>>(gs.desc);
     k_group_units<<<1, 1024, 0, st>>>(gs.desc, gs.ng, gs.units);
-    if (gs.units_bound > 0) {
-        const int blocks = (int)std::min<int64_t>(gs.units_bound, group_grid_blocks());
-        k_meet_group<SRK_GROUP_SLOTS><<<blocks, GROUP_BLOCK, 0, st>>>(
-            gs.desc, gs.ng, gs.units, gs.units + gs.ng + 1, counters);
+    uint32_t *cursors = gs.units + 2 * (gs.ng + 1);
+    if (gs.units_bound[0] > 0) {
+        const int blocks = (int)std::min<int64_t>(gs.units_bound[0], group_grid_blocks<2>());
+        k_meet_group<SRK_GROUP_SLOTS, 2><<<blocks, GROUP_BLOCK, 0, st>>>(gs.desc, gs.ng, gs.units,
+                                                                         cursors, counters);
+    }
+    if (gs.units_bound[1] > 0) {
+        const int blocks = (int)std::min<int64_t>(gs.units_bound[1], group_grid_blocks<8>());
+        k_meet_group<SRK_GROUP_SLOTS, 8><<<blocks, GROUP_BLOCK, 0, st>>>(
+            gs.desc, gs.ng, gs.units + (gs.ng + 1), cursors + 1, counters);
     }
     SRK_HIP(hipGetLastError());
     return SIMRANK_OK;

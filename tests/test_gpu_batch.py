@@ -143,11 +143,12 @@ def test_batch_with_stratified_queries(graphs):
 
 def test_shared_seed_groups_equal_lone_queries(graphs):
     """Plain queries with equal (graph, seed, c, cap) run in groups that share
-    the walks from every node: 11 on one graph (two groups, members with
-    different R spanning several group tiles with a ragged last one, a repeated
-    source, a source without in-edges), 3 on another, 2 with another cap, 2 on
-    the star graph; stitched and stratified queries with the same seed and
-    lone plain queries stay out of the groups.  Every result equals the lone
+    the walks from every node: 11 on one graph (a group of more than 8 members
+    with different R, spanning several group tiles with a ragged last one, a
+    repeated source, a source without in-edges), 3 on another, 2 with another
+    cap, 2 on the star graph, 40 on the small graph with another seed (two
+    groups of 20); stitched and stratified queries with the same seed and lone
+    plain queries stay out of the groups.  Every result equals the lone
     query's and the ungrouped plan's, bit for bit."""
     gs, Gs = graphs
     g2 = gs[2]
@@ -162,6 +163,9 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
            for s in rng.choice(np.nonzero(gs[0].in_degree() > 0)[0], 3, replace=False)]
     qs += [S.make_query(srcs[k], c=0.6, seed=S2, walk_cap=20, R=2048, graph=2) for k in (1, 2)]
     qs += [S.make_query(s, c=0.6, seed=S1, walk_cap=64, R=900, graph=3) for s in (1, 0)]
+    act0 = np.nonzero(gs[0].in_degree() > 0)[0]
+    qs += [S.make_query(int(s), c=0.6, seed=S2, walk_cap=64, R=int(R), graph=0)
+           for s, R in zip(rng.choice(act0, 40), rng.integers(200, 3000, 40))]
     qs += [S.make_query(srcs[3], c=0.5, seed=S1, walk_cap=64, R=3000, graph=2)]   # lone: other c
     qs += [S.make_query(int(np.nonzero(gs[1].in_degree() > 0)[0][3]), c=0.6, seed=S1,
                         walk_cap=64, R=3000, graph=1, mode=S.MODE_STITCHED)]
@@ -170,7 +174,7 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
     qs = [qs[i] for i in order]
     _say(f"shared-seed batch: {len(qs)} queries")
     plan = S.BatchPlan(Gs, qs)
-    assert plan.n_groups == 5
+    assert plan.n_groups == 6
     plan.run()
     st_g = plan.wait()
     flat = S.BatchPlan(Gs, qs, groups=False)
@@ -189,20 +193,22 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
     assert st_g.meets == st_f.meets
     assert st_g.moves < st_f.moves            # the shared walks are taken once
     # a member on the small graph against the oracle
-    i = next(k for k, q in enumerate(qs) if q.graph == 0)
-    want = O.meet_counts_plain(gs[0], qs[i].s, S1, 0.6, 64, 1500)
-    assert np.array_equal(plan.read(i)[1], want)
+    for seed in (S1, S2):
+        i = next(k for k, q in enumerate(qs) if q.graph == 0 and q.seed == seed)
+        want = O.meet_counts_plain(gs[0], qs[i].s, seed, 0.6, 64, qs[i].R_override)
+        assert np.array_equal(plan.read(i)[1], want), seed
     plan.free()
     flat.free()
 
 
-def test_shared_seed_group_full_size():
-    """Eight queries with the medium workload's shape (2^16-node R-MAT graph,
-    eps 0.02, R = 9,502, cap 64) and one seed: the group's counts equal the
-    lone queries', bit for bit."""
+@pytest.mark.parametrize("nq", [8, 21])
+def test_shared_seed_group_full_size(nq):
+    """Queries with the medium workload's shape (2^16-node R-MAT graph, eps
+    0.02, R = 9,502, cap 64) and one seed, as one group of 8 and one of 21:
+    the group's counts equal the lone queries', bit for bit."""
     g = inputs.rmat_in(16, 16 << 16, seed=72)
     G = S.load_csr(g)
-    srcs = [int(x) for x in inputs.sources_with_in_edges(g, 8, 74)]
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, 74)]
     qs = [S.make_query(s, c=0.6, eps=0.02, delta=1e-3, seed=0x2304040150000053, walk_cap=64)
           for s in srcs]
     assert S.simrank_derive_params(qs[0], g.n).R == 9502
@@ -210,7 +216,7 @@ def test_shared_seed_group_full_size():
     assert plan.n_groups == 1
     plan.run()
     st = plan.wait()
-    _say(f"group of 8 at full size: {st.ms:.1f} ms, {st.moves} moves")
+    _say(f"group of {nq} at full size: {st.ms:.1f} ms, {st.moves} moves")
     for i, q in enumerate(qs):
         assert np.array_equal(plan.read(i, want_out=False)[1], S.simrank_single_source_ex(G, q)[1]), i
     plan.free()
