@@ -82,6 +82,9 @@ def parse():
                          "graph's 8 sources (and 32) through Algorithm 2's tuple form")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
+    ap.add_argument("--group-max", type=int, default=0,
+                    help="serving: admit waiting requests with one walk seed as query groups of "
+                         "up to this many (0: every request alone, with its own seed)")
     ap.add_argument("--group-queries", type=int, default=32,
                     help="grouped: number of same-seed queries on the medium graph")
     ap.add_argument("--shared-seed", action="store_true",
@@ -741,7 +744,10 @@ def bench_serving(args):
     eps uniform in {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks.  First the
     plain capacity (requests back to back, one at a time); then Poisson arrivals
     at 0.5, 0.8, 1.0 and 1.2 times that rate into the server (4 slots):
-    achieved queries/s and p50 / p99 latency per level."""
+    achieved queries/s and p50 / p99 latency per level.  --group-max G: the
+    requests share one walk seed and the server (max(4, G) slots) admits those
+    waiting together as query groups of up to G; offered loads 0.5 to 4 times
+    the plain capacity."""
     import numpy as np
     import torch
 
@@ -762,8 +768,9 @@ def bench_serving(args):
 
     def make(i):
         s = int(rng.choice(g.n, p=deg / deg.sum()))
+        seed = 0x2304040150000500 + (0 if args.group_max >= 2 else i)
         return S.make_query(s, c=cfg["c"], eps=float(rng.choice(cfg["eps_choices"])),
-                            delta=cfg["delta"], seed=0x2304040150000500 + i, walk_cap=cfg["L"],
+                            delta=cfg["delta"], seed=seed, walk_cap=cfg["L"],
                             mode=S.MODE_STITCHED)
 
     S.simrank_tune(G, make(0))
@@ -794,10 +801,12 @@ def bench_serving(args):
     footprint = 8 * (gi["m"] + gi["n"] - gi["n_active"])
     gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
     kernel_rate = kmoves / (kms / 1e3)
-    srv = S.Server(G, max_slots=4, max_R=9502, max_L=cfg["L"])
+    grouped = args.group_max >= 2
+    srv = S.Server(G, max_slots=max(4, args.group_max), max_R=9502, max_L=cfg["L"],
+                   group_max=args.group_max)
     levels = []
     k = 1000
-    for load in (0.5, 0.8, 1.0, 1.2):
+    for load in ((0.5, 1.0, 2.0, 3.0, 4.0) if grouped else (0.5, 0.8, 1.0, 1.2)):
         qps = load * capacity
         reqs = [make(k + i) for i in range(args.requests)]
         k += args.requests
@@ -835,13 +844,19 @@ def bench_serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"serving: R-MAT n=2^{cfg['scale']}, avg degree 16, index "
-                               "resident; sources by in-degree, eps in {.05,.02}, stitched; "
-                               "Poisson arrivals at 0.5-1.2x plain capacity; 4 slots",
-                   "n": g.n, "m": g.m, "requests_per_level": args.requests},
+                               "resident; sources by in-degree, eps in {.05,.02}, stitched; " +
+                               (f"one walk seed, query groups of up to {args.group_max}; Poisson "
+                                "arrivals at 0.5-4x plain capacity; "
+                                f"{max(4, args.group_max)} slots" if grouped else
+                                "a seed per request; Poisson arrivals at 0.5-1.2x plain "
+                                "capacity; 4 slots"),
+                   "n": g.n, "m": g.m, "requests_per_level": args.requests,
+                   "group_max": args.group_max},
         "queries_per_s": top["achieved_qps"],
         "plain_queries_per_s": capacity,
         "served_vs_plain": top["achieved_qps"] / capacity,
         "levels": levels,
+        "server_counts": srv.counts(),
         "roofline": {
             "bound": "hbm",
             "kernel": "k_meet<stitched> (fused walk + meet + count), requests one at a time",

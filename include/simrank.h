@@ -351,7 +351,16 @@ typedef struct simrank_server_params {
     int32_t max_slots;    /* 1..64 concurrent requests */
     int32_t max_R;        /* largest R a request may need */
     int32_t max_L;        /* largest walk cap a request may use */
-    int32_t reserved;
+    int32_t group_max;    /* 0 or 1: every request runs alone.  2..32: requests
+                             with equal mode, seed, c and cap that wait together
+                             are admitted as one query group of up to group_max
+                             (and at most the free slots), which takes each
+                             walk (v, j) once for all of them (Section 3's walk
+                             (v, j) does not depend on the source); while the
+                             group runs, new requests wait to form the next
+                             one.  A grouped request's stats are its share
+                             (1/G) of its group's work and the group's device
+                             time. */
     int64_t hbm_budget;   /* device bytes the slots may take; 0: half the free memory */
 } simrank_server_params;
 
@@ -361,11 +370,16 @@ typedef struct simrank_request_info {
     simrank_stats stats;  /* work and device time of the request */
 } simrank_request_info;
 
-/* The graph must outlive the server.  ENOMEM when the budget admits no slot. */
+/* The graph must outlive the server.  ENOMEM when the budget admits no slot;
+ * EINVAL for group_max outside [0, 32]. */
 int simrank_server_create(simrank_graph *g, const simrank_server_params *p,
                           simrank_server **server_out);
 /* Slots made and device bytes per slot. */
 int simrank_server_info(const simrank_server *server, int32_t *slots, int64_t *slot_bytes);
+/* Requests finished and failed so far, query groups launched and the
+ * requests they held (each pointer may be NULL). */
+int simrank_server_counts(simrank_server *server, uint64_t *done, uint64_t *failed,
+                          uint64_t *groups, uint64_t *grouped);
 /* Validates and queues a query (q->graph ignored); returns at once with a ticket. */
 int simrank_server_submit(simrank_server *server, const simrank_query *q, uint64_t *ticket);
 /* Waits up to timeout_s seconds (< 0: no limit) for the request, copies its

@@ -39,24 +39,18 @@ size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
     return b;
 }
 
-// Device bytes of a group's compacted walks.
-size_t group_bytes(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
-    return align_up(4 * (size_t)Rmax) + align_up(4 * ((size_t)Rmax + 1)) +
-           align_up(4 * (size_t)Rmax * (size_t)((G + 3) / 4)) +
-           align_up(4 * (size_t)sum_RL) + align_up(4 * ((size_t)group_max_tiles(Rmax, sum_RL, L, G) + 1)) +
-           align_up(32);
-}
-
-// Groups of plain queries that share (graph, seed, continue threshold, cap):
+// Groups of plain queries, and of stitched queries, that share (graph, seed,
+// continue threshold, cap):
 // each such set of two or more queries is split into ceil(size / GROUP_MAX)
 // groups of nearly equal size, in query order.
 std::vector<std::vector<int32_t>> form_groups(simrank_graph *const *graphs, const simrank_query *qs,
                                               int32_t nq, const std::vector<simrank_params> &ps,
                                               const std::vector<int> &modes) {
-    std::map<std::tuple<const Graph *, uint64_t, uint32_t, int32_t>, std::vector<int32_t>> by;
+    std::map<std::tuple<const Graph *, int, uint64_t, uint32_t, int32_t>, std::vector<int32_t>> by;
     for (int32_t i = 0; i < nq; ++i)
-        if (modes[i] == SIMRANK_MODE_PLAIN)
-            by[std::make_tuple((const Graph *)graphs[qs[i].graph], qs[i].seed, ps[i].T, ps[i].L)]
+        if (modes[i] == SIMRANK_MODE_PLAIN || modes[i] == SIMRANK_MODE_STITCHED)
+            by[std::make_tuple((const Graph *)graphs[qs[i].graph], modes[i], qs[i].seed, ps[i].T,
+                               ps[i].L)]
                 .push_back(i);
     std::vector<std::vector<int32_t>> out;
     for (auto &kv : by) {
@@ -195,8 +189,14 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
     size_t total = 0;
     for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], modes[i], graphs[qs[i].graph]->n);
-    for (int32_t k = 0; k < ngr; ++k)
-        total += group_bytes(g_Rmax[k], g_RL[k], ps[groups[k][0]].L, (int32_t)groups[k].size());
+    for (int32_t k = 0; k < ngr; ++k) {
+        GroupDesc gd{};
+        gd.Rmax = (int32_t)g_Rmax[k];
+        gd.L = ps[groups[k][0]].L;
+        gd.G = (int32_t)groups[k].size();
+        gd.gw = (gd.G + 3) / 4;
+        total += group_buffers(&gd, g_RL[k], nullptr);
+    }
     size_t free_b = 0, tot_b = 0;
     if (hipMemGetInfo(&free_b, &tot_b) == hipSuccess && total > free_b)
         return bail(fail(SIMRANK_ENOMEM, "batch needs " + std::to_string(total) +
@@ -256,7 +256,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
         if (group_of[i] >= 0) {
-            d.kind = K_GROUPED;   // walked with its group
+            d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED : K_GROUPED;   // walked with its group
         } else {
             const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
             set.units_bound[d.kind] += ub;
@@ -266,38 +266,13 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
     p->gdesc.resize(ngr);
     for (int32_t k = 0; k < ngr; ++k) {
         const std::vector<int32_t> &m = groups[k];
-        const QueryDesc &d0 = p->desc[m[0]];
+        std::vector<const QueryDesc *> mem;
+        for (int32_t i : m) mem.push_back(&p->desc[i]);
         GroupDesc &gd = p->gdesc[k];
-        gd = GroupDesc{};
-        gd.nodes = d0.nodes;
-        gd.E = d0.E;
-        gd.active = d0.active;
-        gd.n_active = d0.n_active;
-        gd.vb = d0.vb;
-        gd.n_chunks = d0.n_chunks;
-        gd.G = (int32_t)m.size();
-        gd.gw = (gd.G + 3) / 4;
-        gd.L = d0.L;
-        gd.Rmax = (int32_t)g_Rmax[k];
-        gd.k0 = d0.k0;
-        gd.k1 = d0.k1;
-        gd.T = d0.T;
-        for (int32_t q = 0; q < gd.G; ++q) {
-            const QueryDesc &dq = p->desc[m[q]];
-            gd.s[q] = dq.s;
-            gd.R[q] = dq.R;
-            gd.sw[q] = dq.sw;
-            gd.slen[q] = dq.slen;
-            gd.cnt[q] = dq.cnt;
-        }
-        const int32_t mt = group_max_tiles(g_Rmax[k], g_RL[k], gd.L, gd.G);
-        gd.jj = (uint32_t *)take(4 * (size_t)gd.Rmax);
-        gd.joff = (uint32_t *)take(4 * ((size_t)gd.Rmax + 1));
-        gd.glen = (uint32_t *)take(4 * (size_t)gd.Rmax * gd.gw);
-        gd.pos = (uint32_t *)take(4 * (size_t)g_RL[k]);
-        gd.tiles = (uint32_t *)take(4 * ((size_t)mt + 1));
-        gd.meta = (uint32_t *)take(32);
-        gset.units_bound[gd.G > 8] += (int64_t)mt * gd.n_chunks;
+        describe_group(mem.data(), (int32_t)m.size(), &gd);
+        const int32_t mt = group_max_tiles(gd.Rmax, g_RL[k], gd.L, gd.G);
+        (void)take(group_buffers(&gd, g_RL[k], cur));   // carved at cur, which it advances
+        gset.units_bound[group_list(gd.G, gd.stitched)] += (int64_t)mt * gd.n_chunks;
     }
     if (ngr > 0) {
         e = hipMemcpy(p->gdesc_dev, p->gdesc.data(), sizeof(GroupDesc) * ngr, hipMemcpyHostToDevice);
@@ -454,7 +429,7 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         while (i1 < nq) {
             const size_t b = query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) +
                              sizeof(QueryDesc) + 64 +
-                             (modes[i1] == SIMRANK_MODE_PLAIN   // its share of a group's buffers
+                             (modes[i1] != SIMRANK_MODE_STRATIFIED   // its share of a group's buffers
                                   ? 4 * (size_t)ps[i1].R * ps[i1].L + 16 * (size_t)ps[i1].R + 1024
                                   : 0);
             if (i1 > i0 && used + b > budget) break;

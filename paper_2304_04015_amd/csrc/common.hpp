@@ -203,14 +203,14 @@ struct QuerySet {
 inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1) + N_KINDS; }
 
 // ------------------------------------------------------------ query groups
-// In a batch, plain queries on one graph with the same walk key, continue
-// threshold and cap have the same walk (v, j) from every node v: a group of up
-// to GROUP_MAX such queries follows each walk once and tests it against every
-// member's walk j of its own source (group.hip).  A member keeps its own
-// descriptor (source walks, counts, estimate) with kind K_GROUPED, which no
-// per-kind unit list takes.
+// In a batch, plain (or stitched) queries on one graph with the same walk key,
+// continue threshold and cap have the same walk (v, j) from every node v: a
+// group of up to GROUP_MAX such queries follows each walk once and tests it
+// against every member's walk j of its own source (group.hip).  A member keeps
+// its own descriptor (source walks, counts, estimate) with kind K_GROUPED or
+// K_GROUPED_STITCHED, which no per-kind unit list takes.
 constexpr int GROUP_MAX = 32;
-constexpr int32_t K_GROUPED = N_KINDS;
+constexpr int32_t K_GROUPED = N_KINDS, K_GROUPED_STITCHED = N_KINDS + 1;
 
 struct GroupDesc {
     const uint2 *nodes;
@@ -219,6 +219,8 @@ struct GroupDesc {
     int32_t n_active, vb, n_chunks;
     int32_t G, L, Rmax;
     int32_t gw;                          // words of member lengths per entry: ceil(G / 4)
+    int32_t stitched;                    // members' walks have index tails
+    IndexView ix;
     uint32_t k0, k1, T;
     int32_t s[GROUP_MAX];                // members' sources
     int32_t R[GROUP_MAX];
@@ -240,15 +242,25 @@ struct GroupDesc {
 struct GroupSet {
     const GroupDesc *desc = nullptr;     // device [ng]
     int32_t ng = 0;
-    int64_t units_bound[2] = {0, 0};     // work units of the groups of up to 8 members, of more
+    int64_t units_bound[4] = {0, 0, 0, 0};   // work units per kernel instance (group_list)
     uint32_t *units = nullptr;           // device [group_units_words(ng)]
 };
-// Unit offsets of a group set: two lists of ng + 1 offsets (groups of up to 8
-// members, of more), then one cursor per list.
-inline size_t group_units_words(int32_t ng) { return 2 * ((size_t)ng + 1) + 2; }
+// Kernel instance of a group: plain walks with up to 8 members (0) or more
+// (1), stitched walks with up to 8 (2) or more (3).
+__host__ __device__ inline int group_list(int32_t G, int32_t stitched) { return (G > 8 ? 1 : 0) + (stitched ? 2 : 0); }
+// Unit offsets of a group set: one list of ng + 1 offsets per instance, then
+// one cursor per list.
+inline size_t group_units_words(int32_t ng) { return 4 * ((size_t)ng + 1) + 4; }
 
 // Tiles of a group's compacted walks, at most.
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G);
+// Fills a group's descriptor (all but its compaction buffers jj .. meta) from
+// the descriptors of its G members (kinds K_GROUPED or K_GROUPED_STITCHED,
+// buffers attached).
+void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd);
+// Device bytes of a group's compaction buffers and their carving from `base`
+// (256-byte aligned pieces); returns the bytes taken.
+size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base);
 // Enqueues a query set's groups: compaction, unit offsets, the group meet
 // kernel (after the members' source walks, before their estimates).
 int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st);

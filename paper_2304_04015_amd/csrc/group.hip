@@ -124,26 +124,26 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
 }
 
 // Work-unit offsets of the groups (one block), one list per kernel instance
-// (groups of up to 8 members, then of up to 32): ng + 1 offsets each, then
-// one cursor each.
+// (group_list: plain or stitched walks, up to 8 members or more): ng + 1
+// offsets each, then one cursor each.
 __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restrict__ gd, int32_t ng,
                                                       uint32_t *__restrict__ units) {
     const int32_t per = (ng + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t g0 = min(ng, (int32_t)threadIdx.x * per), g1 = min(ng, g0 + per);
-    for (int list = 0; list < 2; ++list) {
+    for (int list = 0; list < 4; ++list) {
         uint32_t sum = 0;
         for (int32_t g = g0; g < g1; ++g)
-            if ((gd[g].G > 8) == (list == 1)) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+            if (group_list(gd[g].G, gd[g].stitched) == list) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
         uint32_t total;
         uint32_t run = block_excl_sum(sum, &total);
         uint32_t *u = units + list * (ng + 1);
         for (int32_t g = g0; g < g1; ++g) {
             u[g] = run;
-            if ((gd[g].G > 8) == (list == 1)) run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+            if (group_list(gd[g].G, gd[g].stitched) == list) run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
         }
         if (threadIdx.x == 0) {
             u[ng] = total;
-            units[2 * (ng + 1) + list] = 0u;
+            units[4 * (ng + 1) + list] = 0u;
         }
     }
 }
@@ -155,9 +155,11 @@ __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restric
 // LDS, and hand the pairs (v, entry) of a unit, v-major, to the waves in chunks
 // of 64.  A lane keeps NS pairs in flight; a pair carries the entry's member
 // lengths and the mask of members still tested.  A step reads the members'
-// positions of that step, then compares.  Counts go to 16-bit LDS counters per (member, node)
-// (a unit holds at most TJ < 2^16 walks), flushed to the members' counts once
-// per unit.
+// positions of that step, then compares.  Counts go to 16-bit LDS counters per
+// (member, node) (a unit holds at most TJ < 2^16 walks), flushed to the
+// members' counts once per unit.  STITCHED: the walk's first 2^k steps are
+// its own draws, the rest is read from the segment index, one load per
+// iteration, as in the single-query kernel.
 
 template <int GW>
 struct GSlot {
@@ -169,9 +171,65 @@ struct GSlot {
     uint32_t o, d;     // current node: slot offset in E and in-degree
     WalkDraws rng;
     bool busy;
+    uint32_t ph;       // stitched: 0 head; 1 node id, 2 pool offsets, 3 segment length,
+                       // 4 tail step; 5 chain, 6 next segment's length
+    uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position,
+                                        // segment, its length
 };
 
-template <int NS, int GW>
+// Compares the pair's position at step t with every member's position t.
+// Member q's positions lie at [B_q, B_q + len_q) within the tile, B_0 the
+// entry's offset and B_{q+1} = B_q + len_q; position t of member q is read only
+// if t <= len_q (else a harmless word).  A hit on any member sends the lane to
+// an exact pass that credits the members still tested; meets are rare, so the
+// common step is reads and compares only.
+template <int GW>
+__device__ __forceinline__ void group_compare(GSlot<GW> &w, const uint32_t *s_nodes, uint32_t *s_cnt,
+                                              int32_t gw, uint32_t &st_meets) {
+    const uint32_t t1 = w.t - 1u;
+    uint32_t B = w.pos & 0xffffu;
+    bool hit = false;
+#pragma unroll
+    for (int wd = 0; wd < GW; ++wd) {
+        if (wd >= gw) break;   // the group's last length word (uniform)
+        const uint32_t lw = w.len[wd];
+        uint32_t pv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t l = byte_of(lw, b);
+            pv[b] = s_nodes[t1 < l ? B + t1 : 0u];
+            B += l;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) hit |= pv[b] == w.o;
+    }
+    if (!hit) return;
+    uint32_t met = 0;
+    B = w.pos & 0xffffu;
+#pragma unroll
+    for (int wd = 0; wd < GW; ++wd) {
+        if (wd >= gw) break;
+        const uint32_t lw = w.len[wd];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t l = byte_of(lw, b);
+            if (t1 < l && s_nodes[B + t1] == w.o) met |= 1u << (4 * wd + b);
+            B += l;
+        }
+    }
+    met &= w.live;
+    if (met) {
+        const uint32_t vl = w.pos >> 24;
+        st_meets += (uint32_t)__popc(met);
+        w.live &= ~met;
+        for (uint32_t m = met; m; m &= m - 1u) {
+            const uint32_t q = (uint32_t)__builtin_ctz(m);
+            atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
+        }
+    }
+}
+
+template <int NS, int GW, bool STITCHED>
 __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__restrict__ gd, int32_t ng,
                                                             const uint32_t *__restrict__ ustart,
                                                             uint32_t *__restrict__ cursor,
@@ -192,7 +250,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
     const uint32_t n_units = ustart[ng];
     uint32_t cur_g = 0xffffffffu, cur_tile = 0xffffffffu;
     uint32_t K = 0;
-    uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_pairs = 0;
+    uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_pairs = 0, st_tail = 0;
 
     for (;;) {
         if (threadIdx.x == 0) s_unit = atomicAdd(cursor, 1u);
@@ -258,11 +316,14 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         bool drained = false;
         GSlot<GW> sl[NS];
 #pragma unroll
-        for (int qq = 0; qq < NS; ++qq) sl[qq].busy = false;
+        for (int qq = 0; qq < NS; ++qq) {
+            sl[qq].busy = false;
+            sl[qq].ph = 0;
+        }
 
         for (;;) {
             // ---- refill idle slots; a pair with no member to test (each
-            // member's walk j is empty or starts at v itself) is skipped
+            // member's source is v) is skipped
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 uint64_t need = __ballot(!sl[qq].busy);
@@ -308,6 +369,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                             w.o = row.x;
                             w.d = row.y;
                             w.busy = true;
+                            w.ph = 0;
                             filled = true;
                             ++st_pairs;
                         }
@@ -329,14 +391,15 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                 continue;
             }
 
-            // ---- one step of every busy pair: draws, gathers, compares
+            // ---- head steps: draws, then one load per slot (a head step's
+            // gather or the load its stitched tail phase needs), then compares
             bool go[NS];
             uint32_t at[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 go[qq] = false;
                 at[qq] = 0;
-                if (sl[qq].busy) {
+                if (sl[qq].busy && !(STITCHED && sl[qq].ph)) {
                     ++sl[qq].t;
                     const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
@@ -349,9 +412,23 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                 }
             }
             uint2 e[NS];
+            uint32_t tv[NS];
+            int64_t tb[NS], te[NS];
 #pragma unroll
-            for (int qq = 0; qq < NS; ++qq)
+            for (int qq = 0; qq < NS; ++qq) {
                 if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
+                if (STITCHED && sl[qq].busy && sl[qq].ph) {
+                    const GSlot<GW> &w = sl[qq];
+                    switch (w.ph) {
+                    case 1: tv[qq] = d.ix.node_of[w.o]; break;
+                    case 2: tb[qq] = d.ix.pool_off[w.tsig]; te[qq] = d.ix.pool_off[w.tsig + 1]; break;
+                    case 3:
+                    case 6: tv[qq] = d.ix.seg_lens[w.tseg]; break;
+                    case 4: tv[qq] = d.ix.seg[(size_t)w.tseg * d.ix.seg_len + w.tu]; break;
+                    default: tv[qq] = d.ix.chain[(size_t)w.tsig * d.ix.width + w.tm + 1]; break;
+                    }
+                }
+            }
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 if (!go[qq]) continue;
@@ -359,57 +436,63 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                 GSlot<GW> &w = sl[qq];
                 w.o = e[qq].x;
                 w.d = e[qq].y;
-                const uint32_t vl = w.pos >> 24;
-                // Member q's positions lie at [B_q, B_q + len_q) within the
-                // tile, B_0 the entry's offset and B_{q+1} = B_q + len_q;
-                // position t of member q is read only if t <= len_q (else a
-                // harmless word).  A hit on any member sends the lane to an
-                // exact pass that keeps the members still tested; meets are
-                // rare, so the common step is reads and compares only.
-                const uint32_t t1 = w.t - 1u;
-                uint32_t B = w.pos & 0xffffu;
-                bool hit = false;
-#pragma unroll
-                for (int wd = 0; wd < GW; ++wd) {
-                    if (wd >= gw) break;   // the group's last length word (uniform)
-                    const uint32_t lw = w.len[wd];
-                    uint32_t pv[4];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const uint32_t l = byte_of(lw, b);
-                        pv[b] = s_nodes[t1 < l ? B + t1 : 0u];
-                        B += l;
-                    }
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) hit |= pv[b] == w.o;
-                }
-                if (hit) {
-                    uint32_t met = 0;
-                    B = w.pos & 0xffffu;
-#pragma unroll
-                    for (int wd = 0; wd < GW; ++wd) {
-                        if (wd >= gw) break;
-                        const uint32_t lw = w.len[wd];
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const uint32_t l = byte_of(lw, b);
-                            if (t1 < l && s_nodes[B + t1] == w.o) met |= 1u << (4 * wd + b);
-                            B += l;
-                        }
-                    }
-                    met &= w.live;
-                    if (met) {
-                        st_meets += (uint32_t)__popc(met);
-                        w.live &= ~met;
-                        for (uint32_t m = met; m; m &= m - 1u) {
-                            const uint32_t q = (uint32_t)__builtin_ctz(m);
-                            atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
-                        }
-                    }
-                }
+                group_compare(w, s_nodes, s_cnt, gw, st_meets);
                 // the pair ends with its last member walk, when every member
                 // tested has met, or at a node without in-neighbours
-                if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu)) w.busy = false;
+                if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu))
+                    w.busy = false;
+                else if (STITCHED && w.t == (uint32_t)d.ix.seg_len)
+                    w.ph = 1;   // the head made all its moves: enter a pool slot of this node
+            }
+            if (STITCHED) {
+#pragma unroll
+                for (int qq = 0; qq < NS; ++qq) {
+                    GSlot<GW> &w = sl[qq];
+                    if (!(w.busy && w.ph) || go[qq]) continue;
+                    switch (w.ph) {
+                    case 1:   // the end node's id
+                        w.tsig = tv[qq];
+                        w.ph = 2;
+                        break;
+                    case 2: { // its pool: slot picked by draw (v, j, 0, DOM_ENTRY)
+                        const uint4 x = philox4x32_10(s_vid[w.pos >> 24], w.rng.j, 0u, DOM_ENTRY, key);
+                        w.tsig = (uint32_t)(tb[qq] + (int64_t)pick64(x.x, (uint64_t)(te[qq] - tb[qq])));
+                        w.tseg = w.tsig;
+                        w.tm = 0;
+                        w.ph = 3;
+                        break;
+                    }
+                    case 3:
+                    case 6:   // a segment's length
+                        w.tsl = tv[qq];
+                        w.tu = 0;
+                        w.ph = 4;
+                        if (w.tsl == 0u) w.busy = false;
+                        break;
+                    case 4: { // one tail step
+                        ++w.t;
+                        ++st_tail;
+                        w.o = tv[qq];
+                        ++w.tu;
+                        group_compare(w, s_nodes, s_cnt, gw, st_meets);
+                        if (w.live == 0u || w.t == ((w.pos >> 16) & 0xffu)) {
+                            w.busy = false;
+                        } else if (w.tu == w.tsl) {
+                            if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width)
+                                w.busy = false;
+                            else
+                                w.ph = 5;
+                        }
+                        break;
+                    }
+                    default:  // the chain's next segment
+                        ++w.tm;
+                        w.tseg = tv[qq];
+                        if (w.tseg == NIL) w.busy = false;
+                        else w.ph = 6;
+                        break;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -420,34 +503,49 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         }
     }
 
-    unsigned long long v0 = st_moves, v1 = st_draws, v2 = st_meets, v4 = st_pairs;
+    unsigned long long v0 = st_moves, v1 = st_draws, v2 = st_meets, v3 = st_tail, v4 = st_pairs;
     for (int dd = 32; dd > 0; dd >>= 1) {
         v0 += __shfl_xor(v0, dd, 64);
         v1 += __shfl_xor(v1, dd, 64);
         v2 += __shfl_xor(v2, dd, 64);
+        v3 += __shfl_xor(v3, dd, 64);
         v4 += __shfl_xor(v4, dd, 64);
     }
     if (lane == 0) {
         atomicAdd(&counters[C_MOVES], v0);
         atomicAdd(&counters[C_DRAWS], v1);
         atomicAdd(&counters[C_MEETS], v2);
+        atomicAdd(&counters[C_TAIL], v3);
         atomicAdd(&counters[C_PAIRS], v4);
     }
 }
 
-template <int GW>
+#ifndef SRK_GROUP_SLOTS_STITCHED
+#define SRK_GROUP_SLOTS_STITCHED 2
+#endif
+
+template <int NS, int GW, bool STITCHED>
 int group_grid_blocks() {
     static const int blocks = [] {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<SRK_GROUP_SLOTS, GW>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<NS, GW, STITCHED>,
                                                            GROUP_BLOCK, 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
         return cus * per;
     }();
     return blocks;
+}
+
+template <int NS, int GW, bool STITCHED>
+void launch_group_list(const GroupSet &gs, int list, unsigned long long *counters, hipStream_t st) {
+    if (gs.units_bound[list] <= 0) return;
+    const int blocks = (int)std::min<int64_t>(gs.units_bound[list], group_grid_blocks<NS, GW, STITCHED>());
+    k_meet_group<NS, GW, STITCHED><<<blocks, GROUP_BLOCK, 0, st>>>(
+        gs.desc, gs.ng, gs.units + (size_t)list * (gs.ng + 1), gs.units + 4 * ((size_t)gs.ng + 1) + list,
+        counters);
 }
 
 }  // namespace
@@ -458,21 +556,59 @@ int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
     return (int32_t)(2 + Rmax / group_tile_j(GW) + sum_RL / NW);
 }
 
+void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
+    const QueryDesc &d0 = *members[0];
+    *gd = GroupDesc{};
+    gd->nodes = d0.nodes;
+    gd->E = d0.E;
+    gd->active = d0.active;
+    gd->n_active = d0.n_active;
+    gd->vb = d0.vb;
+    gd->n_chunks = d0.n_chunks;
+    gd->G = G;
+    gd->gw = (G + 3) / 4;
+    gd->stitched = d0.kind == K_GROUPED_STITCHED;
+    gd->ix = d0.ix;
+    gd->L = d0.L;
+    gd->k0 = d0.k0;
+    gd->k1 = d0.k1;
+    gd->T = d0.T;
+    for (int32_t q = 0; q < G; ++q) {
+        const QueryDesc &dq = *members[q];
+        gd->s[q] = dq.s;
+        gd->R[q] = dq.R;
+        gd->sw[q] = dq.sw;
+        gd->slen[q] = dq.slen;
+        gd->cnt[q] = dq.cnt;
+        gd->Rmax = std::max(gd->Rmax, dq.R);
+    }
+}
+
+size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base) {
+    size_t at = 0;
+    auto take = [&](size_t b) {
+        char *r = base ? base + at : nullptr;
+        at += (b + 255) & ~(size_t)255;
+        return r;
+    };
+    const int32_t mt = group_max_tiles(gd->Rmax, sum_RL, gd->L, gd->G);
+    gd->jj = (uint32_t *)take(4 * (size_t)gd->Rmax);
+    gd->joff = (uint32_t *)take(4 * ((size_t)gd->Rmax + 1));
+    gd->glen = (uint32_t *)take(4 * (size_t)gd->Rmax * (size_t)gd->gw);
+    gd->pos = (uint32_t *)take(4 * (size_t)sum_RL);
+    gd->tiles = (uint32_t *)take(4 * ((size_t)mt + 1));
+    gd->meta = (uint32_t *)take(32);
+    return at;
+}
+
 int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st) {
     if (gs.ng <= 0) return SIMRANK_OK;
     k_group_compact<<<gs.ng, 1024, 0, st>>>(gs.desc);
     k_group_units<<<1, 1024, 0, st>>>(gs.desc, gs.ng, gs.units);
-    uint32_t *cursors = gs.units + 2 * (gs.ng + 1);
-    if (gs.units_bound[0] > 0) {
-        const int blocks = (int)std::min<int64_t>(gs.units_bound[0], group_grid_blocks<2>());
-        k_meet_group<SRK_GROUP_SLOTS, 2><<<blocks, GROUP_BLOCK, 0, st>>>(gs.desc, gs.ng, gs.units,
-                                                                         cursors, counters);
-    }
-    if (gs.units_bound[1] > 0) {
-        const int blocks = (int)std::min<int64_t>(gs.units_bound[1], group_grid_blocks<8>());
-        k_meet_group<SRK_GROUP_SLOTS, 8><<<blocks, GROUP_BLOCK, 0, st>>>(
-            gs.desc, gs.ng, gs.units + (gs.ng + 1), cursors + 1, counters);
-    }
+    launch_group_list<SRK_GROUP_SLOTS, 2, false>(gs, 0, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS, 8, false>(gs, 1, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 2, true>(gs, 2, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 8, true>(gs, 3, counters, st);
     SRK_HIP(hipGetLastError());
     return SIMRANK_OK;
 }

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
             }
             d.scls[j] = (uint8_t)cls;
         } else {
-            const bool stitched = d.kind == K_STITCHED;
+            const bool stitched = d.kind == K_STITCHED || d.kind == K_GROUPED_STITCHED;
             const int32_t head = stitched ? min(d.ix.seg_len, d.L) : d.L;
             for (int32_t t = 1; t <= head; ++t) {
                 const uint4 x = philox4x32_10((uint32_t)d.s, (uint32_t)j, (uint32_t)t, DOM_WALK, key);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
 // walks and at most NW - 1 + L <= TN positions.
 __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.x];
-    if (d.kind == K_GROUPED) return;   // compacted with its group
+    if (d.kind >= K_GROUPED) return;   // compacted with its group
     const int32_t R = d.R, L = d.L;
     const uint32_t TJ = (uint32_t)tile_j_of(d.kind);
     const uint32_t NW = (uint32_t)(tile_nodes_of(d.kind) - L);

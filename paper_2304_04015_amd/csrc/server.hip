@@ -7,7 +7,13 @@
 // enqueued whole on its slot's stream (query kernels, then the copy of its
 // results to the slot's pinned buffers, then an event), so requests that arrive
 // while others run are started as soon as a slot is free and their kernels
-// overlap on the device.  Each result equals the lone query's.
+// overlap on the device.  With group_max >= 2, plain or stitched requests that
+// share (mode, seed, c, cap) and are waiting together are admitted as one
+// query group (group.hip) into as many slots: one launch on the first slot's
+// stream walks each (v, j) once for all of them.  While a group runs, the
+// requests that arrive wait and form the next group.  Each result equals the
+// lone query's.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -41,6 +47,8 @@ struct Request {
 };
 
 struct Slot {
+    bool grouped = false;           // its request runs in the server's group
+    int32_t group_size = 1;
     Workspace ws;
     double *out_dev = nullptr;
     uint32_t *cnt_dev = nullptr;
@@ -50,6 +58,26 @@ struct Slot {
     hipEvent_t done = nullptr;
     Request *req = nullptr;
 };
+
+// The one group in flight: descriptors of its members and of the group
+// (pinned staging copies and device arrays), the unit tables and counters of
+// its launch, and the group's compaction buffers, sized for group_max members
+// of (max_R, max_L).
+struct GroupRun {
+    QueryDesc *desc_host = nullptr, *desc_dev = nullptr;
+    GroupDesc *gdesc_host = nullptr, *gdesc_dev = nullptr;
+    uint32_t *units = nullptr, *gunits = nullptr;
+    unsigned long long *counters = nullptr;
+    char *buffers = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the group's kernels
+    bool busy = false;
+    int32_t lead = -1;                         // slot whose stream runs it
+};
+
+// Requests of one group share the walks from every node.
+bool same_walks(const Request *a, const Request *b) {
+    return a->mode == b->mode && a->q.seed == b->q.seed && a->p.T == b->p.T && a->p.L == b->p.L;
+}
 
 }  // namespace
 }  // namespace srk
@@ -69,7 +97,78 @@ struct simrank_server {
     bool stop = false;
     std::thread worker;
     uint64_t n_done = 0, n_failed = 0, max_inflight = 0;
+    GroupRun grp;
+    uint64_t n_groups = 0, n_grouped = 0;
 };
+
+// Attaches a slot's workspace and result buffers to a descriptor.
+static void slot_buffers(Slot &sl, QueryDesc *d) {
+    d->sw = sl.ws.sw;
+    d->slen = sl.ws.slen;
+    d->jj = sl.ws.jj;
+    d->joff = sl.ws.joff;
+    d->swc = sl.ws.swc;
+    d->tiles = sl.ws.tiles;
+    d->meta = sl.ws.meta;
+    d->cnt = sl.cnt_dev;
+    d->out = sl.out_dev;
+}
+
+// Enqueues the group of requests rs (2..group_max, equal walks) into the free
+// slots idx on the first slot's stream: descriptors, the query set with its
+// group, result copies, each slot's completion event.
+static int launch_group(simrank_server *S, const std::vector<Request *> &rs,
+                        const std::vector<int32_t> &idx) {
+    GroupRun &gr = S->grp;
+    const Graph *g = S->g;
+    const int32_t G = (int32_t)rs.size();
+    hipStream_t st = S->slots[idx[0]].stream;
+    const int32_t vb = default_unit_nodes(g);
+    std::vector<const QueryDesc *> mem(G);
+    int64_t sum_RL = 0;
+    for (int32_t i = 0; i < G; ++i) {
+        QueryDesc &d = gr.desc_host[i];
+        describe_query(g, &rs[i]->q, rs[i]->p, rs[i]->mode, vb, &d);
+        slot_buffers(S->slots[idx[i]], &d);
+        d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED : K_GROUPED;
+        mem[i] = &d;
+        sum_RL += (int64_t)d.R * d.L;
+    }
+    GroupDesc *gd = gr.gdesc_host;
+    describe_group(mem.data(), G, gd);
+    (void)group_buffers(gd, sum_RL, gr.buffers);
+    const int64_t units = (int64_t)group_max_tiles(gd->Rmax, sum_RL, gd->L, G) * gd->n_chunks;
+    if (units >= (int64_t)0x7fffffff) return fail(SIMRANK_EINVAL, "group has too many work units");
+    GroupSet gs;
+    gs.desc = gr.gdesc_dev;
+    gs.ng = 1;
+    gs.units_bound[group_list(G, gd->stitched)] = units;
+    gs.units = gr.gunits;
+    QuerySet qs;
+    qs.desc = gr.desc_dev;
+    qs.nq = G;
+    qs.max_R = gd->Rmax;
+    qs.max_n = g->n;
+    qs.units = gr.units;
+    qs.counters = gr.counters;
+    qs.groups = &gs;
+    SRK_HIP(hipMemcpyAsync(gr.desc_dev, gr.desc_host, sizeof(QueryDesc) * G, hipMemcpyHostToDevice, st));
+    SRK_HIP(hipMemcpyAsync(gr.gdesc_dev, gr.gdesc_host, sizeof(GroupDesc), hipMemcpyHostToDevice, st));
+    SRK_HIP(hipEventRecord(gr.ev0, st));
+    int rc = launch_query_set(qs, st, nullptr, nullptr);
+    if (rc) return rc;
+    SRK_HIP(hipEventRecord(gr.ev1, st));
+    const size_t n = (size_t)g->n;
+    for (int32_t i = 0; i < G; ++i) {
+        Slot &sl = S->slots[idx[i]];
+        SRK_HIP(hipMemcpyAsync(sl.out_host, sl.out_dev, 8 * n, hipMemcpyDeviceToHost, st));
+        SRK_HIP(hipMemcpyAsync(sl.cnt_host, sl.cnt_dev, 4 * n, hipMemcpyDeviceToHost, st));
+        SRK_HIP(hipEventRecord(sl.done, st));
+    }
+    gr.busy = true;
+    gr.lead = idx[0];
+    return SIMRANK_OK;
+}
 
 static void server_loop(simrank_server *S) {
     (void)hipSetDevice(S->g->device);
@@ -91,11 +190,21 @@ static void server_loop(simrank_server *S) {
                 const size_t n = (size_t)S->g->n;
                 r->out.assign(sl.out_host, sl.out_host + n);
                 r->cnt.assign(sl.cnt_host, sl.cnt_host + n);
+                // a grouped request reports its share (1/G) of its group's work
+                // and the group's device time
                 unsigned long long c[8];
-                hipError_t e2 = hipMemcpy(c, sl.ws.counters, sizeof(c), hipMemcpyDeviceToHost);
+                hipError_t e2 = hipMemcpy(c, sl.grouped ? S->grp.counters : sl.ws.counters, sizeof(c),
+                                          hipMemcpyDeviceToHost);
+                if (sl.grouped)
+                    for (unsigned long long &x : c) x /= (unsigned long long)sl.group_size;
                 float ms = 0.f, mms = 0.f;
-                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, sl.ws.ev0, sl.ws.ev1);
-                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&mms, sl.ws.evm0, sl.ws.evm1);
+                if (sl.grouped) {
+                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, S->grp.ev0, S->grp.ev1);
+                    mms = ms;
+                } else {
+                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, sl.ws.ev0, sl.ws.ev1);
+                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&mms, sl.ws.evm0, sl.ws.evm1);
+                }
                 r->st.pairs = (uint64_t)(S->g->n - 1) * (uint64_t)r->p.R;
                 r->st.pairs_walked = c[C_PAIRS];
                 r->st.moves = c[C_MOVES];
@@ -118,13 +227,69 @@ static void server_loop(simrank_server *S) {
                 ++S->n_failed;
             }
             sl.req = nullptr;
+            sl.grouped = false;
             progressed = true;
         }
+        // the group is done once none of its slots holds a request
+        if (S->grp.busy) {
+            bool running = false;
+            for (Slot &sl : S->slots) running |= sl.grouped;
+            if (!running) S->grp.busy = false;
+        }
         if (progressed) S->cv_done.notify_all();
-        // admissions
+        // Group admission (group_max >= 2): one launch in flight at a time.
+        // Once the device is free, the requests waiting with the same walks as
+        // the first one (up to group_max and the free slots) start as one
+        // group; a request with no partner starts alone.
+        const int32_t gmax = std::min<int32_t>(S->prm.group_max, GROUP_MAX);
+        if (gmax >= 2 && !S->queue.empty() && inflight == 0) {
+            std::vector<int32_t> idx;
+            for (int32_t i = 0; i < (int32_t)S->slots.size(); ++i)
+                if (!S->slots[i].req) idx.push_back(i);
+            std::vector<Request *> rs;
+            Request *head = S->queue.front();
+            for (Request *r : S->queue)
+                if ((int32_t)rs.size() < std::min<int32_t>(gmax, (int32_t)idx.size()) &&
+                    same_walks(head, r))
+                    rs.push_back(r);
+            if (rs.size() >= 2) {
+                idx.resize(rs.size());
+                const double t = now_s();
+                int rc = launch_group(S, rs, idx);
+                for (size_t i = 0; i < rs.size(); ++i) {
+                    Request *r = rs[i];
+                    S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+                    r->t_start = t;
+                    if (rc) {
+                        r->state = 3;
+                        r->rc = rc;
+                        r->err = simrank_last_error();
+                        r->t_done = now_s();
+                        ++S->n_failed;
+                    } else {
+                        r->state = 1;
+                        S->slots[idx[i]].req = r;
+                        S->slots[idx[i]].grouped = true;
+                        S->slots[idx[i]].group_size = (int32_t)rs.size();
+                        ++inflight;
+                    }
+                }
+                if (rc) {
+                    S->grp.busy = false;
+                    S->cv_done.notify_all();
+                } else {
+                    ++S->n_groups;
+                    S->n_grouped += rs.size();
+                }
+                progressed = true;
+            }
+        }
+        // admissions one at a time (with groups: one request alone, and only
+        // when nothing runs)
         for (Slot &sl : S->slots) {
             if (S->queue.empty()) break;
             if (sl.req) continue;
+            if (gmax >= 2 && inflight > 0) break;
             Request *r = S->queue.front();
             S->queue.pop_front();
             r->t_start = now_s();
@@ -163,6 +328,18 @@ static void server_loop(simrank_server *S) {
 }
 
 static void server_release(simrank_server *S) {
+    GroupRun &gr = S->grp;
+    if (gr.lead >= 0 && S->slots[gr.lead].stream) (void)hipStreamSynchronize(S->slots[gr.lead].stream);
+    if (gr.desc_host) (void)hipHostFree(gr.desc_host);
+    if (gr.gdesc_host) (void)hipHostFree(gr.gdesc_host);
+    device_free(gr.desc_dev);
+    device_free(gr.gdesc_dev);
+    device_free(gr.units);
+    device_free(gr.gunits);
+    device_free(gr.counters);
+    device_free(gr.buffers);
+    if (gr.ev0) (void)hipEventDestroy(gr.ev0);
+    if (gr.ev1) (void)hipEventDestroy(gr.ev1);
     for (Slot &sl : S->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         workspace_release(&sl.ws);
@@ -185,6 +362,8 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
     if (p->max_slots < 1 || p->max_slots > 64) return fail(SIMRANK_EINVAL, "max_slots must lie in [1, 64]");
     if (p->max_R < 1 || p->max_R > MAX_R) return fail(SIMRANK_EINVAL, "max_R must lie in [1, 2^24]");
     if (p->max_L < 1 || p->max_L > MAX_CAP) return fail(SIMRANK_EINVAL, "max_L must lie in [1, 255]");
+    if (p->group_max < 0 || p->group_max > GROUP_MAX)
+        return fail(SIMRANK_EINVAL, "group_max must lie in [0, 32]");
     SRK_HIP(hipSetDevice(g->device));
     simrank_server *S = new simrank_server();
     S->g = g;
@@ -217,6 +396,29 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
         if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
         if (rc) break;
     }
+    const int32_t gmax = std::min<int32_t>(p->group_max, nslots);
+    if (!rc && gmax >= 2) {   // the group's own buffers
+        GroupRun &gr = S->grp;
+        GroupDesc gd{};
+        gd.Rmax = p->max_R;
+        gd.L = p->max_L;
+        gd.G = gmax;
+        gd.gw = (gmax + 3) / 4;
+        const int64_t sum_RL = (int64_t)gmax * p->max_R * p->max_L;
+        const size_t gb = group_buffers(&gd, sum_RL, nullptr);
+        rc = device_alloc((void **)&gr.buffers, gb, nullptr);
+        if (!rc) rc = device_alloc((void **)&gr.desc_dev, sizeof(QueryDesc) * gmax, nullptr);
+        if (!rc) rc = device_alloc((void **)&gr.gdesc_dev, sizeof(GroupDesc), nullptr);
+        if (!rc) rc = device_alloc((void **)&gr.units, 4 * units_words(gmax), nullptr);
+        if (!rc) rc = device_alloc((void **)&gr.gunits, 4 * group_units_words(1), nullptr);
+        if (!rc) rc = device_alloc((void **)&gr.counters, 8 * 8, nullptr);
+        hipError_t e = hipSuccess;
+        if (!rc) e = hipHostMalloc((void **)&gr.desc_host, sizeof(QueryDesc) * gmax, hipHostMallocDefault);
+        if (!rc && e == hipSuccess) e = hipHostMalloc((void **)&gr.gdesc_host, sizeof(GroupDesc), hipHostMallocDefault);
+        if (!rc && e == hipSuccess) e = hipEventCreate(&gr.ev0);
+        if (!rc && e == hipSuccess) e = hipEventCreate(&gr.ev1);
+        if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+    }
     if (rc) {
         server_release(S);
         return rc;
@@ -231,6 +433,18 @@ extern "C" int simrank_server_info(const simrank_server *S, int32_t *slots, int6
     if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
     if (slots) *slots = (int32_t)S->slots.size();
     if (slot_bytes) *slot_bytes = S->slot_bytes;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_server_counts(simrank_server *S, uint64_t *done, uint64_t *failed,
+                                     uint64_t *groups, uint64_t *grouped) {
+    clear_error();
+    if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (done) *done = S->n_done;
+    if (failed) *failed = S->n_failed;
+    if (groups) *groups = S->n_groups;
+    if (grouped) *grouped = S->n_grouped;
     return SIMRANK_OK;
 }
 

@@ -67,7 +67,7 @@ class simrank_index_params(C.Structure):
 
 class simrank_server_params(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("max_R", C.c_int32), ("max_L", C.c_int32),
-                ("reserved", C.c_int32), ("hbm_budget", C.c_int64)]
+                ("group_max", C.c_int32), ("hbm_budget", C.c_int64)]
 
 
 class simrank_request_info(C.Structure):
@@ -143,6 +143,7 @@ def lib() -> C.CDLL:
         "simrank_tune": [vp, P(simrank_query), P(i32)],
         "simrank_server_create": [vp, P(simrank_server_params), P(vp)],
         "simrank_server_info": [vp, P(i32), P(i64)],
+        "simrank_server_counts": [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)],
         "simrank_server_submit": [vp, P(simrank_query), P(C.c_uint64)],
         "simrank_server_wait": [vp, C.c_uint64, dbl, vp, vp, P(simrank_request_info)],
         "simrank_server_destroy": [vp],
@@ -510,9 +511,11 @@ class Server:
     """simrank_server_*: continuous admission of single-source requests."""
 
     def __init__(self, g: Graph, max_slots: int = 4, max_R: int = 9502, max_L: int = 64,
-                 hbm_budget: int = 0):
-        p = simrank_server_params(max_slots=max_slots, max_R=max_R, max_L=max_L, reserved=0,
-                                  hbm_budget=hbm_budget)
+                 hbm_budget: int = 0, group_max: int = 0):
+        """group_max >= 2: waiting requests with equal walks (mode, seed, c, cap)
+        are admitted together as one query group."""
+        p = simrank_server_params(max_slots=max_slots, max_R=max_R, max_L=max_L,
+                                  group_max=group_max, hbm_budget=hbm_budget)
         h = C.c_void_p()
         _check(lib().simrank_server_create(g.handle, C.byref(p), C.byref(h)))
         self.handle = h
@@ -522,6 +525,12 @@ class Server:
         s, b = C.c_int32(), C.c_int64()
         _check(lib().simrank_server_info(self.handle, C.byref(s), C.byref(b)))
         return dict(slots=s.value, slot_bytes=b.value)
+
+    def counts(self) -> dict:
+        """Requests done and failed, query groups launched and the requests they held."""
+        v = [C.c_uint64() for _ in range(4)]
+        _check(lib().simrank_server_counts(self.handle, *[C.byref(x) for x in v]))
+        return dict(zip(("done", "failed", "groups", "grouped"), (x.value for x in v)))
 
     def submit(self, q: simrank_query) -> int:
         t = C.c_uint64()

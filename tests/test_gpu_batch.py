@@ -148,8 +148,9 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
     repeated source, a source without in-edges), 3 on another, 2 with another
     cap, 2 on the star graph, 40 on the small graph with another seed (two
     groups of 20); stitched and stratified queries with the same seed and lone
-    plain queries stay out of the groups.  Every result equals the lone
-    query's and the ungrouped plan's, bit for bit."""
+    plain queries stay out of the groups; stitched queries form groups of their
+    own (3 and 12 members).  Every result equals the lone query's and the
+    ungrouped plan's, bit for bit."""
     gs, Gs = graphs
     g2 = gs[2]
     act = np.nonzero(g2.in_degree() > 0)[0]
@@ -167,14 +168,22 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
     qs += [S.make_query(int(s), c=0.6, seed=S2, walk_cap=64, R=int(R), graph=0)
            for s, R in zip(rng.choice(act0, 40), rng.integers(200, 3000, 40))]
     qs += [S.make_query(srcs[3], c=0.5, seed=S1, walk_cap=64, R=3000, graph=2)]   # lone: other c
-    qs += [S.make_query(int(np.nonzero(gs[1].in_degree() > 0)[0][3]), c=0.6, seed=S1,
-                        walk_cap=64, R=3000, graph=1, mode=S.MODE_STITCHED)]
+    act1 = np.nonzero(gs[1].in_degree() > 0)[0]
+    qs += [S.make_query(int(act1[3]), c=0.6, seed=S1, walk_cap=64, R=3000, graph=1,
+                        mode=S.MODE_STITCHED)]                                 # lone stitched
+    qs += [S.make_query(int(s), c=0.6, seed=S2, walk_cap=64, R=int(R), graph=1,
+                        mode=S.MODE_STITCHED)                                  # stitched, 3 and 12
+           for s, R in zip(rng.choice(act1, 3), (1800, 2500, 900))]
+    qs += [S.make_query(int(s), c=0.6, seed=S1 + 7, walk_cap=64, R=int(R), graph=1,
+                        mode=S.MODE_STITCHED)
+           for s, R in zip(rng.choice(act1, 12), rng.integers(300, 3000, 12))]
+    qs += [S.make_query(int(act1[5]), c=0.6, seed=S2, walk_cap=64, R=1000, graph=1)]   # plain
     qs += [S.make_stratified_query(srcs[4], c=0.6, eps=0.2, seed=S1, z=700, phi=12, graph=2)]
     order = rng.permutation(len(qs))
     qs = [qs[i] for i in order]
     _say(f"shared-seed batch: {len(qs)} queries")
     plan = S.BatchPlan(Gs, qs)
-    assert plan.n_groups == 6
+    assert plan.n_groups == 8
     plan.run()
     st_g = plan.wait()
     flat = S.BatchPlan(Gs, qs, groups=False)
@@ -197,20 +206,28 @@ def test_shared_seed_groups_equal_lone_queries(graphs):
         i = next(k for k, q in enumerate(qs) if q.graph == 0 and q.seed == seed)
         want = O.meet_counts_plain(gs[0], qs[i].s, seed, 0.6, 64, qs[i].R_override)
         assert np.array_equal(plan.read(i)[1], want), seed
+    P = O.pool_sizes(gs[1], 1.0)
+    i = next(k for k, q in enumerate(qs) if q.mode == S.MODE_STITCHED and q.seed == S1 + 7)
+    want = O.meet_counts_stitched(gs[1], qs[i].s, S1 + 7, ISEED, 0.6, 64, 8, P, qs[i].R_override)
+    assert np.array_equal(plan.read(i)[1], want)
     plan.free()
     flat.free()
 
 
-@pytest.mark.parametrize("nq", [8, 21])
-def test_shared_seed_group_full_size(nq):
+@pytest.mark.parametrize("nq,mode", [(8, S.MODE_PLAIN), (21, S.MODE_PLAIN),
+                                     (6, S.MODE_STITCHED), (21, S.MODE_STITCHED)])
+def test_shared_seed_group_full_size(nq, mode):
     """Queries with the medium workload's shape (2^16-node R-MAT graph, eps
-    0.02, R = 9,502, cap 64) and one seed, as one group of 8 and one of 21:
-    the group's counts equal the lone queries', bit for bit."""
+    0.02, R = 9,502, cap 64) and one seed, plain and stitched (index with
+    k = 3, kappa = 1), as one group of up to 8 and one of 21: the group's
+    counts equal the lone queries', bit for bit."""
     g = inputs.rmat_in(16, 16 << 16, seed=72)
     G = S.load_csr(g)
+    if mode == S.MODE_STITCHED:
+        S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=0.6, seed=ISEED)
     srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, 74)]
-    qs = [S.make_query(s, c=0.6, eps=0.02, delta=1e-3, seed=0x2304040150000053, walk_cap=64)
-          for s in srcs]
+    qs = [S.make_query(s, c=0.6, eps=0.02, delta=1e-3, seed=0x2304040150000053, walk_cap=64,
+                       mode=mode) for s in srcs]
     assert S.simrank_derive_params(qs[0], g.n).R == 9502
     plan = S.BatchPlan([G], qs)
     assert plan.n_groups == 1

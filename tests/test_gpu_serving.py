@@ -81,3 +81,38 @@ def test_rejects(served):
     with pytest.raises(S.SimRankError):
         srv.wait(123456)
     srv.destroy()
+
+
+def test_grouped_admission_equals_lone(served):
+    """group_max = 8 with 8 slots: requests with one seed (plain, and stitched)
+    that wait together are admitted as query groups; requests with other seeds
+    and a lone stitched request run alone between them.  Every result equals
+    the lone query's, bit for bit."""
+    g, G = served
+    rng = np.random.default_rng(3)
+    deg = g.in_degree().astype(np.float64)
+    qs = []
+    for i in range(40):
+        s = int(rng.choice(g.n, p=deg / deg.sum()))
+        eps = float(rng.choice([0.05, 0.02]))
+        if i % 10 == 9:
+            q = S.make_query(s, c=0.6, eps=eps, delta=1e-3, seed=0x5E99 + i)          # own seed
+        elif i % 4 == 1:
+            q = S.make_query(s, c=0.6, eps=eps, delta=1e-3, seed=0x5E77, mode=S.MODE_STITCHED)
+        else:
+            q = S.make_query(s, c=0.6, eps=eps, delta=1e-3, seed=0x5E77)
+        qs.append(q)
+    lone = [S.simrank_single_source_ex(G, q) for q in qs]
+    srv = S.Server(G, max_slots=8, max_R=9502, max_L=64, group_max=8)
+    tickets = [srv.submit(q) for q in qs]          # all arrive while the first ones run
+    for i, (t, (o1, c1, _)) in enumerate(zip(tickets, lone)):
+        o, c, info = srv.wait(t)
+        assert np.array_equal(c, c1), i
+        assert np.array_equal(o, o1), i
+        assert info.latency_s >= info.queue_s >= 0.0
+    k = srv.counts()
+    assert k["done"] == len(qs) and k["failed"] == 0
+    assert k["groups"] >= 2 and k["grouped"] >= 2 * k["groups"]
+    srv.destroy()
+    with pytest.raises(S.SimRankError):
+        S.Server(G, max_slots=2, group_max=33)
