@@ -429,69 +429,70 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                     }
                 }
             }
+            // ---- one compare per slot that reached a new position (a head
+            // step's node, or a stitched tail step read from the index), then
+            // the end tests of its phase; the other tail phases only advance
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
-                if (!go[qq]) continue;
-                ++st_moves;
                 GSlot<GW> &w = sl[qq];
-                w.o = e[qq].x;
-                w.d = e[qq].y;
-                group_compare(w, s_nodes, s_cnt, gw, st_meets);
-                // the pair ends with its last member walk, when every member
-                // tested has met, or at a node without in-neighbours
-                if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu))
-                    w.busy = false;
-                else if (STITCHED && w.t == (uint32_t)d.ix.seg_len)
-                    w.ph = 1;   // the head made all its moves: enter a pool slot of this node
-            }
-            if (STITCHED) {
-#pragma unroll
-                for (int qq = 0; qq < NS; ++qq) {
-                    GSlot<GW> &w = sl[qq];
-                    if (!(w.busy && w.ph) || go[qq]) continue;
-                    switch (w.ph) {
-                    case 1:   // the end node's id
-                        w.tsig = tv[qq];
-                        w.ph = 2;
-                        break;
-                    case 2: { // its pool: slot picked by draw (v, j, 0, DOM_ENTRY)
-                        const uint4 x = philox4x32_10(s_vid[w.pos >> 24], w.rng.j, 0u, DOM_ENTRY, key);
-                        w.tsig = (uint32_t)(tb[qq] + (int64_t)pick64(x.x, (uint64_t)(te[qq] - tb[qq])));
-                        w.tseg = w.tsig;
-                        w.tm = 0;
-                        w.ph = 3;
-                        break;
-                    }
-                    case 3:
-                    case 6:   // a segment's length
-                        w.tsl = tv[qq];
-                        w.tu = 0;
-                        w.ph = 4;
-                        if (w.tsl == 0u) w.busy = false;
-                        break;
-                    case 4: { // one tail step
-                        ++w.t;
-                        ++st_tail;
-                        w.o = tv[qq];
-                        ++w.tu;
-                        group_compare(w, s_nodes, s_cnt, gw, st_meets);
-                        if (w.live == 0u || w.t == ((w.pos >> 16) & 0xffu)) {
+                const bool tail_step = STITCHED && !go[qq] && w.busy && w.ph == 4u;
+                if (go[qq]) {
+                    ++st_moves;
+                    w.o = e[qq].x;
+                    w.d = e[qq].y;
+                } else if (tail_step) {
+                    ++w.t;
+                    ++st_tail;
+                    w.o = tv[qq];
+                    ++w.tu;
+                }
+                if (go[qq] || tail_step) group_compare(w, s_nodes, s_cnt, gw, st_meets);
+                if (go[qq]) {
+                    // the pair ends with its last member walk, when every
+                    // member tested has met, or at a node without in-neighbours
+                    if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu))
+                        w.busy = false;
+                    else if (STITCHED && w.t == (uint32_t)d.ix.seg_len)
+                        w.ph = 1;   // the head made all its moves: enter a pool slot of this node
+                    continue;
+                }
+                if (!(STITCHED && w.busy && w.ph)) continue;
+                switch (w.ph) {
+                case 1:   // the end node's id
+                    w.tsig = tv[qq];
+                    w.ph = 2;
+                    break;
+                case 2: { // its pool: slot picked by draw (v, j, 0, DOM_ENTRY)
+                    const uint4 x = philox4x32_10(s_vid[w.pos >> 24], w.rng.j, 0u, DOM_ENTRY, key);
+                    w.tsig = (uint32_t)(tb[qq] + (int64_t)pick64(x.x, (uint64_t)(te[qq] - tb[qq])));
+                    w.tseg = w.tsig;
+                    w.tm = 0;
+                    w.ph = 3;
+                    break;
+                }
+                case 3:
+                case 6:   // a segment's length
+                    w.tsl = tv[qq];
+                    w.tu = 0;
+                    w.ph = 4;
+                    if (w.tsl == 0u) w.busy = false;
+                    break;
+                case 4:   // after a tail step
+                    if (w.live == 0u || w.t == ((w.pos >> 16) & 0xffu)) {
+                        w.busy = false;
+                    } else if (w.tu == w.tsl) {
+                        if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width)
                             w.busy = false;
-                        } else if (w.tu == w.tsl) {
-                            if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width)
-                                w.busy = false;
-                            else
-                                w.ph = 5;
-                        }
-                        break;
+                        else
+                            w.ph = 5;
                     }
-                    default:  // the chain's next segment
-                        ++w.tm;
-                        w.tseg = tv[qq];
-                        if (w.tseg == NIL) w.busy = false;
-                        else w.ph = 6;
-                        break;
-                    }
+                    break;
+                default:  // the chain's next segment
+                    ++w.tm;
+                    w.tseg = tv[qq];
+                    if (w.tseg == NIL) w.busy = false;
+                    else w.ph = 6;
+                    break;
                 }
             }
         }
