@@ -726,7 +726,7 @@ def bench_grouped(args):
         "results_equal_ungrouped": same,
         "first_equals_lone_query": lone,
         "roofline": {
-            "bound": "hbm", "kernel": "k_meet_group<2, 8> (whole plan's device time)",
+            "bound": "hbm", "kernel": "k_meet_group<2, 8, false> (whole plan's device time)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_grouped.json")),
