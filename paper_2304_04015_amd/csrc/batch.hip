@@ -167,7 +167,9 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
             const int64_t vb = default_unit_nodes(g);
             const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size()) *
                                ((g->n_active + vb - 1) / vb);
-            if (units + ub >= (int64_t)0x7fffffff) continue;   // these queries run alone
+            // packed positions are addressed in 32 bits
+            if (RL >= (int64_t)0xffff0000) continue;            // these queries run alone
+            if (units + ub >= (int64_t)0x7fffffff) continue;
             units += ub;
             for (int32_t i : m) group_of[i] = (int32_t)kept.size();
             kept.push_back(m);

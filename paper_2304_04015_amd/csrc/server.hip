@@ -98,6 +98,7 @@ struct simrank_server {
     std::thread worker;
     uint64_t n_done = 0, n_failed = 0, max_inflight = 0;
     GroupRun grp;
+    int32_t gmax = 0;          // largest group the server forms (its buffers' size)
     uint64_t n_groups = 0, n_grouped = 0;
 };
 
@@ -241,7 +242,7 @@ static void server_loop(simrank_server *S) {
         // Once the device is free, the requests waiting with the same walks as
         // the first one (up to group_max and the free slots) start as one
         // group; a request with no partner starts alone.
-        const int32_t gmax = std::min<int32_t>(S->prm.group_max, GROUP_MAX);
+        const int32_t gmax = S->gmax;
         if (gmax >= 2 && !S->queue.empty() && inflight == 0) {
             std::vector<int32_t> idx;
             for (int32_t i = 0; i < (int32_t)S->slots.size(); ++i)
@@ -396,7 +397,10 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
         if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
         if (rc) break;
     }
-    const int32_t gmax = std::min<int32_t>(p->group_max, nslots);
+    int32_t gmax = std::min<int32_t>(p->group_max, nslots);
+    // a group's packed positions are addressed in 32 bits
+    while (gmax >= 2 && (int64_t)gmax * p->max_R * p->max_L >= (int64_t)0xffff0000) --gmax;
+    S->gmax = gmax;
     if (!rc && gmax >= 2) {   // the group's own buffers
         GroupRun &gr = S->grp;
         GroupDesc gd{};
