@@ -329,11 +329,41 @@ int simrank_batch_plan_read_stratified(simrank_batch_plan *plan, int32_t i, doub
                                        double *out_n_host, uint64_t *wsum_host);
 int simrank_batch_plan_free(simrank_batch_plan *plan);
 
-/* Measures the meet kernel of query q on g for each work-unit size (nodes per
- * unit 32, 64, 128, 256) and keeps the fastest for later queries on g
- * (*vb_out, may be NULL).  Results never depend on the choice.  Not to be
- * called while other threads query g. */
+/* ---------------------------------------------------------------- tuning */
+
+/* A tuner's choice for a graph. */
+typedef struct simrank_tuning {
+    int32_t unit_nodes;   /* nodes v per meet work unit (walks per block: unit_nodes x tile) */
+    int32_t tile_walks;   /* source walks j per LDS tile */
+    int32_t seg_log2;     /* the index's segment length 2^k (-1: no index) */
+    int32_t reserved;
+    double meet_ms;       /* meet-kernel time of the tuning query at this choice */
+    double build_ms;      /* device time of the index build at this choice */
+} simrank_tuning;
+
+/* Measures the meet kernel of query q (plain or stitched) on g for each tile
+ * of source walks (the kind's largest tile, 8192 for plain walks, halved down
+ * to 2048) and each work-unit size (nodes per unit 32, 64, 128, 256, as long
+ * as the units still number 64 or more) and keeps the fastest pair for later
+ * queries on g, batches and servers included (*out, may be NULL).  Results
+ * never depend on the choice.  Not to be called while other threads query g. */
+int simrank_tune_ex(simrank_graph *g, const simrank_query *q, simrank_tuning *out);
+/* simrank_tune_ex, returning the nodes per unit only (*vb_out, may be NULL). */
 int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out);
+/* Fixes the tuning by hand: unit_nodes in [0, 256] (0: the library's default
+ * by graph size), tile_walks 0 (each kind's largest tile) or in [2048, 8192]
+ * (clamped to each kind's largest tile).  Results never depend on it. */
+int simrank_set_tuning(simrank_graph *g, int32_t unit_nodes, int32_t tile_walks);
+/* Segment-length tuner for the stitched index (Section 4's segments of 2^k
+ * steps joined by pointer doubling): for each seg_log2[i] (count in [1, 7],
+ * each in [0, 6]) builds the index from *base with that k, times stitched
+ * query q's meet kernel (second run) into ms_each[i] (may be NULL), and leaves
+ * the index of the fastest k built (*out, may be NULL).  Stitched walks depend
+ * on k: a query's counts are those of the index it ran with.  EINVAL if q is
+ * not stitched or its c differs from base->c. */
+int simrank_tune_index(simrank_graph *g, const simrank_query *q, const simrank_index_params *base,
+                       const int32_t *seg_log2, int32_t count, simrank_tuning *out,
+                       double *ms_each);
 
 /* --------------------------------------------------------------- serving */
 

@@ -470,7 +470,22 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
 
 // ------------------------------------------------------------------ tuner
 
-extern "C" int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out) {
+// One measurement: the meet kernel's time of q's second run (the first warms
+// the caches) with the graph's current tuning.
+static int time_meet(simrank_graph *g, const simrank_query *q, const simrank_params &p, int mode,
+                     Workspace *ws, uint32_t *cnt, float *ms_out) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+        int rc = enqueue_query(g, q, p, mode, ws, nullptr, cnt, g->stream);
+        if (rc) return rc;
+        SRK_HIP(hipEventSynchronize(ws->ev1));
+        SRK_HIP(hipEventElapsedTime(&ms, ws->evm0, ws->evm1));
+    }
+    *ms_out = ms;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_tune_ex(simrank_graph *g, const simrank_query *q, simrank_tuning *out) {
     clear_error();
     if (!g || !q) return fail(SIMRANK_EINVAL, "NULL argument");
     simrank_params p;
@@ -478,37 +493,122 @@ extern "C" int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *v
     int rc = query_params(q, g->n, &p, &mode);
     if (rc) return rc;
     if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
-    if (mode == SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "the tuner takes plain queries");
+    if (mode == SIMRANK_MODE_STRATIFIED) return fail(SIMRANK_EINVAL, "the tuner takes plain or stitched queries");
+    if (mode == SIMRANK_MODE_STITCHED && (!g->index || g->index->T != p.T))
+        return fail(SIMRANK_ESTATE, "stitched query without a matching index");
+    SRK_HIP(hipSetDevice(g->device));
+    const int kind = mode == SIMRANK_MODE_STITCHED ? K_STITCHED : K_PLAIN;
+    Workspace ws;
+    uint32_t *cnt = nullptr;
+    rc = workspace_init(g, p.R, p.L, &ws);
+    if (!rc) rc = device_alloc((void **)&cnt, 4 * (size_t)g->n, nullptr);
+    const int32_t saved_vb = g->tuned_vb, saved_tj = g->tuned_tile_j[kind];
+    int32_t best_vb = 0, best_tj = 0;
+    float best_ms = 0.f;
+    // walks per tile: the kind's tile and each halving down to MIN_TILE_J;
+    // nodes per unit: 32 .. MEET_VB while the units still fill a GPU
+    for (int32_t tj = tile_j_of(kind); tj >= MIN_TILE_J && !rc; tj /= 2) {
+        for (int32_t vb = 32; vb <= MEET_VB && !rc; vb *= 2) {
+            if (vb > 32 && (g->n_active + vb - 1) / vb < 64) break;
+            g->tuned_vb = vb;
+            g->tuned_tile_j[kind] = tj;
+            float ms = 0.f;
+            rc = time_meet(g, q, p, mode, &ws, cnt, &ms);
+            if (!rc && (best_vb == 0 || ms < best_ms)) {
+                best_vb = vb;
+                best_tj = tj;
+                best_ms = ms;
+            }
+        }
+    }
+    g->tuned_vb = rc ? saved_vb : best_vb;
+    g->tuned_tile_j[kind] = rc ? saved_tj : best_tj;
+    device_free(cnt);
+    workspace_release(&ws);
+    if (!rc && out) {
+        *out = simrank_tuning{};
+        out->unit_nodes = best_vb;
+        out->tile_walks = best_tj;
+        out->seg_log2 = g->index ? g->index->seg_log2 : -1;
+        out->meet_ms = best_ms;
+        out->build_ms = g->index ? g->index->build_ms : 0.0;
+    }
+    return rc;
+}
+
+extern "C" int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out) {
+    simrank_tuning t;
+    const int rc = simrank_tune_ex(g, q, &t);
+    if (!rc && vb_out) *vb_out = t.unit_nodes;
+    return rc;
+}
+
+extern "C" int simrank_set_tuning(simrank_graph *g, int32_t unit_nodes, int32_t tile_walks) {
+    clear_error();
+    if (!g) return fail(SIMRANK_EINVAL, "graph is NULL");
+    if (unit_nodes < 0 || unit_nodes > MEET_VB)
+        return fail(SIMRANK_EINVAL, "unit_nodes must lie in [0, " + std::to_string(MEET_VB) + "]");
+    if (tile_walks != 0 && (tile_walks < MIN_TILE_J || tile_walks > tile_j_of(K_PLAIN)))
+        return fail(SIMRANK_EINVAL, "tile_walks must be 0 or lie in [" + std::to_string(MIN_TILE_J) +
+                                        ", " + std::to_string(tile_j_of(K_PLAIN)) + "]");
+    g->tuned_vb = unit_nodes;
+    for (int k = 0; k < N_KINDS; ++k) g->tuned_tile_j[k] = tile_walks;
+    return SIMRANK_OK;
+}
+
+extern "C" int simrank_tune_index(simrank_graph *g, const simrank_query *q,
+                                  const simrank_index_params *base, const int32_t *seg_log2,
+                                  int32_t count, simrank_tuning *out, double *ms_each) {
+    clear_error();
+    if (!g || !q || !base || !seg_log2) return fail(SIMRANK_EINVAL, "NULL argument");
+    if (count < 1 || count > 7) return fail(SIMRANK_EINVAL, "count must lie in [1, 7]");
+    if (q->mode != SIMRANK_MODE_STITCHED) return fail(SIMRANK_EINVAL, "the index tuner takes a stitched query");
+    for (int32_t i = 0; i < count; ++i)
+        if (seg_log2[i] < 0 || seg_log2[i] > 6) return fail(SIMRANK_EINVAL, "seg_log2 must lie in [0, 6]");
+    simrank_params p;
+    int mode;
+    int rc = query_params(q, g->n, &p, &mode);
+    if (rc) return rc;
+    if (q->s < 0 || q->s >= g->n) return fail(SIMRANK_EINVAL, "source out of range");
+    if (continue_threshold(base->c) != p.T)
+        return fail(SIMRANK_EINVAL, "the query's c differs from the index's c");
     SRK_HIP(hipSetDevice(g->device));
     Workspace ws;
     uint32_t *cnt = nullptr;
     rc = workspace_init(g, p.R, p.L, &ws);
     if (!rc) rc = device_alloc((void **)&cnt, 4 * (size_t)g->n, nullptr);
-    const int32_t saved = g->tuned_vb;
-    int32_t best = 0;
+    int32_t best = -1, built = -1;
     float best_ms = 0.f;
-    for (int32_t vb = 32; vb <= MEET_VB && !rc; vb *= 2) {
-        if (vb > 32 && (g->n_active + vb - 1) / vb < 64) break;   // too few units to fill a GPU
-        g->tuned_vb = vb;
-        float ms_sum = 0.f;
-        for (int rep = 0; rep < 2 && !rc; ++rep) {
-            rc = enqueue_query(g, q, p, mode, &ws, nullptr, cnt, g->stream);
-            if (!rc) {
-                hipError_t e = hipEventSynchronize(ws.ev1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ws.evm0, ws.evm1);
-                if (e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
-                if (rep == 1) ms_sum += ms;   // the first run warms the caches
-            }
-        }
-        if (!rc && (best == 0 || ms_sum < best_ms)) {
-            best = vb;
-            best_ms = ms_sum;
+    for (int32_t i = 0; i < count && !rc; ++i) {
+        simrank_index_params ip = *base;
+        ip.seg_log2 = seg_log2[i];
+        rc = simrank_build_index(g, &ip);
+        if (rc) break;
+        built = seg_log2[i];
+        float ms = 0.f;
+        rc = time_meet(g, q, p, mode, &ws, cnt, &ms);
+        if (rc) break;
+        if (ms_each) ms_each[i] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = seg_log2[i];
+            best_ms = ms;
         }
     }
-    g->tuned_vb = rc ? saved : best;
     device_free(cnt);
     workspace_release(&ws);
-    if (!rc && vb_out) *vb_out = best;
+    if (!rc && built != best) {
+        simrank_index_params ip = *base;
+        ip.seg_log2 = best;
+        rc = simrank_build_index(g, &ip);
+    }
+    if (!rc && out) {
+        *out = simrank_tuning{};
+        out->unit_nodes = default_unit_nodes(g);
+        out->tile_walks = g->tuned_tile_j[K_STITCHED] > 0 ? g->tuned_tile_j[K_STITCHED]
+                                                          : tile_j_of(K_STITCHED);
+        out->seg_log2 = best;
+        out->meet_ms = best_ms;
+        out->build_ms = g->index->build_ms;
+    }
     return rc;
 }

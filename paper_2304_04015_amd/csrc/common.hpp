@@ -74,6 +74,8 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 #define SRK_STRAT_MEET_BLOCK 1024
 #endif
 constexpr int MEET_VB = 256;                // nodes v per work unit, at most
+constexpr int MIN_TILE_J = 2048;            // smallest tile a query may be given (buffers are
+                                            // sized for it: max_tiles_for)
 __host__ __device__ constexpr int tile_j_of(int kind) {
     return kind == K_PLAIN ? SRK_TILE_J : kind == K_STITCHED ? SRK_STITCH_TILE_J : SRK_STRAT_TILE_J;
 }
@@ -108,6 +110,7 @@ struct Graph {
     hipStream_t stream = nullptr; // stream of the synchronous calls
     Index *index = nullptr;
     int32_t tuned_vb = 0;         // nodes per meet work unit chosen by simrank_tune (0: default)
+    int32_t tuned_tile_j[N_KINDS] = {0, 0, 0};   // source walks per LDS tile, per kind (0: default)
     int64_t bytes = 0;
 };
 
@@ -178,6 +181,7 @@ struct QueryDesc {
     int32_t vb;            // nodes per work unit (<= MEET_VB)
     int32_t n_chunks;      // ceil(n_active / vb)
     int32_t kind;          // Kind
+    int32_t tile_j;        // source walks per LDS tile, MIN_TILE_J .. tile_j_of(kind)
     // stratified only (R = N walks per node, L = phi)
     const StratTab *tab;
     uint8_t *scls;         // [R] length class of walk (s, j)

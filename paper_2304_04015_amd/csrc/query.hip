@@ -131,7 +131,7 @@ __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ 
     const QueryDesc &d = qd[blockIdx.x];
     if (d.kind >= K_GROUPED) return;   // compacted with its group
     const int32_t R = d.R, L = d.L;
-    const uint32_t TJ = (uint32_t)tile_j_of(d.kind);
+    const uint32_t TJ = (uint32_t)d.tile_j;
     const uint32_t NW = (uint32_t)(tile_nodes_of(d.kind) - L);
     const int32_t per = (R + blockDim.x - 1) / blockDim.x;
     const int32_t j0 = min(R, (int32_t)threadIdx.x * per), j1 = min(R, j0 + per);
@@ -746,9 +746,11 @@ IndexView index_view(const Graph *g) {
     return v;
 }
 
-// Tiles of R walks of cap L, at most, for any kind (the smallest shape).
+// Tiles of R walks of cap L, at most, for any kind and any tile a query may be
+// given (the smallest shape).
 int32_t max_tiles_for(int32_t R, int32_t L) {
-    const int64_t TJ = std::min({tile_j_of(K_PLAIN), tile_j_of(K_STITCHED), tile_j_of(K_STRAT)});
+    const int64_t TJ =
+        std::min({MIN_TILE_J, tile_j_of(K_PLAIN), tile_j_of(K_STITCHED), tile_j_of(K_STRAT)});
     const int64_t NW =
         std::min({tile_nodes_of(K_PLAIN), tile_nodes_of(K_STITCHED), tile_nodes_of(K_STRAT)}) - L;
     return (int32_t)(2 + R / TJ + ((int64_t)R * L) / NW);
@@ -784,6 +786,8 @@ void describe_query(const Graph *g, const simrank_query *q, const simrank_params
     d->n_chunks = (g->n_active + vb - 1) / vb;
     d->kind = mode == SIMRANK_MODE_STITCHED ? K_STITCHED
               : mode == SIMRANK_MODE_STRATIFIED ? K_STRAT : K_PLAIN;
+    const int32_t tj = g->tuned_tile_j[d->kind];
+    d->tile_j = tj > 0 ? std::min<int32_t>(tj, tile_j_of(d->kind)) : tile_j_of(d->kind);
 }
 
 int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hipEvent_t ev_meet1) {

@@ -70,6 +70,14 @@ class simrank_server_params(C.Structure):
                 ("group_max", C.c_int32), ("hbm_budget", C.c_int64)]
 
 
+class simrank_tuning(C.Structure):
+    _fields_ = [("unit_nodes", C.c_int32), ("tile_walks", C.c_int32), ("seg_log2", C.c_int32),
+                ("reserved", C.c_int32), ("meet_ms", C.c_double), ("build_ms", C.c_double)]
+
+    def asdict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class simrank_request_info(C.Structure):
     _fields_ = [("queue_s", C.c_double), ("latency_s", C.c_double), ("stats", simrank_stats)]
 
@@ -134,6 +142,10 @@ def lib() -> C.CDLL:
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
         "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
         "simrank_batch_plan_create": [P(vp), i32, P(simrank_query), i32, P(vp)],
+        "simrank_tune_ex": [vp, P(simrank_query), P(simrank_tuning)],
+        "simrank_set_tuning": [vp, i32, i32],
+        "simrank_tune_index": [vp, P(simrank_query), P(simrank_index_params), P(i32), i32,
+                               P(simrank_tuning), P(dbl)],
         "simrank_batch_plan_create_ex": [P(vp), i32, P(simrank_query), i32, u32, P(vp), P(i32)],
         "simrank_batch_plan_run": [vp, vp],
         "simrank_batch_plan_wait": [vp, P(simrank_stats)],
@@ -564,6 +576,30 @@ def simrank_tune(g: Graph, q: simrank_query) -> int:
     vb = C.c_int32()
     _check(lib().simrank_tune(g.handle, C.byref(q), C.byref(vb)))
     return vb.value
+
+
+def simrank_tune_ex(g: Graph, q: simrank_query) -> dict:
+    """Nodes per unit and walks per tile chosen for g (kept for later queries)."""
+    t = simrank_tuning()
+    _check(lib().simrank_tune_ex(g.handle, C.byref(q), C.byref(t)))
+    return t.asdict()
+
+
+def simrank_set_tuning(g: Graph, unit_nodes: int = 0, tile_walks: int = 0) -> None:
+    _check(lib().simrank_set_tuning(g.handle, int(unit_nodes), int(tile_walks)))
+
+
+def simrank_tune_index(g: Graph, q: simrank_query, seg_log2=(2, 3, 4), kappa: float = 1.0,
+                       c: float = 0.6, seed: int = 0) -> tuple[dict, list]:
+    """Builds the stitched index with each segment length 2^k, times stitched
+    query q on each and leaves the fastest built: (choice, ms per k)."""
+    ks = (C.c_int32 * len(seg_log2))(*seg_log2)
+    ms = (C.c_double * len(seg_log2))()
+    p = simrank_index_params(seg_log2=int(seg_log2[0]), reserved=0, kappa=kappa, c=c, seed=seed)
+    t = simrank_tuning()
+    _check(lib().simrank_tune_index(g.handle, C.byref(q), C.byref(p), ks, len(seg_log2),
+                                    C.byref(t), ms))
+    return t.asdict(), list(ms)
 
 
 def simrank_version() -> str:

@@ -92,6 +92,9 @@ def test_null_arguments_rejected():
     assert S.lib().simrank_workspace_free(None) == S.SIMRANK_OK
     assert S.lib().simrank_batch(None, 0, None, 0, None, None, None) == S.SIMRANK_OK
     assert S.lib().simrank_last_error() == b""
+    assert S.lib().simrank_set_tuning(None, 0, 0) == S.SIMRANK_EINVAL
+    assert S.lib().simrank_tune_ex(None, None, None) == S.SIMRANK_EINVAL
+    assert S.lib().simrank_tune_index(None, None, None, None, 1, None, None) == S.SIMRANK_EINVAL
 
 
 def test_plan_flags_checked_before_any_device_work():

@@ -237,3 +237,37 @@ def test_shared_seed_group_full_size(nq, mode):
     for i, q in enumerate(qs):
         assert np.array_equal(plan.read(i, want_out=False)[1], S.simrank_single_source_ex(G, q)[1]), i
     plan.free()
+
+
+def test_tile_and_unit_settings_keep_results(graphs):
+    """Walks per tile and nodes per unit, set by hand or by the tuner, change
+    the work's partition only: plain, stitched and stratified counts, alone and
+    in a batch, stay equal to the default tuning's, bit for bit."""
+    gs, Gs = graphs
+    g, G = gs[1], Gs[1]                  # has an index
+    s = int(np.argmax(g.in_degree()))
+    qp = S.make_query(s, c=0.6, seed=91, walk_cap=64, R=9000)
+    qs_ = S.make_query(s, c=0.6, seed=92, walk_cap=64, R=5000, mode=S.MODE_STITCHED)
+    qr = S.make_stratified_query(s, c=0.6, eps=0.1, seed=93, z=3000, phi=12)
+    S.simrank_set_tuning(G, 0, 0)
+    want_p = S.simrank_single_source_ex(G, qp)[1]
+    want_s = S.simrank_single_source_ex(G, qs_)[1]
+    want_r = S.simrank_single_source_stratified(G, qr)[2]
+    for vb, tj in ((32, 2048), (256, 4096), (64, 8192), (128, 6000)):
+        S.simrank_set_tuning(G, vb, tj)
+        assert np.array_equal(S.simrank_single_source_ex(G, qp)[1], want_p), (vb, tj)
+        assert np.array_equal(S.simrank_single_source_ex(G, qs_)[1], want_s), (vb, tj)
+        assert np.array_equal(S.simrank_single_source_stratified(G, qr)[2], want_r), (vb, tj)
+        plan = S.BatchPlan([G], [S.make_query(s, c=0.6, seed=91, walk_cap=64, R=9000, graph=0)])
+        plan.run()
+        plan.wait()
+        assert np.array_equal(plan.read(0, want_out=False)[1], want_p), (vb, tj)
+        plan.free()
+    t = S.simrank_tune_ex(G, qp)
+    _say(f"tuner: {t}")
+    assert t["unit_nodes"] in (32, 64, 128, 256) and t["tile_walks"] in (2048, 4096, 8192)
+    assert np.array_equal(S.simrank_single_source_ex(G, qp)[1], want_p)
+    for bad in ((-1, 0), (257, 0), (0, 1024), (0, 16384)):
+        with pytest.raises(S.SimRankError):
+            S.simrank_set_tuning(G, *bad)
+    S.simrank_set_tuning(G, 0, 0)

@@ -201,3 +201,28 @@ def test_c3_stitching_at_scale():
                                   1 << k, P, R, vs=smp)
     assert np.array_equal(cnt[smp], want)
     _say(f"query: moves={st.moves} tail_steps={st.tail_steps} meet_ms={st.meet_ms:.1f}")
+
+
+def test_index_tuner_picks_a_segment_length(small):
+    """The segment-length tuner builds the index for k = 2, 3, 4, times a
+    stitched query on each and leaves the fastest built; the query's counts on
+    that index equal the oracle's for the chosen k."""
+    g = small
+    G = S.load_csr(g)
+    s = int(np.argsort(g.in_degree())[-2])
+    q = S.make_query(s, c=0.6, seed=SEED, walk_cap=64, R=2000, mode=S.MODE_STITCHED)
+    choice, ms = S.simrank_tune_index(G, q, seg_log2=(2, 3, 4), kappa=1.0, c=0.6, seed=ISEED)
+    _say(f"index tuner: {choice}, meet ms per k {ms}")
+    k = choice["seg_log2"]
+    assert k in (2, 3, 4) and len(ms) == 3 and all(x > 0 for x in ms)
+    assert ms[(2, 3, 4).index(k)] == min(ms)
+    assert S.simrank_index_info(G)["seg_log2"] == k
+    cnt = S.simrank_single_source_ex(G, q)[1]
+    want = O.meet_counts_stitched(g, s, SEED, ISEED, 0.6, 64, 1 << k, O.pool_sizes(g, 1.0), 2000)
+    assert np.array_equal(cnt, want)
+    with pytest.raises(S.SimRankError):   # plain query
+        S.simrank_tune_index(G, S.make_query(s, seed=SEED, R=100), seg_log2=(3,), seed=ISEED)
+    with pytest.raises(S.SimRankError):   # c differs from the index's
+        S.simrank_tune_index(G, q, seg_log2=(3,), c=0.5, seed=ISEED)
+    with pytest.raises(S.SimRankError):
+        S.simrank_tune_index(G, q, seg_log2=(7,), seed=ISEED)
