@@ -11,6 +11,7 @@
 // Each query's result is exactly the one a lone simrank_single_source_ex call
 // returns: results depend only on (graph, query).
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -23,6 +24,11 @@ namespace {
 constexpr size_t ARENA_ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1); }
+
+// A group's walks (GroupDesc::wk) for queries of a mode.
+int32_t walk_kind(int mode) {
+    return mode == SIMRANK_MODE_STITCHED ? 1 : mode == SIMRANK_MODE_STRATIFIED ? 2 : 0;
+}
 
 // Device bytes one query needs in a plan (stratified queries: class table,
 // walk classes, weighted sums and the second estimate instead of counts).
@@ -39,25 +45,34 @@ size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
     return b;
 }
 
-// Groups of plain queries, and of stitched queries, that share (graph, seed,
-// continue threshold, cap):
-// each such set of two or more queries is split into ceil(size / GROUP_MAX)
-// groups of nearly equal size, in query order.
+// Groups of queries of one kind that share (graph, seed, continue threshold,
+// cap; stratified: z, N and phi): each such set of two or more queries is
+// split into ceil(size / max) groups of nearly equal size, in query order (max
+// GROUP_MAX, GROUP_MAX_STRAT for stratified walks).
 std::vector<std::vector<int32_t>> form_groups(simrank_graph *const *graphs, const simrank_query *qs,
                                               int32_t nq, const std::vector<simrank_params> &ps,
                                               const std::vector<int> &modes) {
-    std::map<std::tuple<const Graph *, int, uint64_t, uint32_t, int32_t>, std::vector<int32_t>> by;
-    for (int32_t i = 0; i < nq; ++i)
-        if (modes[i] == SIMRANK_MODE_PLAIN || modes[i] == SIMRANK_MODE_STITCHED)
-            by[std::make_tuple((const Graph *)graphs[qs[i].graph], modes[i], qs[i].seed, ps[i].T,
-                               ps[i].L)]
-                .push_back(i);
+    using Key = std::tuple<const Graph *, int, uint64_t, uint32_t, int32_t, int32_t, uint64_t>;
+    std::map<Key, std::vector<int32_t>> by;
+    for (int32_t i = 0; i < nq; ++i) {
+        const Graph *g = graphs[qs[i].graph];
+        uint64_t zbits = 0;
+        if (modes[i] == SIMRANK_MODE_STRATIFIED) {
+            StratParams sp;
+            if (strat_params(&qs[i], g->n, &sp, nullptr)) continue;
+            std::memcpy(&zbits, &sp.z, sizeof(zbits));
+        }
+        by[Key(g, modes[i], qs[i].seed, ps[i].T, ps[i].L, ps[i].R * (modes[i] == SIMRANK_MODE_STRATIFIED),
+               zbits)]
+            .push_back(i);
+    }
     std::vector<std::vector<int32_t>> out;
     for (auto &kv : by) {
         const std::vector<int32_t> &v = kv.second;
         const int32_t sz = (int32_t)v.size();
         if (sz < 2) continue;
-        const int32_t ngr = (sz + GROUP_MAX - 1) / GROUP_MAX;
+        const int32_t mx = std::get<1>(kv.first) == SIMRANK_MODE_STRATIFIED ? GROUP_MAX_STRAT : GROUP_MAX;
+        const int32_t ngr = (sz + mx - 1) / mx;
         int32_t at = 0;
         for (int32_t k = 0; k < ngr; ++k) {
             const int32_t take = sz / ngr + (k < sz % ngr ? 1 : 0);
@@ -165,7 +180,8 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
             }
             const Graph *g = graphs[qs[m[0]].graph];
             const int64_t vb = default_unit_nodes(g);
-            const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size()) *
+            const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size(),
+                                                        walk_kind(modes[m[0]])) *
                                ((g->n_active + vb - 1) / vb);
             // packed positions are addressed in 32 bits
             if (RL >= (int64_t)0xffff0000) continue;            // these queries run alone
@@ -197,6 +213,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         gd.L = ps[groups[k][0]].L;
         gd.G = (int32_t)groups[k].size();
         gd.gw = (gd.G + 3) / 4;
+        gd.wk = walk_kind(modes[groups[k][0]]);
         total += group_buffers(&gd, g_RL[k], nullptr);
     }
     size_t free_b = 0, tot_b = 0;
@@ -258,7 +275,8 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
         if (group_of[i] >= 0) {
-            d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED : K_GROUPED;   // walked with its group
+            d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED   // walked with its group
+                     : d.kind == K_STRAT  ? K_GROUPED_STRAT : K_GROUPED;
         } else {
             const int64_t ub = (int64_t)max_tiles_for(pp.R, pp.L) * d.n_chunks;
             set.units_bound[d.kind] += ub;
@@ -272,9 +290,9 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         for (int32_t i : m) mem.push_back(&p->desc[i]);
         GroupDesc &gd = p->gdesc[k];
         describe_group(mem.data(), (int32_t)m.size(), &gd);
-        const int32_t mt = group_max_tiles(gd.Rmax, g_RL[k], gd.L, gd.G);
+        const int32_t mt = group_max_tiles(gd.Rmax, g_RL[k], gd.L, gd.G, gd.wk);
         (void)take(group_buffers(&gd, g_RL[k], cur));   // carved at cur, which it advances
-        gset.units_bound[group_list(gd.G, gd.stitched)] += (int64_t)mt * gd.n_chunks;
+        gset.units_bound[group_list(gd.G, gd.wk)] += (int64_t)mt * gd.n_chunks;
     }
     if (ngr > 0) {
         e = hipMemcpy(p->gdesc_dev, p->gdesc.data(), sizeof(GroupDesc) * ngr, hipMemcpyHostToDevice);
@@ -371,7 +389,7 @@ extern "C" int simrank_batch_plan_read(simrank_batch_plan *p, int32_t i, double 
     SRK_HIP(hipSetDevice(p->device));
     SRK_HIP(hipEventSynchronize(p->ev1));
     const size_t n = (size_t)p->graphs[i]->n;
-    if (counts_host && p->desc[i].kind == K_STRAT)
+    if (counts_host && strat_kind(p->desc[i].kind))
         return fail(SIMRANK_EINVAL, "a stratified query has weighted sums, not counts: "
                                     "use simrank_batch_plan_read_stratified");
     if (out_host) SRK_HIP(hipMemcpy(out_host, p->desc[i].out, 8 * n, hipMemcpyDeviceToHost));
@@ -385,7 +403,7 @@ extern "C" int simrank_batch_plan_read_stratified(simrank_batch_plan *p, int32_t
     clear_error();
     if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
     if (i < 0 || i >= p->nq) return fail(SIMRANK_EINVAL, "query index out of range");
-    if (p->desc[i].kind != K_STRAT) return fail(SIMRANK_EINVAL, "not a stratified query");
+    if (!strat_kind(p->desc[i].kind)) return fail(SIMRANK_EINVAL, "not a stratified query");
     if (!p->ran) return fail(SIMRANK_ESTATE, "plan has not run");
     SRK_HIP(hipSetDevice(p->device));
     SRK_HIP(hipEventSynchronize(p->ev1));
@@ -431,9 +449,8 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         while (i1 < nq) {
             const size_t b = query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) +
                              sizeof(QueryDesc) + 64 +
-                             (modes[i1] != SIMRANK_MODE_STRATIFIED   // its share of a group's buffers
-                                  ? 4 * (size_t)ps[i1].R * ps[i1].L + 16 * (size_t)ps[i1].R + 1024
-                                  : 0);
+                             4 * (size_t)ps[i1].R * ps[i1].L + 16 * (size_t)ps[i1].R +
+                             1024;   // its share of a group's buffers
             if (i1 > i0 && used + b > budget) break;
             used += b;
             ++i1;

@@ -207,14 +207,19 @@ struct QuerySet {
 inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1) + N_KINDS; }
 
 // ------------------------------------------------------------ query groups
-// In a batch, plain (or stitched) queries on one graph with the same walk key,
-// continue threshold and cap have the same walk (v, j) from every node v: a
-// group of up to GROUP_MAX such queries follows each walk once and tests it
-// against every member's walk j of its own source (group.hip).  A member keeps
-// its own descriptor (source walks, counts, estimate) with kind K_GROUPED or
-// K_GROUPED_STITCHED, which no per-kind unit list takes.
+// In a batch, queries of one kind on one graph with the same walk key and walk
+// parameters (c and cap; the stratified estimator's z and cap) have the same
+// walk (v, j) from every node v: a group of up to GROUP_MAX such queries (8 for
+// stratified walks) follows each walk once and tests it against every
+// member's walk j of its own source (group.hip).  A member keeps its own
+// descriptor (source walks, counts or weighted sums, estimate) with kind
+// K_GROUPED, K_GROUPED_STITCHED or K_GROUPED_STRAT, which no per-kind unit list
+// takes.
 constexpr int GROUP_MAX = 32;
-constexpr int32_t K_GROUPED = N_KINDS, K_GROUPED_STITCHED = N_KINDS + 1;
+constexpr int32_t K_GROUPED = N_KINDS, K_GROUPED_STITCHED = N_KINDS + 1, K_GROUPED_STRAT = N_KINDS + 2;
+constexpr int GROUP_MAX_STRAT = 8;
+// Kinds whose walks are the stratified estimator's (weighted sums, not counts).
+__host__ __device__ inline bool strat_kind(int32_t kind) { return kind == K_STRAT || kind == K_GROUPED_STRAT; }
 
 struct GroupDesc {
     const uint2 *nodes;
@@ -223,14 +228,19 @@ struct GroupDesc {
     int32_t n_active, vb, n_chunks;
     int32_t G, L, Rmax;
     int32_t gw;                          // words of member lengths per entry: ceil(G / 4)
-    int32_t stitched;                    // members' walks have index tails
+    int32_t wk;                          // walks: 0 plain, 1 stitched (index tails), 2 stratified
     IndexView ix;
+    // stratified: the class table, N = R of every member, the shuffle grid
+    const StratTab *tab;
+    int32_t sa, sb;
     uint32_t k0, k1, T;
     int32_t s[GROUP_MAX];                // members' sources
     int32_t R[GROUP_MAX];
     const uint32_t *sw[GROUP_MAX];       // members' source walks [R][L]
     const uint8_t *slen[GROUP_MAX];      // and their lengths [R]
-    uint32_t *cnt[GROUP_MAX];            // members' meet counts [n]
+    uint32_t *cnt[GROUP_MAX];            // members' meet counts [n] (plain, stitched)
+    unsigned long long *wsum[GROUP_MAX]; // members' weighted sums [n] (stratified)
+    const uint8_t *scls[GROUP_MAX];      // classes of the members' walks [R] (stratified)
     // Compacted walks: entry e is a walk index jj[e] for which at least one
     // member's walk has a step; the members' positions of that walk lie back
     // to back from pos[joff[e]], member q's length in byte q of the entry's
@@ -246,21 +256,24 @@ struct GroupDesc {
 struct GroupSet {
     const GroupDesc *desc = nullptr;     // device [ng]
     int32_t ng = 0;
-    int64_t units_bound[4] = {0, 0, 0, 0};   // work units per kernel instance (group_list)
+    int64_t units_bound[5] = {0, 0, 0, 0, 0};   // work units per kernel instance (group_list)
     uint32_t *units = nullptr;           // device [group_units_words(ng)]
 };
 // Kernel instance of a group: plain walks with up to 8 members (0) or more
-// (1), stitched walks with up to 8 (2) or more (3).
-__host__ __device__ inline int group_list(int32_t G, int32_t stitched) { return (G > 8 ? 1 : 0) + (stitched ? 2 : 0); }
+// (1), stitched walks with up to 8 (2) or more (3), stratified walks (4).
+constexpr int GROUP_LISTS = 5;
+__host__ __device__ inline int group_list(int32_t G, int32_t wk) {
+    return wk == 2 ? 4 : (G > 8 ? 1 : 0) + (wk == 1 ? 2 : 0);
+}
 // Unit offsets of a group set: one list of ng + 1 offsets per instance, then
 // one cursor per list.
-inline size_t group_units_words(int32_t ng) { return 4 * ((size_t)ng + 1) + 4; }
+inline size_t group_units_words(int32_t ng) { return GROUP_LISTS * ((size_t)ng + 1) + GROUP_LISTS; }
 
 // Tiles of a group's compacted walks, at most.
-int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G);
+int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int32_t wk);
 // Fills a group's descriptor (all but its compaction buffers jj .. meta) from
-// the descriptors of its G members (kinds K_GROUPED or K_GROUPED_STITCHED,
-// buffers attached).
+// the descriptors of its G members (kinds K_GROUPED, K_GROUPED_STITCHED or
+// K_GROUPED_STRAT, buffers attached).
 void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd);
 // Device bytes of a group's compaction buffers and their carving from `base`
 // (256-byte aligned pieces); returns the bytes taken.

@@ -1,5 +1,5 @@
-// Query groups: plain queries of one batch that share a graph, a walk key, a
-// continue threshold and a cap.
+// Query groups: queries of one batch (or of the server's waiting requests)
+// that share a graph, a kind of walks, a walk key and the walks' parameters.
 //
 // The estimator of Section 3 pairs walk j of the source s with walk j of every
 // node v.  The walk (v, j) draws its steps from counters (v, j, t, 0) under the
@@ -11,7 +11,11 @@
 // has no further step.  The pair ends when the walk stops, reaches a node
 // without in-neighbours, or no member is left.  Each member's counts are
 // therefore exactly those of its lone run; the walks from the nodes are paid
-// for once per group instead of once per query.
+// for once per group instead of once per query.  The same holds for stitched
+// walks (their tails come from the shared index, entered by a draw keyed
+// (v, j)) and for the stratified estimator's walks (walk j of v is the walk in
+// slot pi_v(j), a function of v and the key; a meet adds Lemma 5's weight of
+// the two walks' classes).
 #include <algorithm>
 
 #include "common.hpp"
@@ -21,7 +25,8 @@ namespace srk {
 namespace {
 
 // Tile shapes of the group meet kernel (walks and member positions per tile)
-// for groups of up to 8 members and of up to 32.
+// for groups of up to 8 members, of up to 32, and of stratified walks (whose
+// 64-bit weighted sums take LDS from the tile).
 #ifndef SRK_GROUP_TILE_J
 #define SRK_GROUP_TILE_J 1280
 #endif
@@ -34,24 +39,31 @@ namespace {
 #ifndef SRK_GROUP32_TILE_NODES
 #define SRK_GROUP32_TILE_NODES 28672
 #endif
+#ifndef SRK_GROUP_STRAT_TILE_J
+#define SRK_GROUP_STRAT_TILE_J 1024
+#endif
+#ifndef SRK_GROUP_STRAT_TILE_NODES
+#define SRK_GROUP_STRAT_TILE_NODES 24576
+#endif
 #ifndef SRK_GROUP_SLOTS
 #define SRK_GROUP_SLOTS 2
 #endif
 constexpr int GROUP_BLOCK = 1024;
 // GW: words of member lengths per entry the kernel instance holds (2: up to 8
-// members, 8: up to 32).
-__host__ __device__ constexpr int group_tile_j(int GW) {
-    return GW <= 2 ? SRK_GROUP_TILE_J : SRK_GROUP32_TILE_J;
+// members, 8: up to 32); WK: walks (0 plain, 1 stitched, 2 stratified).
+__host__ __device__ constexpr int group_tile_j(int GW, int WK) {
+    return WK == 2 ? SRK_GROUP_STRAT_TILE_J : GW <= 2 ? SRK_GROUP_TILE_J : SRK_GROUP32_TILE_J;
 }
-__host__ __device__ constexpr int group_tile_nodes(int GW) {   // < 2^16
-    return GW <= 2 ? SRK_GROUP_TILE_NODES : SRK_GROUP32_TILE_NODES;
+__host__ __device__ constexpr int group_tile_nodes(int GW, int WK) {   // < 2^16
+    return WK == 2 ? SRK_GROUP_STRAT_TILE_NODES : GW <= 2 ? SRK_GROUP_TILE_NODES : SRK_GROUP32_TILE_NODES;
 }
-static_assert(group_tile_nodes(2) < 65536 && group_tile_nodes(2) > 8 * MAX_CAP, "tile shape");
-static_assert(group_tile_nodes(8) < 65536 && group_tile_nodes(8) > 32 * MAX_CAP, "tile shape");
-static_assert(GROUP_MAX == 32, "length words");
+static_assert(group_tile_nodes(2, 0) < 65536 && group_tile_nodes(2, 0) > 8 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(8, 0) < 65536 && group_tile_nodes(8, 0) > 32 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(2, 2) < 65536 && group_tile_nodes(2, 2) > 8 * MAX_CAP, "tile shape");
+static_assert(GROUP_MAX == 32 && GROUP_MAX_STRAT <= 8, "length words");
 
-// The kernel instance for groups of G members.
-inline int group_gw(int32_t G) { return G <= 8 ? 2 : 8; }
+// The kernel instance's length words for groups of G members.
+__host__ __device__ inline int group_gw(int32_t G) { return G <= 8 ? 2 : 8; }
 
 // Length of member q in an entry's length words (byte q).
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int q) { return (w >> (8 * (q & 3))) & 0xffu; }
@@ -67,8 +79,8 @@ __device__ __forceinline__ uint32_t byte_of(uint32_t w, int q) { return (w >> (8
 __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restrict__ gd) {
     const GroupDesc &d = gd[blockIdx.x];
     const int32_t Rmax = d.Rmax, L = d.L, G = d.G, gw = d.gw;
-    const uint32_t TJ = (uint32_t)group_tile_j(G <= 8 ? 2 : 8);
-    const uint32_t NW = (uint32_t)(group_tile_nodes(G <= 8 ? 2 : 8) - G * L);
+    const uint32_t TJ = (uint32_t)group_tile_j(group_gw(G), d.wk);
+    const uint32_t NW = (uint32_t)(group_tile_nodes(group_gw(G), d.wk) - G * L);
     const int32_t per = (Rmax + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t j0 = min(Rmax, (int32_t)threadIdx.x * per), j1 = min(Rmax, j0 + per);
     uint32_t cnt = 0, nodes = 0;
@@ -124,26 +136,26 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
 }
 
 // Work-unit offsets of the groups (one block), one list per kernel instance
-// (group_list: plain or stitched walks, up to 8 members or more): ng + 1
+// (group_list: the walks, up to 8 members or more): ng + 1
 // offsets each, then one cursor each.
 __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restrict__ gd, int32_t ng,
                                                       uint32_t *__restrict__ units) {
     const int32_t per = (ng + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t g0 = min(ng, (int32_t)threadIdx.x * per), g1 = min(ng, g0 + per);
-    for (int list = 0; list < 4; ++list) {
+    for (int list = 0; list < GROUP_LISTS; ++list) {
         uint32_t sum = 0;
         for (int32_t g = g0; g < g1; ++g)
-            if (group_list(gd[g].G, gd[g].stitched) == list) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+            if (group_list(gd[g].G, gd[g].wk) == list) sum += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
         uint32_t total;
         uint32_t run = block_excl_sum(sum, &total);
         uint32_t *u = units + list * (ng + 1);
         for (int32_t g = g0; g < g1; ++g) {
             u[g] = run;
-            if (group_list(gd[g].G, gd[g].stitched) == list) run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
+            if (group_list(gd[g].G, gd[g].wk) == list) run += gd[g].meta[2] * (uint32_t)gd[g].n_chunks;
         }
         if (threadIdx.x == 0) {
             u[ng] = total;
-            units[4 * (ng + 1) + list] = 0u;
+            units[GROUP_LISTS * (ng + 1) + list] = 0u;
         }
     }
 }
@@ -157,9 +169,13 @@ __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restric
 // lengths and the mask of members still tested.  A step reads the members'
 // positions of that step, then compares.  Counts go to 16-bit LDS counters per
 // (member, node) (a unit holds at most TJ < 2^16 walks), flushed to the
-// members' counts once per unit.  STITCHED: the walk's first 2^k steps are
-// its own draws, the rest is read from the segment index, one load per
-// iteration, as in the single-query kernel.
+// members' counts once per unit.  WK = 1 (stitched): the walk's first 2^k
+// steps are its own draws, the rest is read from the segment index, one load
+// per iteration, as in the single-query kernel.  WK = 2 (stratified): walk j
+// of v is the fixed-length walk of slot pi_v(j) (the shuffle and the class
+// search are done when the pair starts), it takes no stop draws, and a meet of
+// member q adds Lemma 5's weight of the classes of walk j of s_q and of v to a
+// 64-bit LDS sum per (member, node).
 
 template <int GW>
 struct GSlot {
@@ -175,17 +191,18 @@ struct GSlot {
                        // 4 tail step; 5 chain, 6 next segment's length
     uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position,
                                         // segment, its length
+    uint32_t cv, jw;   // stratified: class (and last step) of walk (v, j), and j
 };
 
 // Compares the pair's position at step t with every member's position t.
 // Member q's positions lie at [B_q, B_q + len_q) within the tile, B_0 the
 // entry's offset and B_{q+1} = B_q + len_q; position t of member q is read only
 // if t <= len_q (else a harmless word).  A hit on any member sends the lane to
-// an exact pass that credits the members still tested; meets are rare, so the
-// common step is reads and compares only.
+// an exact pass; meets are rare, so the common step is reads and compares
+// only.  Returns the members still tested that meet at this step.
 template <int GW>
-__device__ __forceinline__ void group_compare(GSlot<GW> &w, const uint32_t *s_nodes, uint32_t *s_cnt,
-                                              int32_t gw, uint32_t &st_meets) {
+__device__ __forceinline__ uint32_t group_compare(const GSlot<GW> &w, const uint32_t *s_nodes,
+                                                  int32_t gw) {
     const uint32_t t1 = w.t - 1u;
     uint32_t B = w.pos & 0xffffu;
     bool hit = false;
@@ -203,7 +220,7 @@ __device__ __forceinline__ void group_compare(GSlot<GW> &w, const uint32_t *s_no
 #pragma unroll
         for (int b = 0; b < 4; ++b) hit |= pv[b] == w.o;
     }
-    if (!hit) return;
+    if (!hit) return 0u;
     uint32_t met = 0;
     B = w.pos & 0xffffu;
 #pragma unroll
@@ -217,29 +234,26 @@ __device__ __forceinline__ void group_compare(GSlot<GW> &w, const uint32_t *s_no
             B += l;
         }
     }
-    met &= w.live;
-    if (met) {
-        const uint32_t vl = w.pos >> 24;
-        st_meets += (uint32_t)__popc(met);
-        w.live &= ~met;
-        for (uint32_t m = met; m; m &= m - 1u) {
-            const uint32_t q = (uint32_t)__builtin_ctz(m);
-            atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
-        }
-    }
+    return met & w.live;
 }
 
-template <int NS, int GW, bool STITCHED>
+template <int NS, int GW, int WK>
 __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__restrict__ gd, int32_t ng,
                                                             const uint32_t *__restrict__ ustart,
                                                             uint32_t *__restrict__ cursor,
                                                             unsigned long long *__restrict__ counters) {
-    constexpr int TJ = group_tile_j(GW), TN = group_tile_nodes(GW), GM = 4 * GW;
+    constexpr bool STITCHED = WK == 1, STRAT = WK == 2;
+    constexpr int TJ = group_tile_j(GW, WK), TN = group_tile_nodes(GW, WK), GM = 4 * GW;
     __shared__ uint32_t s_nodes[TN];
     __shared__ uint32_t s_j[TJ];
     __shared__ uint16_t s_off[TJ];
     __shared__ uint32_t s_len[TJ * GW];
-    __shared__ uint32_t s_cnt[GM / 2 * MEET_VB];   // members 2i, 2i+1 in the low, high half
+    __shared__ uint32_t s_cnt[STRAT ? 1 : GM / 2 * MEET_VB];   // members 2i, 2i+1 in the low, high half
+    // stratified: weighted sums per (member, node), the nodes' shuffle keys,
+    // the class starts
+    __shared__ unsigned long long s_w[STRAT ? GM * MEET_VB : 1];
+    __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
+    __shared__ uint32_t s_ccum[STRAT ? MAX_CAP + 2 : 1];
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
     __shared__ uint32_t s_srcm[MEET_VB];   // members whose source is the node
@@ -274,6 +288,8 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         const PhiloxKey key{uni(d.k0), uni(d.k1)};
         const uint32_t T = uni(d.T);
         const uint32_t gmask = G >= 32 ? 0xffffffffu : (1u << G) - 1u;
+        const uint32_t NN = uni((uint32_t)d.Rmax), sa = uni((uint32_t)d.sa), sb = uni((uint32_t)d.sb);
+        const int32_t phi = (int32_t)uni((uint32_t)d.L);
         if ((uint32_t)gi != cur_g || tile != cur_tile) {
             const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
             const uint32_t nb = d.joff[k0], ne = d.joff[k1];
@@ -293,12 +309,18 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                 s_len[i] = (int32_t)wd < gw ? d.glen[(size_t)(k0 + k) * gw + wd] : 0u;
             }
             for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.pos[nb + i];
+            if (STRAT)
+                for (uint32_t i = threadIdx.x; i < (uint32_t)phi + 2; i += blockDim.x)
+                    s_ccum[i] = d.tab->ccum[i];
             cur_g = (uint32_t)gi;
             cur_tile = tile;
         }
         const int32_t vbase = (int32_t)chunk * vb;
         const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
-        for (uint32_t i = threadIdx.x; i < GM / 2 * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
+        if (STRAT)
+            for (uint32_t i = threadIdx.x; i < GM * MEET_VB; i += blockDim.x) s_w[i] = 0ull;
+        else
+            for (uint32_t i = threadIdx.x; i < GM / 2 * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
             const uint32_t id = (uint32_t)d.active[vbase + (int32_t)i];
             s_vid[i] = id;
@@ -306,6 +328,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
             uint32_t m = 0;
             for (int32_t q = 0; q < G; ++q) m |= (uint32_t)((uint32_t)d.s[q] == id) << q;
             s_srcm[i] = m;
+            if (STRAT) s_fk[i] = philox4x32_10(id, 0u, 0u, DOM_SHUFFLE, key);
         }
         if (threadIdx.x == 0) s_item = 0u;
         __syncthreads();
@@ -323,7 +346,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
 
         for (;;) {
             // ---- refill idle slots; a pair with no member to test (each
-            // member's source is v) is skipped
+            // member's source is v), or a stratified walk of class 0, is skipped
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 uint64_t need = __ballot(!sl[qq].busy);
@@ -357,10 +380,21 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                         // members tested: all but those whose source is v (a
                         // member whose walk j is empty never reads a position)
                         const uint32_t live = gmask & ~s_srcm[vl];
-                        if (live) {
+                        uint32_t r = 0, cv = 0;
+                        if (STRAT && live) {
+                            r = shuffle_slot(s_j[k], NN, sa, sb, s_fk[vl]);
+                            cv = slot_class(r, s_ccum, phi);
+                        }
+                        if (live && (!STRAT || cv > 0u)) {
                             const uint2 row = s_vrow[vl];
                             GSlot<GW> &w = sl[qq];
-                            w.rng = walk_draws_begin(s_vid[vl], s_j[k], key);
+                            if (STRAT) {
+                                w.rng = walk_draws_begin(s_vid[vl], r, key, DOM_STRAT);
+                                w.cv = cv;
+                                w.jw = s_j[k];
+                            } else {
+                                w.rng = walk_draws_begin(s_vid[vl], s_j[k], key);
+                            }
                             w.pos = (uint32_t)s_off[k] | ((uint32_t)s_maxl[k] << 16) | (vl << 24);
                             w.live = live;
 #pragma unroll
@@ -403,7 +437,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                     ++sl[qq].t;
                     const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
-                    if (x.x >= T) {
+                    if (!STRAT && x.x >= T) {
                         sl[qq].busy = false;
                     } else {
                         go[qq] = true;
@@ -446,11 +480,28 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                     w.o = tv[qq];
                     ++w.tu;
                 }
-                if (go[qq] || tail_step) group_compare(w, s_nodes, s_cnt, gw, st_meets);
+                if (go[qq] || tail_step) {
+                    const uint32_t met = group_compare(w, s_nodes, gw);
+                    if (met) {
+                        const uint32_t vl = w.pos >> 24;
+                        st_meets += (uint32_t)__popc(met);
+                        w.live &= ~met;
+                        for (uint32_t m = met; m; m &= m - 1u) {
+                            const uint32_t q = (uint32_t)__builtin_ctz(m);
+                            if (STRAT)
+                                atomicAdd(&s_w[q * MEET_VB + vl],
+                                          strat_weight(d.tab->a, d.scls[q][w.jw], w.cv));
+                            else
+                                atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
+                        }
+                    }
+                }
                 if (go[qq]) {
-                    // the pair ends with its last member walk, when every
-                    // member tested has met, or at a node without in-neighbours
-                    if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu))
+                    // the pair ends with its last member walk (or, stratified,
+                    // the class of walk (v, j)), when every member tested has
+                    // met, or at a node without in-neighbours
+                    if (w.live == 0u || w.d == 0u || w.t == ((w.pos >> 16) & 0xffu) ||
+                        (STRAT && w.t == w.cv))
                         w.busy = false;
                     else if (STITCHED && w.t == (uint32_t)d.ix.seg_len)
                         w.ph = 1;   // the head made all its moves: enter a pool slot of this node
@@ -499,8 +550,13 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < (uint32_t)G * nv; i += blockDim.x) {
             const uint32_t q = i / nv, vi = i - q * nv;
-            const uint32_t c = (s_cnt[(q >> 1) * MEET_VB + vi] >> (16 * (q & 1u))) & 0xffffu;
-            if (c) atomicAdd(&d.cnt[q][s_vid[vi]], c);
+            if (STRAT) {
+                const unsigned long long c = s_w[q * MEET_VB + vi];
+                if (c) atomicAdd(&d.wsum[q][s_vid[vi]], c);
+            } else {
+                const uint32_t c = (s_cnt[(q >> 1) * MEET_VB + vi] >> (16 * (q & 1u))) & 0xffffu;
+                if (c) atomicAdd(&d.cnt[q][s_vid[vi]], c);
+            }
         }
     }
 
@@ -525,13 +581,13 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
 #define SRK_GROUP_SLOTS_STITCHED 2
 #endif
 
-template <int NS, int GW, bool STITCHED>
+template <int NS, int GW, int WK>
 int group_grid_blocks() {
     static const int blocks = [] {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<NS, GW, STITCHED>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet_group<NS, GW, WK>,
                                                            GROUP_BLOCK, 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
@@ -540,21 +596,21 @@ int group_grid_blocks() {
     return blocks;
 }
 
-template <int NS, int GW, bool STITCHED>
+template <int NS, int GW, int WK>
 void launch_group_list(const GroupSet &gs, int list, unsigned long long *counters, hipStream_t st) {
     if (gs.units_bound[list] <= 0) return;
-    const int blocks = (int)std::min<int64_t>(gs.units_bound[list], group_grid_blocks<NS, GW, STITCHED>());
-    k_meet_group<NS, GW, STITCHED><<<blocks, GROUP_BLOCK, 0, st>>>(
-        gs.desc, gs.ng, gs.units + (size_t)list * (gs.ng + 1), gs.units + 4 * ((size_t)gs.ng + 1) + list,
-        counters);
+    const int blocks = (int)std::min<int64_t>(gs.units_bound[list], group_grid_blocks<NS, GW, WK>());
+    k_meet_group<NS, GW, WK><<<blocks, GROUP_BLOCK, 0, st>>>(
+        gs.desc, gs.ng, gs.units + (size_t)list * (gs.ng + 1),
+        gs.units + GROUP_LISTS * ((size_t)gs.ng + 1) + list, counters);
 }
 
 }  // namespace
 
-int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G) {
+int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int32_t wk) {
     const int GW = group_gw(G);
-    const int64_t NW = group_tile_nodes(GW) - (int64_t)G * L;
-    return (int32_t)(2 + Rmax / group_tile_j(GW) + sum_RL / NW);
+    const int64_t NW = group_tile_nodes(GW, wk) - (int64_t)G * L;
+    return (int32_t)(2 + Rmax / group_tile_j(GW, wk) + sum_RL / NW);
 }
 
 void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
@@ -568,8 +624,11 @@ void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
     gd->n_chunks = d0.n_chunks;
     gd->G = G;
     gd->gw = (G + 3) / 4;
-    gd->stitched = d0.kind == K_GROUPED_STITCHED;
+    gd->wk = d0.kind == K_GROUPED_STITCHED ? 1 : d0.kind == K_GROUPED_STRAT ? 2 : 0;
     gd->ix = d0.ix;
+    gd->tab = d0.tab;
+    gd->sa = d0.sa;
+    gd->sb = d0.sb;
     gd->L = d0.L;
     gd->k0 = d0.k0;
     gd->k1 = d0.k1;
@@ -581,6 +640,8 @@ void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
         gd->sw[q] = dq.sw;
         gd->slen[q] = dq.slen;
         gd->cnt[q] = dq.cnt;
+        gd->wsum[q] = dq.wsum;
+        gd->scls[q] = dq.scls;
         gd->Rmax = std::max(gd->Rmax, dq.R);
     }
 }
@@ -592,7 +653,7 @@ size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base) {
         at += (b + 255) & ~(size_t)255;
         return r;
     };
-    const int32_t mt = group_max_tiles(gd->Rmax, sum_RL, gd->L, gd->G);
+    const int32_t mt = group_max_tiles(gd->Rmax, sum_RL, gd->L, gd->G, gd->wk);
     gd->jj = (uint32_t *)take(4 * (size_t)gd->Rmax);
     gd->joff = (uint32_t *)take(4 * ((size_t)gd->Rmax + 1));
     gd->glen = (uint32_t *)take(4 * (size_t)gd->Rmax * (size_t)gd->gw);
@@ -606,10 +667,11 @@ int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t 
     if (gs.ng <= 0) return SIMRANK_OK;
     k_group_compact<<<gs.ng, 1024, 0, st>>>(gs.desc);
     k_group_units<<<1, 1024, 0, st>>>(gs.desc, gs.ng, gs.units);
-    launch_group_list<SRK_GROUP_SLOTS, 2, false>(gs, 0, counters, st);
-    launch_group_list<SRK_GROUP_SLOTS, 8, false>(gs, 1, counters, st);
-    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 2, true>(gs, 2, counters, st);
-    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 8, true>(gs, 3, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS, 2, 0>(gs, 0, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS, 8, 0>(gs, 1, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 2, 1>(gs, 2, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS_STITCHED, 8, 1>(gs, 3, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS, 2, 2>(gs, 4, counters, st);
     SRK_HIP(hipGetLastError());
     return SIMRANK_OK;
 }

@@ -33,7 +33,7 @@ __global__ void k_init(const QueryDesc *__restrict__ qd, unsigned long long *__r
         d.meta[threadIdx.x] = 0u;
         if (blockIdx.y == 0) counters[threadIdx.x] = 0ull;
     }
-    if (d.kind == K_STRAT) {
+    if (strat_kind(d.kind)) {
         for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.wsum[v] = 0ull;
     } else {
         for (int64_t v = i; v < d.n; v += (int64_t)gridDim.x * blockDim.x) d.cnt[v] = 0u;
@@ -48,7 +48,7 @@ __global__ void k_estimate(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.y];
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        if (d.kind == K_STRAT) {
+        if (strat_kind(d.kind)) {
             const double x = (double)d.wsum[v] * 9.094947017729282379150390625e-13;   // 2^-40
             const double e = x / d.z;
             if (d.out) d.out[v] = (v == d.s) ? 1.0 : e;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
         uint32_t *row = d.sw + (size_t)j * d.L;
         uint2 cur = d.nodes[d.s];
         int32_t len = 0;
-        if (d.kind == K_STRAT) {
+        if (strat_kind(d.kind)) {
             const uint4 fk = philox4x32_10((uint32_t)d.s, 0u, 0u, DOM_SHUFFLE, key);
             const uint32_t r = shuffle_slot((uint32_t)j, (uint32_t)d.R, (uint32_t)d.sa, (uint32_t)d.sb, fk);
             const uint32_t cls = slot_class(r, d.tab->ccum, d.L);

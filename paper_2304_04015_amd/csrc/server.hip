@@ -138,12 +138,12 @@ static int launch_group(simrank_server *S, const std::vector<Request *> &rs,
     GroupDesc *gd = gr.gdesc_host;
     describe_group(mem.data(), G, gd);
     (void)group_buffers(gd, sum_RL, gr.buffers);
-    const int64_t units = (int64_t)group_max_tiles(gd->Rmax, sum_RL, gd->L, G) * gd->n_chunks;
+    const int64_t units = (int64_t)group_max_tiles(gd->Rmax, sum_RL, gd->L, G, gd->wk) * gd->n_chunks;
     if (units >= (int64_t)0x7fffffff) return fail(SIMRANK_EINVAL, "group has too many work units");
     GroupSet gs;
     gs.desc = gr.gdesc_dev;
     gs.ng = 1;
-    gs.units_bound[group_list(G, gd->stitched)] = units;
+    gs.units_bound[group_list(G, gd->wk)] = units;
     gs.units = gr.gunits;
     QuerySet qs;
     qs.desc = gr.desc_dev;

@@ -271,3 +271,64 @@ def test_tile_and_unit_settings_keep_results(graphs):
         with pytest.raises(S.SimRankError):
             S.simrank_set_tuning(G, *bad)
     S.simrank_set_tuning(G, 0, 0)
+
+
+def test_stratified_groups_equal_lone(graphs):
+    """Stratified queries with one seed, z and phi form groups of up to 8 that
+    walk each (v, j) once (walk j of v: slot pi_v(j), its class, its steps);
+    every member's weighted sums, and both estimates, equal its lone run's,
+    bit for bit; queries with another z or seed stay in groups of their own."""
+    gs, Gs = graphs
+    g, G = gs[2], Gs[2]
+    rng = np.random.default_rng(17)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    S1, S2 = 0x2304040150000061, 0x2304040150000062
+    srcs = [int(x) for x in rng.choice(act, 14, replace=False)]
+    qs = [S.make_stratified_query(s, c=0.6, eps=0.1, seed=S1, z=2500, phi=12, graph=2)
+          for s in srcs[:11]]
+    qs += [S.make_stratified_query(s, c=0.6, eps=0.1, seed=S1, z=900, phi=12, graph=2)
+           for s in srcs[11:14]]
+    qs += [S.make_stratified_query(s, c=0.6, eps=0.1, seed=S2, z=2500, phi=12, graph=2)
+           for s in srcs[:2]]
+    qs += [S.make_query(srcs[0], c=0.6, seed=S1, walk_cap=12, R=1000, graph=2)]   # plain, alone
+    plan = S.BatchPlan(Gs, qs)
+    assert plan.n_groups == 4          # 11 -> 6 + 5, 3, 2
+    plan.run()
+    st = plan.wait()
+    flat = S.BatchPlan(Gs, qs, groups=False)
+    flat.run()
+    fst = flat.wait()
+    _say(f"stratified groups: {st.moves} moves vs {fst.moves} ungrouped")
+    for i, q in enumerate(qs):
+        if q.mode != S.MODE_STRATIFIED:
+            continue
+        o1, on1, w1, _ = S.simrank_single_source_stratified(G, q)
+        o, on, w = plan.read_stratified(i)
+        assert np.array_equal(w, w1) and np.array_equal(o, o1) and np.array_equal(on, on1), i
+        assert np.array_equal(flat.read_stratified(i)[2], w1), i
+        with pytest.raises(S.SimRankError):
+            plan.read(i, want_out=False, want_counts=True)
+    assert st.meets == fst.meets and st.moves < fst.moves
+    P = O.strat_params(g.n, 0.6, 0.1, z=900.0, phi=12)
+    assert np.array_equal(plan.read_stratified(11)[2], O.strat_sums(g, srcs[11], S1, P))
+    plan.free()
+    flat.free()
+
+
+def test_stratified_group_full_size():
+    """Eight stratified queries with Algorithm 2's z and Algorithm 1's cap on a
+    2^16-node R-MAT graph (N = 14,825, phi = 43) and one seed: one group, each
+    member's weighted sums equal to its lone run's."""
+    g = inputs.rmat_in(16, 16 << 16, seed=72)
+    G = S.load_csr(g)
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, 8, 75)]
+    qs = [S.make_stratified_query(s, c=0.6, eps=0.02, seed=0x2304040150000063) for s in srcs]
+    plan = S.BatchPlan([G], qs)
+    assert plan.n_groups == 1
+    plan.run()
+    st = plan.wait()
+    _say(f"stratified group of 8 at full size: {st.ms:.1f} ms, {st.moves} moves")
+    for i, q in enumerate(qs):
+        assert np.array_equal(plan.read_stratified(i)[2],
+                              S.simrank_single_source_stratified(G, q)[2]), i
+    plan.free()
