@@ -82,11 +82,15 @@ def parse():
                          "graph's 8 sources (and 32) through Algorithm 2's tuple form")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
+    ap.add_argument("--tune-index", action="store_true",
+                    help="stitching: also run the segment-length tuner (k = 2, 3, 4) and report it")
     ap.add_argument("--group-max", type=int, default=0,
                     help="serving: admit waiting requests with one walk seed as query groups of "
                          "up to this many (0: every request alone, with its own seed)")
     ap.add_argument("--group-queries", type=int, default=32,
                     help="grouped: number of same-seed queries on the medium graph")
+    ap.add_argument("--group-kind", default="plain", choices=["plain", "stratified"],
+                    help="grouped: plain queries (groups of up to 32) or stratified ones (up to 8)")
     ap.add_argument("--shared-seed", action="store_true",
                     help="batching: one walk seed per graph instead of one per query, so that "
                          "the queries of a graph share their walks from every node (query groups)")
@@ -525,6 +529,12 @@ def bench_stitching(args):
                            "kernel_steps_per_s": steps_per_s,
                            "steps_vs_random_gather": steps_per_s / gather["per_s"]},
     }
+    if args.tune_index:
+        # segment-length tuner: the index built with k = 2, 3, 4, the same
+        # stitched query timed on each; the fastest index is left built
+        choice, ms_k = S.simrank_tune_index(G, q, seg_log2=(2, 3, 4), kappa=cfg["kappa"],
+                                            c=cfg["c"], seed=cfg["index_seed"])
+        result["index_tuner"] = {"seg_log2": [2, 3, 4], "meet_ms": ms_k, "choice": choice}
     print(json.dumps(result))
     ws.free()
     G.free()
@@ -567,7 +577,7 @@ def bench_batching(args):
     for gi, G in enumerate(Gs):
         act = np.nonzero(gs[gi].in_degree() > 0)[0]
         tq = S.make_query(int(act[0]), c=cfg["c"], eps=0.02, delta=cfg["delta"], walk_cap=cfg["L"])
-        tuned.append(S.simrank_tune(G, tq))
+        tuned.append(S.simrank_tune_ex(G, tq))
     # (a) one query at a time
     maxR = [1] * len(Gs)
     for q in queries:
@@ -627,7 +637,8 @@ def bench_batching(args):
             ms += qs_.meet_ms
         rate = moves / (ms / 1e3) if ms > 0 else 0.0
         per_graph.append({"n": gs[gi].n, "m": gs[gi].m, "queries": sum(q.graph == gi for q in queries),
-                          "unit_nodes": tuned[gi], "moves_per_s": rate,
+                          "unit_nodes": tuned[gi]["unit_nodes"],
+                          "tile_walks": tuned[gi]["tile_walks"], "moves_per_s": rate,
                           "achieved_GBps": BYTES_PER_MOVE * rate / 1e9,
                           "frac": BYTES_PER_MOVE * rate / 1e9 / HBM_PEAK_GBS})
     result = {
@@ -649,7 +660,7 @@ def bench_batching(args):
         "batch_results_equal_plain": same,
         "groups": plan.n_groups,
         "ungrouped_batch": flat,
-        "tuned_unit_nodes": tuned,
+        "tuned": [{"unit_nodes": t["unit_nodes"], "tile_walks": t["tile_walks"]} for t in tuned],
         "batch": {"moves": st.moves, "draws": st.draws, "device_ms": st.ms, "pairs": st.pairs},
         "per_graph": per_graph,
     }
@@ -680,10 +691,16 @@ def bench_grouped(args):
     g = inputs.workload_graph(cfg)
     G = S.load_csr(g)
     nq = args.group_queries
+    strat = args.group_kind == "stratified"
     srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, cfg["source_seed"])]
-    qs = [S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
-                       walk_cap=cfg["L"]) for s in srcs]
-    R = S.simrank_derive_params(qs[0], g.n).R
+    if strat:
+        qs = [S.make_stratified_query(s, c=cfg["c"], eps=cfg["eps"], seed=cfg["walk_seed"])
+              for s in srcs]
+        R = S.simrank_derive_stratified(qs[0], g.n).N
+    else:
+        qs = [S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
+                           walk_cap=cfg["L"]) for s in srcs]
+        R = S.simrank_derive_params(qs[0], g.n).R
     plan = S.BatchPlan([G], qs)
     stream = torch.cuda.Stream()
     for _ in range(args.warmup):
@@ -698,12 +715,15 @@ def bench_grouped(args):
         moves += st.moves + st.source_moves
         dev_ms += st.ms
     dt = time.perf_counter() - t0
-    grouped = [plan.read(i, want_out=False)[1] for i in range(nq)]
+    def res(p, i):
+        return p.read_stratified(i)[2] if strat else p.read(i, want_out=False)[1]
+    grouped = [res(plan, i) for i in range(nq)]
     flat = S.BatchPlan([G], qs, groups=False)
     flat.run(stream)
     fst = flat.wait()
-    same = all(np.array_equal(flat.read(i, want_out=False)[1], grouped[i]) for i in range(nq))
-    lone = np.array_equal(S.simrank_single_source_ex(G, qs[0])[1], grouped[0])
+    same = all(np.array_equal(res(flat, i), grouped[i]) for i in range(nq))
+    lone = np.array_equal(S.simrank_single_source_stratified(G, qs[0])[2] if strat else
+                          S.simrank_single_source_ex(G, qs[0])[1], grouped[0])
     kernel_s = (dev_ms / steps) / 1e3
     achieved = BYTES_PER_MOVE * st.moves / kernel_s / 1e9
     result = {
@@ -714,8 +734,10 @@ def bench_grouped(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"grouped: medium graph (R-MAT n=2^20, 16n edge draws), {nq} "
-                               "single-source queries with one walk seed, eps=0.02 delta=1e-3 "
-                               f"R={R} L=64, one captured batch plan forming one query group",
+                               "single-source queries with one walk seed, eps=0.02 delta=1e-3 " +
+                               (f"stratified (N={R}), one captured batch plan forming "
+                                f"{plan.n_groups} query groups of up to 8" if strat else
+                                f"R={R} L=64, one captured batch plan forming one query group"),
                    "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries": nq,
                    "groups": plan.n_groups},
         "queries_per_s": nq * steps / dt,
@@ -726,10 +748,13 @@ def bench_grouped(args):
         "results_equal_ungrouped": same,
         "first_equals_lone_query": lone,
         "roofline": {
-            "bound": "hbm", "kernel": "k_meet_group<2, 8, false> (whole plan's device time)",
+            "bound": "hbm",
+            "kernel": ("k_meet_group<2, 2, 2>" if strat else "k_meet_group<2, 8, 0>") +
+                      " (whole plan's device time)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_grouped.json")),
+            "traffic": None if strat else
+            measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_grouped.json")),
         },
     }
     print(json.dumps(result))
