@@ -302,10 +302,12 @@ int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
 /* Flags of simrank_batch_plan_create_ex. */
 #define SIMRANK_PLAN_GROUPS 1u
 /* simrank_batch_plan_create with flags (simrank_batch_plan_create and
- * simrank_batch pass SIMRANK_PLAN_GROUPS).  SIMRANK_PLAN_GROUPS: plain queries
- * on one graph with equal seed, c and walk cap are run in groups of up to 32
- * that share the walks from every node (Section 3's walk (v, j) depends on the
- * seed, c and cap only, not on the source): each walk (v, j) is taken once
+ * simrank_batch pass SIMRANK_PLAN_GROUPS).  SIMRANK_PLAN_GROUPS: queries of one
+ * mode on one graph with equal seed and walk parameters (plain and stitched:
+ * c and walk cap; stratified: z, N and phi) are run in groups of up to 32 (8
+ * for stratified queries) that share the walks from every node (Section 3's
+ * walk (v, j), and Algorithm 1's walk in slot pi_v(j), depend on the seed and
+ * those parameters only, not on the source): each walk (v, j) is taken once
  * and compared with walk j of every member's source.  Results are bit for bit
  * those without the flag; the stats count a shared walk's steps once.
  * n_groups_out (may be NULL) receives the number of groups formed.  EINVAL

@@ -6,8 +6,8 @@
 // whose work units span all queries (per kind: plain, stitched, stratified),
 // estimate.
 // Queries on graphs of very different sizes share the launch and its tail.
-// Plain queries on one graph with the same seed, c and cap form groups that
-// walk each pair (v, j) once for all members (group.hip).
+// Queries of one kind on one graph with the same seed and walk parameters form
+// groups that walk each pair (v, j) once for all members (group.hip).
 // Each query's result is exactly the one a lone simrank_single_source_ex call
 // returns: results depend only on (graph, query).
 #include <algorithm>
