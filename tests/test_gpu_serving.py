@@ -116,3 +116,44 @@ def test_grouped_admission_equals_lone(served):
     srv.destroy()
     with pytest.raises(S.SimRankError):
         S.Server(G, max_slots=2, group_max=33)
+
+
+def test_concurrent_submitters_with_groups(served):
+    """Four client threads submit and wait at once (plain and stitched requests,
+    two seeds) into a grouping server: every result equals the lone query's."""
+    import threading
+    g, G = served
+    rng = np.random.default_rng(23)
+    deg = g.in_degree().astype(np.float64)
+    per_thread = []
+    for t in range(4):
+        qs = []
+        for i in range(8):
+            s = int(rng.choice(g.n, p=deg / deg.sum()))
+            mode = S.MODE_STITCHED if (t + i) % 3 == 0 else S.MODE_PLAIN
+            qs.append(S.make_query(s, c=0.6, eps=0.05, delta=1e-3, seed=0x5EA0 + (i % 2), mode=mode))
+        per_thread.append(qs)
+    lone = [[S.simrank_single_source_ex(G, q)[1] for q in qs] for qs in per_thread]
+    srv = S.Server(G, max_slots=8, max_R=9502, max_L=64, group_max=8)
+    errors = []
+
+    def client(t):
+        try:
+            tickets = [srv.submit(q) for q in per_thread[t]]
+            for k, tk in enumerate(tickets):
+                _, c, _ = srv.wait(tk, want_out=False)
+                if not np.array_equal(c, lone[t][k]):
+                    errors.append((t, k))
+        except Exception as e:   # reported below
+            errors.append((t, repr(e)))
+
+    threads = [threading.Thread(target=client, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    assert not any(th.is_alive() for th in threads)
+    assert not errors, errors
+    k = srv.counts()
+    assert k["done"] == 32 and k["failed"] == 0
+    srv.destroy()
