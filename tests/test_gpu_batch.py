@@ -332,3 +332,40 @@ def test_stratified_group_full_size():
         assert np.array_equal(plan.read_stratified(i)[2],
                               S.simrank_single_source_stratified(G, q)[2]), i
     plan.free()
+
+
+def test_group_edge_cases():
+    """Groups at the edges: walk cap 1, R = 1, every member with the same
+    source, a member whose source has no in-edges (no entries of its own),
+    a star graph, and stitched groups on indexes with 1-step and 64-step
+    segments; every count equals the lone query's."""
+    g = inputs.from_edges(6, [0, 0, 0, 0, 1, 2, 3], [1, 2, 3, 4, 0, 0, 5])
+    G = S.load_csr(g)
+    no_in = int(np.argmax(g.in_degree() == 0))
+    cases = [
+        [S.make_query(s, c=0.6, seed=0xE1, walk_cap=1, R=R) for s, R in ((0, 1), (1, 2), (5, 5))],
+        [S.make_query(1, c=0.6, seed=0xE2, walk_cap=8, R=R) for R in (40, 41, 7)],   # one source
+        [S.make_query(s, c=0.6, seed=0xE3, walk_cap=64, R=300) for s in (no_in, 0, 1)],
+    ]
+    for qs in cases:
+        plan = S.BatchPlan([G], qs)
+        assert plan.n_groups == 1
+        plan.run()
+        plan.wait()
+        for i, q in enumerate(qs):
+            assert np.array_equal(plan.read(i)[1], S.simrank_single_source_ex(G, q)[1]), (i, q.s)
+        plan.free()
+    g2 = inputs.rmat_in(10, 8 << 10, seed=83)
+    G2 = S.load_csr(g2)
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g2, 5, 84)]
+    for k in (0, 6):
+        S.simrank_build_index(G2, seg_log2=k, kappa=1.0, c=0.6, seed=ISEED)
+        qs = [S.make_query(s, c=0.6, seed=0xE4, walk_cap=64, R=700, mode=S.MODE_STITCHED)
+              for s in srcs]
+        plan = S.BatchPlan([G2], qs)
+        assert plan.n_groups == 1
+        plan.run()
+        plan.wait()
+        for i, q in enumerate(qs):
+            assert np.array_equal(plan.read(i)[1], S.simrank_single_source_ex(G2, q)[1]), (k, i)
+        plan.free()
