@@ -21,7 +21,9 @@
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low
  * word, seed high word) and counter = (node, walk, step, domain); domain 0 =
  * step of a walk, 1 = step of a pool segment, 2 = pool slot entered after the
- * private head, 3 = successor slot of a segment.  At step t (1-based) a walk
+ * private head, 3 = successor slot of a segment, 4 = step of a stratified
+ * fixed-length walk (counter (node, slot, step, 4)), 5 = round keys of a
+ * node's walk shuffle (counter (node, 0, 0, 5)).  At step t (1-based) a walk
  * draws x; it stops if x0 >= T = floor(sqrt(c) * 2^32) or its node has no
  * in-neighbour, else moves to in-neighbour number floor(x1 * deg / 2^32) of the
  * in-edge row (row order as passed to simrank_load_graph).  Results are a pure
