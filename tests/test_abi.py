@@ -149,3 +149,22 @@ def test_derive_stratified_rejects(kw):
     with pytest.raises(S.SimRankError) as e:
         S.simrank_derive_stratified(q, n)
     assert e.value.code == S.SIMRANK_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises on first use; there is no
+    CPU fallback on the product path."""
+    import os
+    import subprocess
+    import sys
+    env = dict(os.environ, SIMRANK_LIB=str(tmp_path / "absent.so"))
+    code = ("from paper_2304_04015_amd import simrank as S\n"
+            "try:\n"
+            "    S.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "else:\n"
+            "    print('loaded')\n")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))), timeout=300)
+    assert "raised" in r.stdout and "absent.so" in r.stdout, (r.stdout, r.stderr)
