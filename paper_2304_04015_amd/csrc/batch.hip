@@ -47,8 +47,8 @@ size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
 
 // Groups of queries of one kind that share (graph, seed, continue threshold,
 // cap; stratified: z, N and phi): each such set of two or more queries is
-// split into ceil(size / max) groups of nearly equal size, in query order (max
-// GROUP_MAX, GROUP_MAX_STRAT for stratified walks).
+// split into ceil(size / GROUP_MAX) groups of nearly equal size, in query
+// order.
 std::vector<std::vector<int32_t>> form_groups(simrank_graph *const *graphs, const simrank_query *qs,
                                               int32_t nq, const std::vector<simrank_params> &ps,
                                               const std::vector<int> &modes) {
@@ -71,8 +71,7 @@ std::vector<std::vector<int32_t>> form_groups(simrank_graph *const *graphs, cons
         const std::vector<int32_t> &v = kv.second;
         const int32_t sz = (int32_t)v.size();
         if (sz < 2) continue;
-        const int32_t mx = std::get<1>(kv.first) == SIMRANK_MODE_STRATIFIED ? GROUP_MAX_STRAT : GROUP_MAX;
-        const int32_t ngr = (sz + mx - 1) / mx;
+        const int32_t ngr = (sz + GROUP_MAX - 1) / GROUP_MAX;
         int32_t at = 0;
         for (int32_t k = 0; k < ngr; ++k) {
             const int32_t take = sz / ngr + (k < sz % ngr ? 1 : 0);
@@ -179,7 +178,9 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
                 RL += (int64_t)ps[i].R * ps[i].L;
             }
             const Graph *g = graphs[qs[m[0]].graph];
-            const int64_t vb = default_unit_nodes(g);
+            int64_t vb = default_unit_nodes(g);
+            if (modes[m[0]] == SIMRANK_MODE_STRATIFIED && m.size() > 8)
+                vb = std::min<int64_t>(vb, GROUP_STRAT32_VB);   // as describe_group sets it
             const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size(),
                                                         walk_kind(modes[m[0]])) *
                                ((g->n_active + vb - 1) / vb);

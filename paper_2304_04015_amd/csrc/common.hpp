@@ -209,15 +209,17 @@ inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1
 // ------------------------------------------------------------ query groups
 // In a batch, queries of one kind on one graph with the same walk key and walk
 // parameters (c and cap; the stratified estimator's z and cap) have the same
-// walk (v, j) from every node v: a group of up to GROUP_MAX such queries (8 for
-// stratified walks) follows each walk once and tests it against every
+// walk (v, j) from every node v: a group of up to GROUP_MAX such queries
+// follows each walk once and tests it against every
 // member's walk j of its own source (group.hip).  A member keeps its own
 // descriptor (source walks, counts or weighted sums, estimate) with kind
 // K_GROUPED, K_GROUPED_STITCHED or K_GROUPED_STRAT, which no per-kind unit list
 // takes.
 constexpr int GROUP_MAX = 32;
 constexpr int32_t K_GROUPED = N_KINDS, K_GROUPED_STITCHED = N_KINDS + 1, K_GROUPED_STRAT = N_KINDS + 2;
-constexpr int GROUP_MAX_STRAT = 8;
+// Groups of more than 8 stratified queries keep their 64-bit weighted sums for
+// at most this many nodes per work unit.
+constexpr int GROUP_STRAT32_VB = 64;
 // Kinds whose walks are the stratified estimator's (weighted sums, not counts).
 __host__ __device__ inline bool strat_kind(int32_t kind) { return kind == K_STRAT || kind == K_GROUPED_STRAT; }
 
@@ -260,11 +262,10 @@ struct GroupSet {
     uint32_t *units = nullptr;           // device [group_units_words(ng)]
 };
 // Kernel instance of a group: plain walks with up to 8 members (0) or more
-// (1), stitched walks with up to 8 (2) or more (3), stratified walks (4).
-constexpr int GROUP_LISTS = 5;
-__host__ __device__ inline int group_list(int32_t G, int32_t wk) {
-    return wk == 2 ? 4 : (G > 8 ? 1 : 0) + (wk == 1 ? 2 : 0);
-}
+// (1), stitched walks with up to 8 (2) or more (3), stratified walks with up
+// to 8 (4) or more (5).
+constexpr int GROUP_LISTS = 6;
+__host__ __device__ inline int group_list(int32_t G, int32_t wk) { return 2 * wk + (G > 8 ? 1 : 0); }
 // Unit offsets of a group set: one list of ng + 1 offsets per instance, then
 // one cursor per list.
 inline size_t group_units_words(int32_t ng) { return GROUP_LISTS * ((size_t)ng + 1) + GROUP_LISTS; }

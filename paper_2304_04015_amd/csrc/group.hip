@@ -25,8 +25,9 @@ namespace srk {
 namespace {
 
 // Tile shapes of the group meet kernel (walks and member positions per tile)
-// for groups of up to 8 members, of up to 32, and of stratified walks (whose
-// 64-bit weighted sums take LDS from the tile).
+// for groups of up to 8 members and of up to 32; stratified walks keep 64-bit
+// weighted sums in LDS, which take room from the tile (and, beyond 8 members,
+// from the nodes per work unit).
 #ifndef SRK_GROUP_TILE_J
 #define SRK_GROUP_TILE_J 1280
 #endif
@@ -52,15 +53,18 @@ constexpr int GROUP_BLOCK = 1024;
 // GW: words of member lengths per entry the kernel instance holds (2: up to 8
 // members, 8: up to 32); WK: walks (0 plain, 1 stitched, 2 stratified).
 __host__ __device__ constexpr int group_tile_j(int GW, int WK) {
-    return WK == 2 ? SRK_GROUP_STRAT_TILE_J : GW <= 2 ? SRK_GROUP_TILE_J : SRK_GROUP32_TILE_J;
+    return GW > 2 ? SRK_GROUP32_TILE_J : WK == 2 ? SRK_GROUP_STRAT_TILE_J : SRK_GROUP_TILE_J;
 }
 __host__ __device__ constexpr int group_tile_nodes(int GW, int WK) {   // < 2^16
-    return WK == 2 ? SRK_GROUP_STRAT_TILE_NODES : GW <= 2 ? SRK_GROUP_TILE_NODES : SRK_GROUP32_TILE_NODES;
+    return GW > 2 ? SRK_GROUP32_TILE_NODES : WK == 2 ? SRK_GROUP_STRAT_TILE_NODES : SRK_GROUP_TILE_NODES;
 }
+// Nodes per work unit whose sums a stratified instance keeps in LDS.
+__host__ __device__ constexpr int group_strat_vb(int GW) { return GW > 2 ? GROUP_STRAT32_VB : MEET_VB; }
 static_assert(group_tile_nodes(2, 0) < 65536 && group_tile_nodes(2, 0) > 8 * MAX_CAP, "tile shape");
 static_assert(group_tile_nodes(8, 0) < 65536 && group_tile_nodes(8, 0) > 32 * MAX_CAP, "tile shape");
 static_assert(group_tile_nodes(2, 2) < 65536 && group_tile_nodes(2, 2) > 8 * MAX_CAP, "tile shape");
-static_assert(GROUP_MAX == 32 && GROUP_MAX_STRAT <= 8, "length words");
+static_assert(group_tile_nodes(8, 2) < 65536 && group_tile_nodes(8, 2) > 32 * MAX_CAP, "tile shape");
+static_assert(GROUP_MAX == 32, "length words");
 
 // The kernel instance's length words for groups of G members.
 __host__ __device__ inline int group_gw(int32_t G) { return G <= 8 ? 2 : 8; }
@@ -251,7 +255,8 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
     __shared__ uint32_t s_cnt[STRAT ? 1 : GM / 2 * MEET_VB];   // members 2i, 2i+1 in the low, high half
     // stratified: weighted sums per (member, node), the nodes' shuffle keys,
     // the class starts
-    __shared__ unsigned long long s_w[STRAT ? GM * MEET_VB : 1];
+    constexpr int VBW = group_strat_vb(GW);
+    __shared__ unsigned long long s_w[STRAT ? GM * VBW : 1];
     __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
     __shared__ uint32_t s_ccum[STRAT ? MAX_CAP + 2 : 1];
     __shared__ uint32_t s_vid[MEET_VB];
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         const int32_t vbase = (int32_t)chunk * vb;
         const uint32_t nv = (uint32_t)min(vb, d.n_active - vbase);
         if (STRAT)
-            for (uint32_t i = threadIdx.x; i < GM * MEET_VB; i += blockDim.x) s_w[i] = 0ull;
+            for (uint32_t i = threadIdx.x; i < GM * VBW; i += blockDim.x) s_w[i] = 0ull;
         else
             for (uint32_t i = threadIdx.x; i < GM / 2 * MEET_VB; i += blockDim.x) s_cnt[i] = 0u;
         for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                         for (uint32_t m = met; m; m &= m - 1u) {
                             const uint32_t q = (uint32_t)__builtin_ctz(m);
                             if (STRAT)
-                                atomicAdd(&s_w[q * MEET_VB + vl],
+                                atomicAdd(&s_w[q * VBW + vl],
                                           strat_weight(d.tab->a, d.scls[q][w.jw], w.cv));
                             else
                                 atomicAdd(&s_cnt[(q >> 1) * MEET_VB + vl], 1u << (16 * (q & 1u)));
@@ -551,7 +556,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
         for (uint32_t i = threadIdx.x; i < (uint32_t)G * nv; i += blockDim.x) {
             const uint32_t q = i / nv, vi = i - q * nv;
             if (STRAT) {
-                const unsigned long long c = s_w[q * MEET_VB + vi];
+                const unsigned long long c = s_w[q * VBW + vi];
                 if (c) atomicAdd(&d.wsum[q][s_vid[vi]], c);
             } else {
                 const uint32_t c = (s_cnt[(q >> 1) * MEET_VB + vi] >> (16 * (q & 1u))) & 0xffffu;
@@ -625,6 +630,10 @@ void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
     gd->G = G;
     gd->gw = (G + 3) / 4;
     gd->wk = d0.kind == K_GROUPED_STITCHED ? 1 : d0.kind == K_GROUPED_STRAT ? 2 : 0;
+    if (gd->wk == 2 && G > 8 && gd->vb > GROUP_STRAT32_VB) {   // the LDS sums' node limit
+        gd->vb = GROUP_STRAT32_VB;
+        gd->n_chunks = (gd->n_active + gd->vb - 1) / gd->vb;
+    }
     gd->ix = d0.ix;
     gd->tab = d0.tab;
     gd->sa = d0.sa;
@@ -672,6 +681,7 @@ int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t 
     launch_group_list<SRK_GROUP_SLOTS_STITCHED, 2, 1>(gs, 2, counters, st);
     launch_group_list<SRK_GROUP_SLOTS_STITCHED, 8, 1>(gs, 3, counters, st);
     launch_group_list<SRK_GROUP_SLOTS, 2, 2>(gs, 4, counters, st);
+    launch_group_list<SRK_GROUP_SLOTS, 8, 2>(gs, 5, counters, st);
     SRK_HIP(hipGetLastError());
     return SIMRANK_OK;
 }

@@ -274,10 +274,10 @@ def test_tile_and_unit_settings_keep_results(graphs):
 
 
 def test_stratified_groups_equal_lone(graphs):
-    """Stratified queries with one seed, z and phi form groups of up to 8 that
-    walk each (v, j) once (walk j of v: slot pi_v(j), its class, its steps);
-    every member's weighted sums, and both estimates, equal its lone run's,
-    bit for bit; queries with another z or seed stay in groups of their own."""
+    """Stratified queries with one seed, z and phi form groups that walk each
+    (v, j) once (walk j of v: slot pi_v(j), its class, its steps); every
+    member's weighted sums, and both estimates, equal its lone run's, bit for
+    bit; queries with another z or seed stay in groups of their own."""
     gs, Gs = graphs
     g, G = gs[2], Gs[2]
     rng = np.random.default_rng(17)
@@ -292,7 +292,7 @@ def test_stratified_groups_equal_lone(graphs):
            for s in srcs[:2]]
     qs += [S.make_query(srcs[0], c=0.6, seed=S1, walk_cap=12, R=1000, graph=2)]   # plain, alone
     plan = S.BatchPlan(Gs, qs)
-    assert plan.n_groups == 4          # 11 -> 6 + 5, 3, 2
+    assert plan.n_groups == 3          # 11, 3, 2
     plan.run()
     st = plan.wait()
     flat = S.BatchPlan(Gs, qs, groups=False)
@@ -315,19 +315,21 @@ def test_stratified_groups_equal_lone(graphs):
     flat.free()
 
 
-def test_stratified_group_full_size():
-    """Eight stratified queries with Algorithm 2's z and Algorithm 1's cap on a
-    2^16-node R-MAT graph (N = 14,825, phi = 43) and one seed: one group, each
-    member's weighted sums equal to its lone run's."""
+@pytest.mark.parametrize("nq", [8, 13])
+def test_stratified_group_full_size(nq):
+    """Stratified queries with Algorithm 2's z and Algorithm 1's cap on a
+    2^16-node R-MAT graph (N = 14,825, phi = 43) and one seed: one group of 8
+    and one of 13 (whose sums are kept for 64 nodes per unit), each member's
+    weighted sums equal to its lone run's."""
     g = inputs.rmat_in(16, 16 << 16, seed=72)
     G = S.load_csr(g)
-    srcs = [int(x) for x in inputs.sources_with_in_edges(g, 8, 75)]
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, 75)]
     qs = [S.make_stratified_query(s, c=0.6, eps=0.02, seed=0x2304040150000063) for s in srcs]
     plan = S.BatchPlan([G], qs)
     assert plan.n_groups == 1
     plan.run()
     st = plan.wait()
-    _say(f"stratified group of 8 at full size: {st.ms:.1f} ms, {st.moves} moves")
+    _say(f"stratified group of {nq} at full size: {st.ms:.1f} ms, {st.moves} moves")
     for i, q in enumerate(qs):
         assert np.array_equal(plan.read_stratified(i)[2],
                               S.simrank_single_source_stratified(G, q)[2]), i
