@@ -255,17 +255,18 @@ struct GroupDesc {
     uint32_t *meta;                      // [8]: entries, positions, tiles
 };
 
-struct GroupSet {
-    const GroupDesc *desc = nullptr;     // device [ng]
-    int32_t ng = 0;
-    int64_t units_bound[5] = {0, 0, 0, 0, 0};   // work units per kernel instance (group_list)
-    uint32_t *units = nullptr;           // device [group_units_words(ng)]
-};
 // Kernel instance of a group: plain walks with up to 8 members (0) or more
 // (1), stitched walks with up to 8 (2) or more (3), stratified walks with up
 // to 8 (4) or more (5).
 constexpr int GROUP_LISTS = 6;
 __host__ __device__ inline int group_list(int32_t G, int32_t wk) { return 2 * wk + (G > 8 ? 1 : 0); }
+
+struct GroupSet {
+    const GroupDesc *desc = nullptr;     // device [ng]
+    int32_t ng = 0;
+    int64_t units_bound[GROUP_LISTS] = {};       // work units per kernel instance (group_list)
+    uint32_t *units = nullptr;           // device [group_units_words(ng)]
+};
 // Unit offsets of a group set: one list of ng + 1 offsets per instance, then
 // one cursor per list.
 inline size_t group_units_words(int32_t ng) { return GROUP_LISTS * ((size_t)ng + 1) + GROUP_LISTS; }

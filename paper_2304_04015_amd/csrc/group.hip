@@ -672,6 +672,8 @@ size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base) {
     return at;
 }
 
+static_assert(GROUP_LISTS == 6, "one launch below per group kernel instance");
+
 int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st) {
     if (gs.ng <= 0) return SIMRANK_OK;
     k_group_compact<<<gs.ng, 1024, 0, st>>>(gs.desc);
