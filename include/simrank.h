@@ -306,8 +306,8 @@ int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
 /* simrank_batch_plan_create with flags (simrank_batch_plan_create and
  * simrank_batch pass SIMRANK_PLAN_GROUPS).  SIMRANK_PLAN_GROUPS: queries of one
  * mode on one graph with equal seed and walk parameters (plain and stitched:
- * c and walk cap; stratified: z, N and phi) are run in groups of up to 32 (8
- * for stratified queries) that share the walks from every node (Section 3's
+ * c and walk cap; stratified: z, N and phi) are run in groups of up to 32
+ * that share the walks from every node (Section 3's
  * walk (v, j), and Algorithm 1's walk in slot pi_v(j), depend on the seed and
  * those parameters only, not on the source): each walk (v, j) is taken once
  * and compared with walk j of every member's source.  Results are bit for bit
