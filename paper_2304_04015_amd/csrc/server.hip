@@ -276,6 +276,9 @@ static void server_loop(simrank_server *S) {
                     }
                 }
                 if (rc) {
+                    // copies of the staged descriptors may have been enqueued:
+                    // let them finish before the staging buffers are reused
+                    (void)hipStreamSynchronize(S->slots[idx[0]].stream);
                     S->grp.busy = false;
                     S->cv_done.notify_all();
                 } else {
