@@ -765,8 +765,10 @@ def bench_grouped(args):
 
 def bench_serving(args):
     """Serving workload: R-MAT n=2^22, avg degree 16, graph and stitched segment
-    index resident in HBM.  Requests: sources drawn proportionally to in-degree,
-    eps uniform in {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks.  First the
+    index resident in HBM (segment length 2^k chosen among k = 2, 3, 4 by the
+    segment-length tuner, then nodes per unit and walks per tile by the tuner).
+    Requests: sources drawn proportionally to in-degree, eps uniform in
+    {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks.  First the
     plain capacity (requests back to back, one at a time); then Poisson arrivals
     at 0.5, 0.8, 1.0 and 1.2 times that rate into the server (4 slots):
     achieved queries/s and p50 / p99 latency per level.  --group-max G: the
@@ -787,7 +789,6 @@ def bench_serving(args):
     g = inputs.workload_graph(cfg)
     print(f"# graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s", file=sys.stderr)
     G = S.load_csr(g)
-    S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=cfg["c"], seed=0x2304040150000023)
     rng = np.random.default_rng(31)
     deg = g.in_degree().astype(np.float64)
 
@@ -798,7 +799,13 @@ def bench_serving(args):
                             delta=cfg["delta"], seed=seed, walk_cap=cfg["L"],
                             mode=S.MODE_STITCHED)
 
-    S.simrank_tune(G, make(0))
+    # the index's segment length and the work partition, chosen by the tuners
+    # on one request of the workload (the index left built is the fastest one)
+    tq = make(0)
+    tq.eps = 0.02                     # the larger R of the mix
+    index_choice, index_ms = S.simrank_tune_index(G, tq, seg_log2=(2, 3, 4), kappa=1.0,
+                                                  c=cfg["c"], seed=0x2304040150000023)
+    tuning = S.simrank_tune_ex(G, tq)
     # plain capacity: one request at a time, back to back
     warm = [make(i) for i in range(2)]
     cap_q = [make(100 + i) for i in range(12)]
@@ -882,6 +889,8 @@ def bench_serving(args):
         "served_vs_plain": top["achieved_qps"] / capacity,
         "levels": levels,
         "server_counts": srv.counts(),
+        "index_tuner": {"seg_log2": [2, 3, 4], "meet_ms": index_ms, "choice": index_choice},
+        "tuning": tuning,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_meet<stitched> (fused walk + meet + count), requests one at a time",
