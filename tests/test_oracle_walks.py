@@ -3,6 +3,8 @@ distributions, meet-count special cases with exact laws, and the estimator
 against exact SimRank (Lemma 2, Hoeffding bound of Section 3)."""
 import math
 import os
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -30,6 +32,33 @@ def _kat_rows():
 def test_philox_known_answers(row):
     ctr, key, want = row
     assert list(O.philox(ctr, key)) == want
+
+
+ROCRAND_H = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+
+
+@pytest.mark.skipif(not (os.path.exists(ROCRAND_H) and shutil.which("g++")),
+                    reason="rocRAND headers or g++ not present")
+def test_philox_equals_rocrand(tmp_path):
+    """The oracle's Philox4x32-10 against rocRAND's (header-only, built for the
+    host): 4,096 random (counter, key) pairs plus the counter forms the walks
+    use (node, walk, step, domain) and all-zero / all-one words."""
+    src = os.path.join(os.path.dirname(__file__), "philox_rocrand_probe.cpp")
+    exe = str(tmp_path / "probe")
+    subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", src, "-o", exe],
+                   check=True, capture_output=True, timeout=120)
+    rng = np.random.default_rng(20230404)
+    rows = [list(r) for r in rng.integers(0, 2 ** 32, size=(4096, 6), dtype=np.uint64)]
+    k0, k1 = SEED & 0xFFFFFFFF, SEED >> 32
+    rows += [[v, j, t, d, k0, k1] for v in (0, 1, 1048575) for j in (0, 9501)
+             for t in (0, 1, 64) for d in range(6)]
+    rows += [[0] * 6, [0xFFFFFFFF] * 6, [0xFFFFFFFF] * 4 + [0, 0], [0] * 4 + [0xFFFFFFFF] * 2]
+    text = "".join(" ".join(f"{int(w):08x}" for w in r) + "\n" for r in rows)
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True, timeout=120)
+    got = [[int(w, 16) for w in line.split()] for line in out.stdout.splitlines()]
+    assert len(got) == len(rows)
+    for r, g in zip(rows, got):
+        assert list(O.philox([int(w) for w in r[:4]], [int(w) for w in r[4:]])) == g, r
 
 
 def test_philox_uniform_words():
