@@ -231,6 +231,11 @@ def main():
         slots_bytes = 8 * (info["m"] + info["n"] - info["n_active"])
         gi = S.simrank_roofline_gather(slots_bytes, 8, dependent=False)
         gd = S.simrank_roofline_gather(slots_bytes, 8, dependent=True)
+        # the same gathers from half the CUs, and from one wave per CU: the rate
+        # is the memory system's if these match the full grid's
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        gh = S.simrank_roofline_gather_grid(slots_bytes, 8, max(1, cus // 2), 1024)
+        gw = S.simrank_roofline_gather_grid(slots_bytes, 8, cus, 64)
         ph = S.simrank_roofline_philox()
         cp = S.simrank_roofline_copy(1 << 30)
         moves_per_s = moves_per_launch / avg_meet_s
@@ -239,6 +244,8 @@ def main():
             "footprint_bytes": slots_bytes,
             "random_gather_8B_per_s": gi["per_s"],
             "dependent_chain_gather_8B_per_s": gd["per_s"],
+            "random_gather_8B_per_s_half_cus": gh["per_s"],
+            "random_gather_8B_per_s_one_wave_per_cu": gw["per_s"],
             "philox_draws_per_s": ph["per_s"],
             "copy_bytes_per_s": cp["per_s"],
             "kernel_moves_per_s": moves_per_s,

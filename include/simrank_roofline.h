@@ -36,6 +36,15 @@ typedef struct simrank_rate {
 int simrank_roofline_gather(int64_t footprint_bytes, int32_t entry_bytes, int32_t dependent,
                             simrank_rate *out);
 
+/* Independent random gathers as above, in a grid of `blocks` blocks of
+ * `block_threads` threads (a multiple of 64 in [64, 1024]; blocks in
+ * [1, 2^20]) instead of the full-occupancy grid; each lane keeps 4 gathers in
+ * flight, and the launch makes at least as many gathers as the full grid's.
+ * With fewer CUs or fewer waves per CU than the full grid it shows whether
+ * the gather rate is set per CU or by the memory system as a whole. */
+int simrank_roofline_gather_grid(int64_t footprint_bytes, int32_t entry_bytes, int32_t blocks,
+                                 int32_t block_threads, simrank_rate *out);
+
 /* Philox4x32-10 draws per second (counter (lane, i, 0, 0), all four words used). */
 int simrank_roofline_philox(simrank_rate *out);
 

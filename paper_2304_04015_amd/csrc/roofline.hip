@@ -52,6 +52,31 @@ __global__ __launch_bounds__(RF_BLOCK) void k_rf_gather(const T *__restrict__ bu
     if (acc == 0x5eed5eed5eedull) sink[0] = acc;   // keeps the loads
 }
 
+// The same independent gathers in a grid of the caller's shape (blocks of up
+// to 1024 threads), to see whether the rate depends on the CUs or the waves
+// that issue them.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_rf_gather_grid(const T *__restrict__ buf, uint64_t n,
+                                                         int32_t iters, uint64_t *__restrict__ sink) {
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t acc = 0;
+    uint32_t h = mix32(gid * 0x27d4eb2du + 1u);
+    for (int32_t i = 0; i < iters; ++i) {
+        uint64_t idx[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            h = mix32(h + 0x9e3779b9u);
+            idx[u] = ((uint64_t)h * n) >> 32;
+        }
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = buf[idx[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (uint64_t)v[u];
+    }
+    if (acc == 0x5eed5eed5eedull) sink[0] = acc;
+}
+
 // Dependent chains: each lane's next index is a hash of the value it just
 // loaded and its own salt, so lanes never fall into shared paths (plain
 // next = buf[cur] chains merge and then share cache lines).
@@ -121,7 +146,8 @@ int timed(F launch, double *ms_out) {
 }
 
 template <typename T>
-int gather_impl(int64_t footprint, int32_t dependent, simrank_rate *out) {
+int gather_impl(int64_t footprint, int32_t dependent, simrank_rate *out, int32_t blocks = 0,
+                int32_t threads = 0) {
     const uint64_t n = (uint64_t)footprint / sizeof(T);
     T *buf = nullptr;
     uint64_t *sink = nullptr;
@@ -133,14 +159,20 @@ int gather_impl(int64_t footprint, int32_t dependent, simrank_rate *out) {
         return rc;
     }
     const int grid = full_grid();
-    const int64_t lanes = (int64_t)grid * RF_BLOCK;
     k_rf_fill<T><<<grid, RF_BLOCK>>>(buf, n);
-    const int32_t iters = dependent ? 512 : 256;
+    const bool shaped = blocks > 0;
+    const int64_t lanes = shaped ? (int64_t)blocks * threads : (int64_t)grid * RF_BLOCK;
+    // about as many gathers as the full-grid launch, whatever the shape
+    const int32_t iters = dependent ? 512
+                          : shaped  ? (int32_t)std::max<int64_t>(256, (int64_t)grid * RF_BLOCK * 256 / lanes)
+                                    : 256;
     double ms = 0;
     rc = timed(
         [&](hipStream_t st) {
             if (dependent)
                 k_rf_chase<T><<<grid, RF_BLOCK, 0, st>>>(buf, n, iters, sink);
+            else if (shaped)
+                k_rf_gather_grid<T><<<blocks, threads, 0, st>>>(buf, n, iters, sink);
             else
                 k_rf_gather<T><<<grid, RF_BLOCK, 0, st>>>(buf, n, iters, sink);
         },
@@ -169,6 +201,23 @@ extern "C" int simrank_roofline_gather(int64_t footprint_bytes, int32_t entry_by
         return fail(SIMRANK_EINVAL, "footprint above 2^32 entries");
     if (entry_bytes == 4) return gather_impl<uint32_t>(footprint_bytes, dependent, out);
     if (entry_bytes == 8) return gather_impl<uint64_t>(footprint_bytes, dependent, out);
+    return fail(SIMRANK_EINVAL, "entry_bytes must be 4 or 8");
+}
+
+extern "C" int simrank_roofline_gather_grid(int64_t footprint_bytes, int32_t entry_bytes,
+                                            int32_t blocks, int32_t block_threads,
+                                            simrank_rate *out) {
+    clear_error();
+    if (!out) return fail(SIMRANK_EINVAL, "out is NULL");
+    if (footprint_bytes < 4096) return fail(SIMRANK_EINVAL, "footprint below 4096 bytes");
+    if (footprint_bytes / entry_bytes >= ((int64_t)1 << 32))
+        return fail(SIMRANK_EINVAL, "footprint above 2^32 entries");
+    if (blocks < 1 || blocks > (1 << 20))
+        return fail(SIMRANK_EINVAL, "blocks must be in [1, 2^20]");
+    if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+        return fail(SIMRANK_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+    if (entry_bytes == 4) return gather_impl<uint32_t>(footprint_bytes, 0, out, blocks, block_threads);
+    if (entry_bytes == 8) return gather_impl<uint64_t>(footprint_bytes, 0, out, blocks, block_threads);
     return fail(SIMRANK_EINVAL, "entry_bytes must be 4 or 8");
 }
 

@@ -160,6 +160,7 @@ def lib() -> C.CDLL:
         "simrank_server_wait": [vp, C.c_uint64, dbl, vp, vp, P(simrank_request_info)],
         "simrank_server_destroy": [vp],
         "simrank_roofline_gather": [i64, i32, i32, P(simrank_rate)],
+        "simrank_roofline_gather_grid": [i64, i32, i32, i32, P(simrank_rate)],
         "simrank_roofline_philox": [P(simrank_rate)],
         "simrank_roofline_copy": [i64, P(simrank_rate)],
     }
@@ -444,6 +445,14 @@ def simrank_roofline_gather(footprint_bytes: int, entry_bytes: int = 8,
     r = simrank_rate()
     _check(lib().simrank_roofline_gather(int(footprint_bytes), entry_bytes, 1 if dependent else 0,
                                          C.byref(r)))
+    return r.asdict()
+
+
+def simrank_roofline_gather_grid(footprint_bytes: int, entry_bytes: int, blocks: int,
+                                 block_threads: int) -> dict:
+    r = simrank_rate()
+    _check(lib().simrank_roofline_gather_grid(int(footprint_bytes), entry_bytes, blocks,
+                                              block_threads, C.byref(r)))
     return r.asdict()
 
 

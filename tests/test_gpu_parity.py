@@ -194,3 +194,8 @@ def test_roofline_probes_run():
     assert S.simrank_roofline_copy(1 << 26)["per_s"] > 1e11
     with pytest.raises(S.SimRankError):
         S.simrank_roofline_gather(100, 8)
+    r = S.simrank_roofline_gather_grid(1 << 24, 8, 16, 64)
+    assert r["per_s"] > 1e8 and r["count"] >= 16 * 64 * 4 * 256
+    for blocks, threads in ((0, 64), (16, 32), (16, 96), (16, 2048)):
+        with pytest.raises(S.SimRankError):
+            S.simrank_roofline_gather_grid(1 << 24, 8, blocks, threads)
