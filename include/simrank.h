@@ -419,10 +419,13 @@ int simrank_server_submit(simrank_server *server, const simrank_query *q, uint64
 /* Waits up to timeout_s seconds (< 0: no limit) for the request, copies its
  * estimate (host double[n], may be NULL) and counts (host uint32[n], may be
  * NULL) and fills info (may be NULL); the ticket is then retired.  ESTATE on
- * timeout (the ticket stays valid). */
+ * timeout (the ticket stays valid); EINVAL for an unknown or retired ticket
+ * (of two waits on one ticket, one receives the result, the other EINVAL).
+ * Safe to call from several threads at once. */
 int simrank_server_wait(simrank_server *server, uint64_t ticket, double timeout_s,
                         double *out_host, uint32_t *counts_host, simrank_request_info *info);
-/* Finishes the queued and running requests, then frees the server. */
+/* Finishes the queued and running requests, then frees the server.  No other
+ * call on the server may run during or after it. */
 int simrank_server_destroy(simrank_server *server);
 
 /* ---------------------------------------------------------------- errors */

@@ -96,7 +96,7 @@ struct simrank_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
-    uint64_t n_done = 0, n_failed = 0, max_inflight = 0;
+    uint64_t n_done = 0, n_failed = 0;
     GroupRun grp;
     int32_t gmax = 0;          // largest group the server forms (its buffers' size)
     uint64_t n_groups = 0, n_grouped = 0;
@@ -171,13 +171,74 @@ static int launch_group(simrank_server *S, const std::vector<Request *> &rs,
     return SIMRANK_OK;
 }
 
+// Copies a finished slot's results and work counters into its request.
+static void collect_results(simrank_server *S, Slot &sl, Request *r) {
+    const size_t n = (size_t)S->g->n;
+    r->out.assign(sl.out_host, sl.out_host + n);
+    r->cnt.assign(sl.cnt_host, sl.cnt_host + n);
+    // a grouped request reports its share (1/G) of its group's work and the
+    // group's device time
+    unsigned long long c[8];
+    hipError_t e = hipMemcpy(c, sl.grouped ? S->grp.counters : sl.ws.counters, sizeof(c),
+                             hipMemcpyDeviceToHost);
+    if (sl.grouped)
+        for (unsigned long long &x : c) x /= (unsigned long long)sl.group_size;
+    float ms = 0.f, mms = 0.f;
+    if (sl.grouped) {
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, S->grp.ev0, S->grp.ev1);
+        mms = ms;
+    } else {
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, sl.ws.ev0, sl.ws.ev1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&mms, sl.ws.evm0, sl.ws.evm1);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        r->rc = SIMRANK_EDEVICE;
+        r->err = hipGetErrorString(e);
+        return;
+    }
+    r->st.pairs = (uint64_t)(S->g->n - 1) * (uint64_t)r->p.R;
+    r->st.pairs_walked = c[C_PAIRS];
+    r->st.moves = c[C_MOVES];
+    r->st.draws = c[C_DRAWS];
+    r->st.meets = c[C_MEETS];
+    r->st.tail_steps = c[C_TAIL];
+    r->st.source_moves = c[C_SRC_MOVES];
+    r->st.ms = ms;
+    r->st.meet_ms = mms;
+    r->st.R = r->p.R;
+    r->st.L = r->p.L;
+    r->st.T = r->p.T;
+    r->rc = SIMRANK_OK;
+}
+
+// Enqueues request r alone on slot sl: its kernels, the copies of its results
+// to the slot's pinned buffers, the slot's completion event.
+static int launch_single(simrank_server *S, Slot &sl, Request *r) {
+    const size_t n = (size_t)S->g->n;
+    int rc = enqueue_query(S->g, &r->q, r->p, r->mode, &sl.ws, sl.out_dev, sl.cnt_dev, sl.stream);
+    if (rc) return rc;
+    SRK_HIP(hipMemcpyAsync(sl.out_host, sl.out_dev, 8 * n, hipMemcpyDeviceToHost, sl.stream));
+    SRK_HIP(hipMemcpyAsync(sl.cnt_host, sl.cnt_dev, 4 * n, hipMemcpyDeviceToHost, sl.stream));
+    SRK_HIP(hipEventRecord(sl.done, sl.stream));
+    return SIMRANK_OK;
+}
+
+// The worker.  It alone touches the slots and the group's buffers, and it
+// alone writes a running request's results; the mutex guards the queue, the
+// requests' states and the counters.  A waiter reads a request's results only
+// after its state, set under the mutex, says it ended, so results are copied
+// and kernels enqueued without holding the mutex, and submitters and waiters
+// are never held up by device calls.
 static void server_loop(simrank_server *S) {
     (void)hipSetDevice(S->g->device);
-    std::unique_lock<std::mutex> lk(S->mu);
-    while (true) {
+    std::vector<Request *> ended, admitted;
+    std::vector<int32_t> idx;
+    for (;;) {
         bool progressed = false;
-        // completions
         uint64_t inflight = 0;
+        // completions
+        ended.clear();
         for (Slot &sl : S->slots) {
             if (!sl.req) continue;
             const hipError_t e = hipEventQuery(sl.done);
@@ -186,50 +247,17 @@ static void server_loop(simrank_server *S) {
                 continue;
             }
             Request *r = sl.req;
-            r->t_done = now_s();
             if (e == hipSuccess) {
-                const size_t n = (size_t)S->g->n;
-                r->out.assign(sl.out_host, sl.out_host + n);
-                r->cnt.assign(sl.cnt_host, sl.cnt_host + n);
-                // a grouped request reports its share (1/G) of its group's work
-                // and the group's device time
-                unsigned long long c[8];
-                hipError_t e2 = hipMemcpy(c, sl.grouped ? S->grp.counters : sl.ws.counters, sizeof(c),
-                                          hipMemcpyDeviceToHost);
-                if (sl.grouped)
-                    for (unsigned long long &x : c) x /= (unsigned long long)sl.group_size;
-                float ms = 0.f, mms = 0.f;
-                if (sl.grouped) {
-                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, S->grp.ev0, S->grp.ev1);
-                    mms = ms;
-                } else {
-                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, sl.ws.ev0, sl.ws.ev1);
-                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&mms, sl.ws.evm0, sl.ws.evm1);
-                }
-                r->st.pairs = (uint64_t)(S->g->n - 1) * (uint64_t)r->p.R;
-                r->st.pairs_walked = c[C_PAIRS];
-                r->st.moves = c[C_MOVES];
-                r->st.draws = c[C_DRAWS];
-                r->st.meets = c[C_MEETS];
-                r->st.tail_steps = c[C_TAIL];
-                r->st.source_moves = c[C_SRC_MOVES];
-                r->st.ms = ms;
-                r->st.meet_ms = mms;
-                r->st.R = r->p.R;
-                r->st.L = r->p.L;
-                r->st.T = r->p.T;
-                r->state = 2;
-                ++S->n_done;
+                collect_results(S, sl, r);
             } else {
                 (void)hipGetLastError();
-                r->state = 3;
                 r->rc = SIMRANK_EDEVICE;
                 r->err = hipGetErrorString(e);
-                ++S->n_failed;
             }
+            r->t_done = now_s();
+            ended.push_back(r);
             sl.req = nullptr;
             sl.grouped = false;
-            progressed = true;
         }
         // the group is done once none of its slots holds a request
         if (S->grp.busy) {
@@ -237,96 +265,114 @@ static void server_loop(simrank_server *S) {
             for (Slot &sl : S->slots) running |= sl.grouped;
             if (!running) S->grp.busy = false;
         }
-        if (progressed) S->cv_done.notify_all();
-        // Group admission (group_max >= 2): one launch in flight at a time.
-        // Once the device is free, the requests waiting with the same walks as
-        // the first one (up to group_max and the free slots) start as one
-        // group; a request with no partner starts alone.
+        idx.clear();
+        for (int32_t i = 0; i < (int32_t)S->slots.size(); ++i)
+            if (!S->slots[i].req) idx.push_back(i);
+        // admission: requests leave the queue under the mutex
+        admitted.clear();
+        bool group = false;
         const int32_t gmax = S->gmax;
-        if (gmax >= 2 && !S->queue.empty() && inflight == 0) {
-            std::vector<int32_t> idx;
-            for (int32_t i = 0; i < (int32_t)S->slots.size(); ++i)
-                if (!S->slots[i].req) idx.push_back(i);
-            std::vector<Request *> rs;
-            Request *head = S->queue.front();
-            for (Request *r : S->queue)
-                if ((int32_t)rs.size() < std::min<int32_t>(gmax, (int32_t)idx.size()) &&
-                    same_walks(head, r))
-                    rs.push_back(r);
-            if (rs.size() >= 2) {
-                idx.resize(rs.size());
-                const double t = now_s();
-                int rc = launch_group(S, rs, idx);
-                for (size_t i = 0; i < rs.size(); ++i) {
-                    Request *r = rs[i];
-                    S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
-                    r->t_start = t;
-                    if (rc) {
-                        r->state = 3;
-                        r->rc = rc;
-                        r->err = simrank_last_error();
-                        r->t_done = now_s();
-                        ++S->n_failed;
-                    } else {
-                        r->state = 1;
-                        S->slots[idx[i]].req = r;
-                        S->slots[idx[i]].grouped = true;
-                        S->slots[idx[i]].group_size = (int32_t)rs.size();
-                        ++inflight;
-                    }
-                }
-                if (rc) {
-                    // copies of the staged descriptors may have been enqueued:
-                    // let them finish before the staging buffers are reused
-                    (void)hipStreamSynchronize(S->slots[idx[0]].stream);
-                    S->grp.busy = false;
-                    S->cv_done.notify_all();
-                } else {
-                    ++S->n_groups;
-                    S->n_grouped += rs.size();
-                }
-                progressed = true;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (Request *r : ended) {
+                r->state = r->rc ? 3 : 2;
+                ++(r->rc ? S->n_failed : S->n_done);
             }
-        }
-        // admissions one at a time (with groups: one request alone, and only
-        // when nothing runs)
-        for (Slot &sl : S->slots) {
-            if (S->queue.empty()) break;
-            if (sl.req) continue;
-            if (gmax >= 2 && inflight > 0) break;
-            Request *r = S->queue.front();
-            S->queue.pop_front();
-            r->t_start = now_s();
-            int rc = enqueue_query(S->g, &r->q, r->p, r->mode, &sl.ws, sl.out_dev, sl.cnt_dev,
-                                   sl.stream);
-            const size_t n = (size_t)S->g->n;
-            hipError_t e = hipSuccess;
-            if (!rc) e = hipMemcpyAsync(sl.out_host, sl.out_dev, 8 * n, hipMemcpyDeviceToHost,
-                                        sl.stream);
-            if (!rc && e == hipSuccess)
-                e = hipMemcpyAsync(sl.cnt_host, sl.cnt_dev, 4 * n, hipMemcpyDeviceToHost, sl.stream);
-            if (!rc && e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
-            if (rc || e != hipSuccess) {
-                r->state = 3;
-                r->rc = rc ? rc : SIMRANK_EDEVICE;
-                r->err = rc ? simrank_last_error() : hipGetErrorString(e);
-                r->t_done = now_s();
-                ++S->n_failed;
+            if (!ended.empty()) {
+                progressed = true;
                 S->cv_done.notify_all();
+            }
+            // Groups (group_max >= 2): one launch in flight at a time.  Once
+            // the device is free, the requests waiting with the same walks as
+            // the first one (up to group_max and the free slots) start as one
+            // group; a request with no partner starts alone.
+            if (gmax >= 2 && !S->queue.empty() && inflight == 0) {
+                Request *head = S->queue.front();
+                const size_t cap = (size_t)std::min<int32_t>(gmax, (int32_t)idx.size());
+                for (Request *r : S->queue)
+                    if (admitted.size() < cap && same_walks(head, r)) admitted.push_back(r);
+                if (admitted.size() >= 2) {
+                    group = true;
+                    for (Request *r : admitted)
+                        S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+                } else {
+                    admitted.clear();
+                }
+            }
+            if (!group) {
+                // one request per free slot; with groups, one alone and only
+                // when nothing runs
+                const size_t cap = gmax >= 2 ? (inflight == 0 ? 1 : 0) : idx.size();
+                while (admitted.size() < std::min(cap, idx.size()) && !S->queue.empty()) {
+                    admitted.push_back(S->queue.front());
+                    S->queue.pop_front();
+                }
+            }
+            for (Request *r : admitted) r->state = 1;
+            if (admitted.empty()) {
+                if (S->stop && S->queue.empty() && inflight == 0) break;
+                if (!progressed) {
+                    if (inflight == 0 && S->queue.empty())
+                        S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+                    else
+                        S->cv_work.wait_for(lk, std::chrono::microseconds(50));
+                }
                 continue;
             }
-            r->state = 1;
-            sl.req = r;
-            ++inflight;
-            progressed = true;
         }
-        if (inflight > S->max_inflight) S->max_inflight = inflight;
-        if (S->stop && S->queue.empty() && inflight == 0) break;
-        if (!progressed) {
-            if (inflight == 0 && S->queue.empty())
-                S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-            else
-                S->cv_work.wait_for(lk, std::chrono::microseconds(50));
+        // enqueue on the device, without the mutex
+        const double t = now_s();
+        for (Request *r : admitted) r->t_start = t;
+        if (group) {
+            idx.resize(admitted.size());
+            const int rc = launch_group(S, admitted, idx);
+            for (size_t i = 0; i < admitted.size(); ++i) {
+                Request *r = admitted[i];
+                if (rc) {
+                    r->rc = rc;
+                    r->err = simrank_last_error();
+                    r->t_done = now_s();
+                } else {
+                    Slot &sl = S->slots[idx[i]];
+                    sl.req = r;
+                    sl.grouped = true;
+                    sl.group_size = (int32_t)admitted.size();
+                }
+            }
+            if (rc) {
+                // copies of the staged descriptors may have been enqueued:
+                // let them finish before the staging buffers are reused
+                (void)hipStreamSynchronize(S->slots[idx[0]].stream);
+                S->grp.busy = false;
+            }
+        } else {
+            for (size_t i = 0; i < admitted.size(); ++i) {
+                Request *r = admitted[i];
+                Slot &sl = S->slots[idx[i]];
+                const int rc = launch_single(S, sl, r);
+                if (rc) {
+                    r->rc = rc;
+                    r->err = simrank_last_error();
+                    r->t_done = now_s();
+                } else {
+                    sl.req = r;
+                }
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            bool failed = false;
+            for (Request *r : admitted)
+                if (r->rc) {
+                    r->state = 3;
+                    ++S->n_failed;
+                    failed = true;
+                }
+            if (group && !failed) {
+                ++S->n_groups;
+                S->n_grouped += admitted.size();
+            }
+            if (failed) S->cv_done.notify_all();
         }
     }
 }
@@ -494,15 +540,21 @@ extern "C" int simrank_server_wait(simrank_server *S, uint64_t ticket, double ti
     clear_error();
     if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->all.find(ticket);
-    if (it == S->all.end()) return fail(SIMRANK_EINVAL, "unknown ticket");
-    Request *r = it->second;
-    auto finished = [&] { return r->state >= 2; };
+    if (S->all.find(ticket) == S->all.end()) return fail(SIMRANK_EINVAL, "unknown ticket");
+    // looked up afresh at every wake-up: another wait on the same ticket may
+    // have retired it meanwhile
+    auto finished = [&] {
+        auto it = S->all.find(ticket);
+        return it == S->all.end() || it->second->state >= 2;
+    };
     if (timeout_s < 0) {
         S->cv_done.wait(lk, finished);
     } else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
         return fail(SIMRANK_ESTATE, "request not finished");
     }
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(SIMRANK_EINVAL, "ticket retired by another wait");
+    Request *r = it->second;
     S->all.erase(it);
     lk.unlock();
     int rc = SIMRANK_OK;

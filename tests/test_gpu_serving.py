@@ -157,3 +157,32 @@ def test_concurrent_submitters_with_groups(served):
     k = srv.counts()
     assert k["done"] == 32 and k["failed"] == 0
     srv.destroy()
+
+
+def test_two_waits_on_one_ticket(served):
+    """Two threads wait on the same ticket: one receives the result (equal to
+    the lone query's), the other an EINVAL for the retired ticket."""
+    import threading
+    g, G = served
+    q = _requests(g, 1, 5)[0]
+    lone = S.simrank_single_source_ex(G, q)[1]
+    srv = S.Server(G, max_slots=2, max_R=9502, max_L=64)
+    tk = srv.submit(q)
+    got, errs = [], []
+
+    def waiter():
+        try:
+            got.append(srv.wait(tk, want_out=False)[1])
+        except S.SimRankError as e:
+            errs.append(e.code)
+
+    threads = [threading.Thread(target=waiter) for _ in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not any(th.is_alive() for th in threads)
+    assert len(got) == 1 and len(errs) == 1
+    assert np.array_equal(got[0], lone)
+    assert errs[0] == S.SIMRANK_EINVAL
+    srv.destroy()
