@@ -36,6 +36,9 @@
  *     "device" pointers are HIP device memory on the graph's device.
  *   - A graph (and its index, once built) is immutable and may be queried from
  *     several threads at once; a workspace is used by one call at a time.
+ *     The calls that change a graph (simrank_build_index, the tuners,
+ *     simrank_set_tuning, simrank_free_graph) must not overlap other calls on
+ *     it.
  */
 #ifndef SIMRANK_H
 #define SIMRANK_H
@@ -265,7 +268,9 @@ int simrank_tuple_meets(const simrank_graph *g, const simrank_query *qs, int32_t
 /* Builds the stitched-walk index on the graph (replacing any earlier one):
  * per-node segment pools, one 2^k-step walk per slot keyed (y, i, t, 1),
  * successor picks keyed (y, i, 0, 3), and long walks of up to 64 steps by
- * pointer doubling.  Synchronous.  ENOMEM if it does not fit. */
+ * pointer doubling.  Synchronous.  ENOMEM if it does not fit.  Not to be
+ * called while other threads query g or a server serves it; a batch plan with
+ * stitched queries made before the rebuild refuses to run (ESTATE). */
 int simrank_build_index(simrank_graph *g, const simrank_index_params *p);
 int simrank_index_info(const simrank_graph *g, simrank_index_summary *out);
 
@@ -317,7 +322,10 @@ int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t ngraphs,
 int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_t ngraphs,
                                  const simrank_query *qs, int32_t nq, uint32_t flags,
                                  simrank_batch_plan **plan_out, int32_t *n_groups_out);
-/* Enqueues the plan's graph on `stream` (hipStream_t; NULL = default stream). */
+/* Enqueues the plan's graph on `stream` (hipStream_t; NULL = default stream).
+ * Every run writes the plan's own buffers: runs of one plan must not overlap,
+ * so enqueue the next run on the same stream or after simrank_batch_plan_wait.
+ * Plans are independent of each other. */
 int simrank_batch_plan_run(simrank_batch_plan *plan, void *stream);
 /* Waits for the last run; st (may be NULL) receives totals and its device time. */
 int simrank_batch_plan_wait(simrank_batch_plan *plan, simrank_stats *st);
@@ -356,7 +364,8 @@ int simrank_tune_ex(simrank_graph *g, const simrank_query *q, simrank_tuning *ou
 int simrank_tune(simrank_graph *g, const simrank_query *q, int32_t *vb_out);
 /* Fixes the tuning by hand: unit_nodes in [0, 256] (0: the library's default
  * by graph size), tile_walks 0 (each kind's largest tile) or in [2048, 8192]
- * (clamped to each kind's largest tile).  Results never depend on it. */
+ * (clamped to each kind's largest tile).  Results never depend on it.  Not to
+ * be called while other threads query g. */
 int simrank_set_tuning(simrank_graph *g, int32_t unit_nodes, int32_t tile_walks);
 /* Segment-length tuner for the stitched index (Section 4's segments of 2^k
  * steps joined by pointer doubling): for each seg_log2[i] (count in [1, 7],
@@ -364,7 +373,8 @@ int simrank_set_tuning(simrank_graph *g, int32_t unit_nodes, int32_t tile_walks)
  * query q's meet kernel (second run) into ms_each[i] (may be NULL), and leaves
  * the index of the fastest k built (*out, may be NULL).  Stitched walks depend
  * on k: a query's counts are those of the index it ran with.  EINVAL if q is
- * not stitched or its c differs from base->c. */
+ * not stitched or its c differs from base->c.  Rebuilds the index: the same
+ * rules as simrank_build_index apply. */
 int simrank_tune_index(simrank_graph *g, const simrank_query *q, const simrank_index_params *base,
                        const int32_t *seg_log2, int32_t count, simrank_tuning *out,
                        double *ms_each);

@@ -94,6 +94,7 @@ struct simrank_batch_plan {
     std::vector<GroupDesc> gdesc;
     std::vector<simrank_params> params;
     std::vector<const Graph *> graphs;
+    std::vector<uint64_t> index_gen;   // per stitched query: its graph's index generation
     char *arena = nullptr;
     QueryDesc *desc_dev = nullptr;
     uint32_t *units = nullptr;
@@ -242,6 +243,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
     };
     p->desc.resize(nq);
     p->graphs.resize(nq);
+    p->index_gen.assign(nq, ~0ull);
     for (int32_t i = 0; i < nq; ++i) {
         const simrank_graph *g = graphs[qs[i].graph];
         const simrank_params &pp = ps[i];
@@ -273,6 +275,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
             d.cnt = (uint32_t *)take(4 * (size_t)g->n);
         }
         p->graphs[i] = g;
+        if (modes[i] == SIMRANK_MODE_STITCHED) p->index_gen[i] = g->index_gen;
         set.max_R = std::max(set.max_R, pp.R);
         set.max_n = std::max(set.max_n, g->n);
         if (group_of[i] >= 0) {
@@ -346,6 +349,12 @@ extern "C" int simrank_batch_plan_create(simrank_graph *const *graphs, int32_t n
 extern "C" int simrank_batch_plan_run(simrank_batch_plan *p, void *stream) {
     clear_error();
     if (!p) return fail(SIMRANK_EINVAL, "plan is NULL");
+    // a stitched query's descriptor holds the addresses of the index it was
+    // planned with
+    for (int32_t i = 0; i < p->nq; ++i)
+        if (p->index_gen[i] != ~0ull && p->graphs[i]->index_gen != p->index_gen[i])
+            return fail(SIMRANK_ESTATE, "query " + std::to_string(i) +
+                                            ": its graph's index was rebuilt after the plan was made");
     SRK_HIP(hipSetDevice(p->device));
     hipStream_t st = (hipStream_t)stream;
     SRK_HIP(hipEventRecord(p->ev0, st));
@@ -415,12 +424,16 @@ extern "C" int simrank_batch_plan_read_stratified(simrank_batch_plan *p, int32_t
     return SIMRANK_OK;
 }
 
-extern "C" int simrank_batch_plan_free(simrank_batch_plan *p) {
-    clear_error();
-    if (!p) return SIMRANK_OK;
+// Waits for the plan's last run and frees it (leaves the error message alone).
+static void plan_finish(simrank_batch_plan *p) {
     (void)hipSetDevice(p->device);
     if (p->ran) (void)hipEventSynchronize(p->ev1);
     plan_release(p);
+}
+
+extern "C" int simrank_batch_plan_free(simrank_batch_plan *p) {
+    clear_error();
+    if (p) plan_finish(p);
     return SIMRANK_OK;
 }
 
@@ -469,8 +482,11 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
             rc = simrank_batch_plan_read(p, i - i0, outs ? outs[i] : nullptr,
                                          counts_opt && modes[i] != SIMRANK_MODE_STRATIFIED
                                              ? counts_opt[i] : nullptr);
-        if (st) (void)hipStreamDestroy(st);
-        simrank_batch_plan_free(p);
+        if (st) {
+            (void)hipStreamSynchronize(st);   // whatever was enqueued has ended
+            (void)hipStreamDestroy(st);
+        }
+        plan_finish(p);
         tot.pairs += s1.pairs;
         tot.pairs_walked += s1.pairs_walked;
         tot.moves += s1.moves;

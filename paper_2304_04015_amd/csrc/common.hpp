@@ -109,6 +109,7 @@ struct Graph {
     int32_t *active = nullptr;    // [n_active] nodes with deg >= 1, ascending
     hipStream_t stream = nullptr; // stream of the synchronous calls
     Index *index = nullptr;
+    uint64_t index_gen = 0;       // counts replacements of the index (plans check it)
     int32_t tuned_vb = 0;         // nodes per meet work unit chosen by simrank_tune (0: default)
     int32_t tuned_tile_j[N_KINDS] = {0, 0, 0};   // source walks per LDS tile, per kind (0: default)
     int64_t bytes = 0;

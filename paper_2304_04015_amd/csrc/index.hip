@@ -212,6 +212,7 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
     SRK_HIP(hipSetDevice(g->device));
     hipStream_t st = g->stream;
     SRK_HIP(hipStreamSynchronize(st));
+    ++g->index_gen;   // plans made with the old index must not run on the new one
     if (g->index) {
         index_free(g->index);
         delete g->index;

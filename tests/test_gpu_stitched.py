@@ -129,6 +129,32 @@ def test_full_segment_reduces_to_plain(small):
     assert np.array_equal(a, b)
 
 
+def test_plan_refuses_a_rebuilt_index(small):
+    """A plan's stitched queries hold the addresses of the index they were
+    planned with: after a rebuild the plan refuses to run (ESTATE), a plan
+    without stitched queries still runs, and a new plan gives the new index's
+    counts."""
+    g = small
+    G = S.load_csr(g)
+    S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=0.6, seed=ISEED)
+    qs = [S.make_query(s, seed=SEED, R=500, mode=S.MODE_STITCHED) for s in (3, 11)]
+    plain = S.BatchPlan([G], [S.make_query(3, seed=SEED, R=500)])
+    plan = S.BatchPlan([G], qs)
+    plan.run()
+    plan.wait()
+    S.simrank_build_index(G, seg_log2=2, kappa=1.0, c=0.6, seed=ISEED)
+    with pytest.raises(S.SimRankError) as e:
+        plan.run()
+    assert e.value.code == S.SIMRANK_ESTATE
+    plain.run()
+    plain.wait()
+    fresh = S.BatchPlan([G], qs)
+    fresh.run()
+    fresh.wait()
+    want = S.simrank_single_source_ex(G, qs[1])[1]
+    assert np.array_equal(fresh.read(1, want_out=False)[1], want)
+
+
 def test_stitched_requires_matching_index(small):
     G = S.load_csr(small)
     with pytest.raises(S.SimRankError) as e:
