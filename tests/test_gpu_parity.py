@@ -128,6 +128,29 @@ def test_edge_cases(case):
         assert cnt.sum() == st.R
 
 
+def test_hub_with_huge_in_degree():
+    """A hub with 300,000 in-neighbours (every other node points to it and it
+    points to every other node, plus one random edge per node): neighbour picks
+    over a row far longer than any tile or wave, and many meets at the hub at
+    step 1.  Counts equal the oracle's on a sample of nodes and the hub."""
+    n = 300_001
+    rng = np.random.default_rng(77)
+    leaves = np.arange(1, n)
+    extra = rng.integers(1, n, n - 1)
+    src = np.concatenate([leaves, np.zeros(n - 1, np.int64), extra])
+    dst = np.concatenate([np.zeros(n - 1, np.int64), leaves, leaves])
+    g = inputs.from_edges(n, src, dst)
+    assert g.in_degree()[0] == n - 1
+    G = S.load_csr(g)
+    q = S.make_query(1, c=0.6, seed=0xB0B, walk_cap=16, R=3000)
+    out, cnt, st = _counts(G, q)
+    vs = np.union1d(rng.choice(n, 3000, replace=False), [0, 1, n - 1]).astype(np.int32)
+    want = O.meet_counts_plain(g, 1, 0xB0B, 0.6, 16, 3000, vs=vs)
+    assert np.array_equal(cnt[vs], want)
+    assert cnt[1] == 3000 and cnt[2:].max() > 0
+    G.free()
+
+
 def test_repeat_is_deterministic_and_async_matches():
     import torch
     g = inputs.erdos_renyi_in(2000, 5.0, seed=8)
