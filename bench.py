@@ -267,6 +267,19 @@ def main():
         gpu_cnt = cnts[0].cpu().numpy().view(np.uint32)
         same = bool(np.array_equal(gpu_cnt[vs], cnt))
         pairs = vs.size * R
+        # the same oracle call on the same sample split over host threads (the
+        # call holds no shared state and releases the GIL), at most 16: the
+        # host share of one GPU
+        from concurrent.futures import ThreadPoolExecutor
+        nt = max(1, min(16, len(os.sched_getaffinity(0))))
+        parts = np.array_split(vs, nt)
+        t2 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=nt) as ex:
+            outs = list(ex.map(lambda p: O.meet_counts_plain(g, s0, cfg["walk_seed"], cfg["c"],
+                                                             cfg["L"], R, vs=p, with_work=True),
+                               parts))
+        dt_mt = time.perf_counter() - t2
+        same_mt = bool(np.array_equal(np.concatenate([o[0] for o in outs]), cnt))
         result["cpu_baseline"] = {
             "value": float(w.sum()) / dt,
             "unit": "walk-steps/s",
@@ -275,6 +288,13 @@ def main():
             "sample": f"source {s0}, {vs.size} random nodes with in-edges x R={R} pairs "
                       f"({pairs} pairs, {dt:.1f}s single-threaded); counts equal to the GPU's: {same}",
             "queries_per_s": pairs / dt / ((g.n - 1) * R),
+            "threads": {
+                "value": float(w.sum()) / dt_mt,
+                "cores": nt,
+                "sample": f"the same sample in {nt} node chunks, one thread each ({dt_mt:.1f}s); "
+                          f"counts equal: {same_mt}",
+                "queries_per_s": pairs / dt_mt / ((g.n - 1) * R),
+            },
         }
     print(json.dumps(result))
     for ws in wss:
