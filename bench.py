@@ -253,6 +253,13 @@ def main():
             "moves_vs_random_gather": moves_per_s / gi["per_s"],
             "draws_vs_philox": draws_per_s / ph["per_s"],
         }
+        if traffic:
+            # the kernel's 128-byte line requests per second (from the byte
+            # counters) against the same machine's rate for random gathers
+            # over the same footprint, each of which is one such request
+            req_per_s = traffic / 128.0 / avg_meet_s
+            result["measured_roofs"]["line_requests_per_s"] = req_per_s
+            result["measured_roofs"]["line_requests_vs_random_gather"] = req_per_s / gi["per_s"]
 
     if not args.no_cpu:
         import oracle as O
