@@ -186,7 +186,8 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
                                                         walk_kind(modes[m[0]])) *
                                ((g->n_active + vb - 1) / vb);
             // packed positions are addressed in 32 bits
-            if (RL >= (int64_t)0xffff0000) continue;            // these queries run alone
+            if (group_pos_words(Rmax, RL, ps[m[0]].L) >= (int64_t)0xffff0000)
+                continue;                                       // these queries run alone
             if (units + ub >= (int64_t)0x7fffffff) continue;
             units += ub;
             for (int32_t i : m) group_of[i] = (int32_t)kept.size();

@@ -245,13 +245,14 @@ struct GroupDesc {
     unsigned long long *wsum[GROUP_MAX]; // members' weighted sums [n] (stratified)
     const uint8_t *scls[GROUP_MAX];      // classes of the members' walks [R] (stratified)
     // Compacted walks: entry e is a walk index jj[e] for which at least one
-    // member's walk has a step; the members' positions of that walk lie back
-    // to back from pos[joff[e]], member q's length in byte q of the entry's
-    // gw words glen[e gw ...].
+    // member's walk has a step; from pos[joff[e]], one block per step t of its
+    // longest member walk: a word with bit q set for each member q whose walk
+    // j has a position at step t, then those positions in member order.
+    // Member q's length is byte q of the entry's gw words glen[e gw ...].
     uint32_t *jj;                        // [Rmax]
     uint32_t *joff;                      // [Rmax + 1]
     uint32_t *glen;                      // [Rmax][gw]
-    uint32_t *pos;                       // [sum of R_q x L]
+    uint32_t *pos;                       // [group_pos_words]
     uint32_t *tiles;                     // [group_max_tiles + 1]
     uint32_t *meta;                      // [8]: entries, positions, tiles
 };
@@ -272,6 +273,9 @@ struct GroupSet {
 // one cursor per list.
 inline size_t group_units_words(int32_t ng) { return GROUP_LISTS * ((size_t)ng + 1) + GROUP_LISTS; }
 
+// Words of a group's compacted walks, at most: every member position and one
+// member word per step of each entry.
+inline int64_t group_pos_words(int64_t Rmax, int64_t sum_RL, int32_t L) { return sum_RL + Rmax * L; }
 // Tiles of a group's compacted walks, at most.
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int32_t wk);
 // Fills a group's descriptor (all but its compaction buffers jj .. meta) from

@@ -40,6 +40,9 @@ namespace {
 #ifndef SRK_GROUP32_TILE_NODES
 #define SRK_GROUP32_TILE_NODES 28672
 #endif
+#ifndef SRK_GROUP32_STRAT_TILE_NODES
+#define SRK_GROUP32_STRAT_TILE_NODES 28672
+#endif
 #ifndef SRK_GROUP_STRAT_TILE_J
 #define SRK_GROUP_STRAT_TILE_J 1024
 #endif
@@ -56,14 +59,16 @@ __host__ __device__ constexpr int group_tile_j(int GW, int WK) {
     return GW > 2 ? SRK_GROUP32_TILE_J : WK == 2 ? SRK_GROUP_STRAT_TILE_J : SRK_GROUP_TILE_J;
 }
 __host__ __device__ constexpr int group_tile_nodes(int GW, int WK) {   // < 2^16
-    return GW > 2 ? SRK_GROUP32_TILE_NODES : WK == 2 ? SRK_GROUP_STRAT_TILE_NODES : SRK_GROUP_TILE_NODES;
+    return GW > 2 ? (WK == 2 ? SRK_GROUP32_STRAT_TILE_NODES : SRK_GROUP32_TILE_NODES)
+                  : WK == 2 ? SRK_GROUP_STRAT_TILE_NODES : SRK_GROUP_TILE_NODES;
 }
 // Nodes per work unit whose sums a stratified instance keeps in LDS.
 __host__ __device__ constexpr int group_strat_vb(int GW) { return GW > 2 ? GROUP_STRAT32_VB : MEET_VB; }
-static_assert(group_tile_nodes(2, 0) < 65536 && group_tile_nodes(2, 0) > 8 * MAX_CAP, "tile shape");
-static_assert(group_tile_nodes(8, 0) < 65536 && group_tile_nodes(8, 0) > 32 * MAX_CAP, "tile shape");
-static_assert(group_tile_nodes(2, 2) < 65536 && group_tile_nodes(2, 2) > 8 * MAX_CAP, "tile shape");
-static_assert(group_tile_nodes(8, 2) < 65536 && group_tile_nodes(8, 2) > 32 * MAX_CAP, "tile shape");
+// a tile holds at least one entry of the longest form ((G + 1) L words)
+static_assert(group_tile_nodes(2, 0) < 65536 && group_tile_nodes(2, 0) > 9 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(8, 0) < 65536 && group_tile_nodes(8, 0) > 33 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(2, 2) < 65536 && group_tile_nodes(2, 2) > 9 * MAX_CAP, "tile shape");
+static_assert(group_tile_nodes(8, 2) < 65536 && group_tile_nodes(8, 2) > 33 * MAX_CAP, "tile shape");
 static_assert(GROUP_MAX == 32, "length words");
 
 // The kernel instance's length words for groups of G members.
@@ -74,33 +79,42 @@ __device__ __forceinline__ uint32_t byte_of(uint32_t w, int q) { return (w >> (8
 
 // ------------------------------------------------------------ compaction
 // One block per group.  Keeps the walk indices j for which at least one
-// member's walk j has a step, packs the members' positions of walk j back to
-// back (member 0 first), and cuts the entries into tiles of at most TJ
-// entries and TN positions (a boundary wherever the entry index crosses a
-// multiple of TJ or the packed offset a multiple of NW = TN - G L; an entry
-// holds at most G L positions).  (TJ, TN) is the shape of the kernel instance
-// that runs the group.
+// member's walk j has a step and packs the members' positions of walk j step
+// by step: for each step t up to the longest member walk, the word of members
+// with a position at t, then their positions at t in member order.  Cuts the
+// entries into tiles of at most TJ entries and TN words (a boundary wherever
+// the entry index crosses a multiple of TJ or the packed offset a multiple of
+// NW = TN - (G + 1) L; an entry holds at most (G + 1) L words).  (TJ, TN) is
+// the shape of the kernel instance that runs the group.
 __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restrict__ gd) {
     const GroupDesc &d = gd[blockIdx.x];
     const int32_t Rmax = d.Rmax, L = d.L, G = d.G, gw = d.gw;
     const uint32_t TJ = (uint32_t)group_tile_j(group_gw(G), d.wk);
-    const uint32_t NW = (uint32_t)(group_tile_nodes(group_gw(G), d.wk) - G * L);
+    const uint32_t NW = (uint32_t)(group_tile_nodes(group_gw(G), d.wk) - (G + 1) * L);
     const int32_t per = (Rmax + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t j0 = min(Rmax, (int32_t)threadIdx.x * per), j1 = min(Rmax, j0 + per);
     uint32_t cnt = 0, nodes = 0;
     for (int32_t j = j0; j < j1; ++j) {
-        uint32_t tot = 0;
-        for (int32_t q = 0; q < G; ++q) tot += j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+        uint32_t tot = 0, mx = 0;
+        for (int32_t q = 0; q < G; ++q) {
+            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+            tot += l;
+            mx = max(mx, l);
+        }
         cnt += tot > 0;
-        nodes += tot;
+        nodes += tot + mx;
     }
     uint32_t E1, total;
     const uint32_t kb = block_excl_sum(cnt, &E1);
     const uint32_t nb = block_excl_sum(nodes, &total);
     uint32_t k = kb, off = nb;
     for (int32_t j = j0; j < j1; ++j) {
-        uint32_t tot = 0;
-        for (int32_t q = 0; q < G; ++q) tot += j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+        uint32_t tot = 0, mx = 0;
+        for (int32_t q = 0; q < G; ++q) {
+            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+            tot += l;
+            mx = max(mx, l);
+        }
         if (!tot) continue;
         d.jj[k] = (uint32_t)j;
         d.joff[k] = off;
@@ -113,11 +127,17 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
             }
             d.glen[(size_t)k * gw + wd] = w;
         }
-        for (int32_t q = 0; q < G; ++q) {
-            const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
-            const uint32_t *src = d.sw[q] + (size_t)j * L;
-            for (uint32_t t = 0; t < l; ++t) d.pos[off + t] = src[t];
-            off += l;
+        for (uint32_t t = 0; t < mx; ++t) {
+            const uint32_t at = off++;
+            uint32_t am = 0;
+            for (int32_t q = 0; q < G; ++q) {
+                const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
+                if (t < l) {
+                    am |= 1u << q;
+                    d.pos[off++] = d.sw[q][(size_t)j * L + t];
+                }
+            }
+            d.pos[at] = am;
         }
         ++k;
     }
@@ -186,7 +206,7 @@ struct GSlot {
     uint32_t pos;      // LDS offset of the entry's positions (16 bits) | its longest
                        // member walk << 16 | node index << 24
     uint32_t live;     // members still tested (bit q)
-    uint32_t len[GW];  // the entry's member lengths, one byte each
+    uint32_t b;        // LDS offset of the entry's block for the next step
     uint32_t t;        // steps taken
     uint32_t o, d;     // current node: slot offset in E and in-degree
     WalkDraws rng;
@@ -198,45 +218,35 @@ struct GSlot {
     uint32_t cv, jw;   // stratified: class (and last step) of walk (v, j), and j
 };
 
-// Compares the pair's position at step t with every member's position t.
-// Member q's positions lie at [B_q, B_q + len_q) within the tile, B_0 the
-// entry's offset and B_{q+1} = B_q + len_q; position t of member q is read only
-// if t <= len_q (else a harmless word).  A hit on any member sends the lane to
-// an exact pass; meets are rare, so the common step is reads and compares
-// only.  Returns the members still tested that meet at this step.
+// Compares the pair's position at step t with the members' positions at step
+// t.  The entry's block for step t is the word of members with a position at
+// t, then those positions in member order; the slot's offset b moves on to the
+// next step's block (every step is compared once, in order).  A hit sends the
+// lane to an exact pass that names the members; meets are rare, so the common
+// step reads and compares only the positions of the members still walking.
+// Returns the members still tested that meet at this step.
 template <int GW>
-__device__ __forceinline__ uint32_t group_compare(const GSlot<GW> &w, const uint32_t *s_nodes,
-                                                  int32_t gw) {
-    const uint32_t t1 = w.t - 1u;
-    uint32_t B = w.pos & 0xffffu;
+__device__ __forceinline__ uint32_t group_compare(GSlot<GW> &w, const uint32_t *s_nodes) {
+    const uint32_t B = w.b;
+    const uint32_t am = s_nodes[B];
+    const uint32_t c = (uint32_t)__popc(am);
+    w.b = B + 1u + c;
     bool hit = false;
-#pragma unroll
-    for (int wd = 0; wd < GW; ++wd) {
-        if (wd >= gw) break;   // the group's last length word (uniform)
-        const uint32_t lw = w.len[wd];
+    // four positions per round; a read past the block takes word B instead,
+    // and a false hit from it is cleared by the exact pass
+    for (uint32_t i = 0; i < c; i += 4u) {
         uint32_t pv[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t l = byte_of(lw, b);
-            pv[b] = s_nodes[t1 < l ? B + t1 : 0u];
-            B += l;
-        }
+        for (uint32_t u = 0; u < 4u; ++u) pv[u] = s_nodes[i + u < c ? B + 1u + i + u : B];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) hit |= pv[b] == w.o;
+        for (int u = 0; u < 4; ++u) hit |= pv[u] == w.o;
     }
     if (!hit) return 0u;
-    uint32_t met = 0;
-    B = w.pos & 0xffffu;
-#pragma unroll
-    for (int wd = 0; wd < GW; ++wd) {
-        if (wd >= gw) break;
-        const uint32_t lw = w.len[wd];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t l = byte_of(lw, b);
-            if (t1 < l && s_nodes[B + t1] == w.o) met |= 1u << (4 * wd + b);
-            B += l;
-        }
+    uint32_t met = 0, m = am;
+    for (uint32_t i = 0; i < c; ++i) {
+        const uint32_t q = (uint32_t)__builtin_ctz(m);
+        m &= m - 1u;
+        if (s_nodes[B + 1u + i] == w.o) met |= 1u << q;
     }
     return met & w.live;
 }
@@ -251,7 +261,6 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
     __shared__ uint32_t s_nodes[TN];
     __shared__ uint32_t s_j[TJ];
     __shared__ uint16_t s_off[TJ];
-    __shared__ uint32_t s_len[TJ * GW];
     __shared__ uint32_t s_cnt[STRAT ? 1 : GM / 2 * MEET_VB];   // members 2i, 2i+1 in the low, high half
     // stratified: weighted sums per (member, node), the nodes' shuffle keys,
     // the class starts
@@ -308,10 +317,6 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                     mx = max(mx, max(max(byte_of(lw, 0), byte_of(lw, 1)), max(byte_of(lw, 2), byte_of(lw, 3))));
                 }
                 s_maxl[i] = (uint8_t)mx;
-            }
-            for (uint32_t i = threadIdx.x; i < K * GW; i += blockDim.x) {
-                const uint32_t k = i / GW, wd = i - k * GW;
-                s_len[i] = (int32_t)wd < gw ? d.glen[(size_t)(k0 + k) * gw + wd] : 0u;
             }
             for (uint32_t i = threadIdx.x; i < ne - nb; i += blockDim.x) s_nodes[i] = d.pos[nb + i];
             if (STRAT)
@@ -402,8 +407,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                             }
                             w.pos = (uint32_t)s_off[k] | ((uint32_t)s_maxl[k] << 16) | (vl << 24);
                             w.live = live;
-#pragma unroll
-                            for (int wd = 0; wd < GW; ++wd) w.len[wd] = s_len[k * GW + wd];
+                            w.b = s_off[k];
                             w.t = 0;
                             w.o = row.x;
                             w.d = row.y;
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
                     ++w.tu;
                 }
                 if (go[qq] || tail_step) {
-                    const uint32_t met = group_compare(w, s_nodes, gw);
+                    const uint32_t met = group_compare(w, s_nodes);
                     if (met) {
                         const uint32_t vl = w.pos >> 24;
                         st_meets += (uint32_t)__popc(met);
@@ -614,8 +618,8 @@ void launch_group_list(const GroupSet &gs, int list, unsigned long long *counter
 
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int32_t wk) {
     const int GW = group_gw(G);
-    const int64_t NW = group_tile_nodes(GW, wk) - (int64_t)G * L;
-    return (int32_t)(2 + Rmax / group_tile_j(GW, wk) + sum_RL / NW);
+    const int64_t NW = group_tile_nodes(GW, wk) - (int64_t)(G + 1) * L;
+    return (int32_t)(2 + Rmax / group_tile_j(GW, wk) + group_pos_words(Rmax, sum_RL, L) / NW);
 }
 
 void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
@@ -666,7 +670,7 @@ size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base) {
     gd->jj = (uint32_t *)take(4 * (size_t)gd->Rmax);
     gd->joff = (uint32_t *)take(4 * ((size_t)gd->Rmax + 1));
     gd->glen = (uint32_t *)take(4 * (size_t)gd->Rmax * (size_t)gd->gw);
-    gd->pos = (uint32_t *)take(4 * (size_t)sum_RL);
+    gd->pos = (uint32_t *)take(4 * (size_t)group_pos_words(gd->Rmax, sum_RL, gd->L));
     gd->tiles = (uint32_t *)take(4 * ((size_t)mt + 1));
     gd->meta = (uint32_t *)take(32);
     return at;

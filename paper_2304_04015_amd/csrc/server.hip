@@ -448,7 +448,9 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
     }
     int32_t gmax = std::min<int32_t>(p->group_max, nslots);
     // a group's packed positions are addressed in 32 bits
-    while (gmax >= 2 && (int64_t)gmax * p->max_R * p->max_L >= (int64_t)0xffff0000) --gmax;
+    while (gmax >= 2 &&
+           group_pos_words(p->max_R, (int64_t)gmax * p->max_R * p->max_L, p->max_L) >= (int64_t)0xffff0000)
+        --gmax;
     S->gmax = gmax;
     if (!rc && gmax >= 2) {   // the group's own buffers
         GroupRun &gr = S->grp;
