@@ -127,14 +127,24 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
             }
             d.glen[(size_t)k * gw + wd] = w;
         }
+        // the lengths again from the words just written (registers), not
+        // from the members' length arrays at every step
+        uint32_t lw[GROUP_MAX / 4];
+#pragma unroll
+        for (int wd = 0; wd < GROUP_MAX / 4; ++wd)
+            lw[wd] = wd < gw ? d.glen[(size_t)k * gw + wd] : 0u;
         for (uint32_t t = 0; t < mx; ++t) {
             const uint32_t at = off++;
             uint32_t am = 0;
-            for (int32_t q = 0; q < G; ++q) {
-                const uint32_t l = j < d.R[q] ? (uint32_t)d.slen[q][j] : 0u;
-                if (t < l) {
-                    am |= 1u << q;
-                    d.pos[off++] = d.sw[q][(size_t)j * L + t];
+#pragma unroll
+            for (int wd = 0; wd < GROUP_MAX / 4; ++wd) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int q = 4 * wd + b;
+                    if (t < byte_of(lw[wd], b)) {
+                        am |= 1u << q;
+                        d.pos[off++] = d.sw[q][(size_t)j * L + t];
+                    }
                 }
             }
             d.pos[at] = am;
