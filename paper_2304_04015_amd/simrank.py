@@ -197,10 +197,24 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
-def _dev_ptr(t) -> int | None:
+def _dev_ptr(t, n: int, itemsize: int, name: str) -> int | None:
+    """Device address of buffer t for n elements of itemsize bytes.  A tensor
+    must live on a GPU, be contiguous, have that element size and hold at
+    least n elements (the kernels write n); a raw integer address is passed
+    through as the caller's promise."""
     if t is None:
         return None
     if hasattr(t, "data_ptr"):
+        dev = getattr(t, "device", None)
+        if dev is not None and getattr(dev, "type", "cuda") != "cuda":
+            raise SimRankError(SIMRANK_EINVAL, f"{name}: not a device tensor ({dev})")
+        if hasattr(t, "is_contiguous") and not t.is_contiguous():
+            raise SimRankError(SIMRANK_EINVAL, f"{name}: not contiguous")
+        if t.element_size() != itemsize:
+            raise SimRankError(SIMRANK_EINVAL, f"{name}: element size {t.element_size()}, "
+                                               f"expected {itemsize}")
+        if t.numel() < n:
+            raise SimRankError(SIMRANK_EINVAL, f"{name}: {t.numel()} elements, needs {n}")
         return int(t.data_ptr())
     return int(t)
 
@@ -309,8 +323,9 @@ def simrank_single_source_async(g: Graph, q: simrank_query, ws: Workspace, out_d
     sp = None
     if stream is not None:
         sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
-    _check(lib().simrank_single_source_async(g.handle, C.byref(q), ws.handle, _dev_ptr(out_dev),
-                                             _dev_ptr(counts_dev), sp))
+    _check(lib().simrank_single_source_async(g.handle, C.byref(q), ws.handle,
+                                             _dev_ptr(out_dev, g.n, 8, "out_dev"),
+                                             _dev_ptr(counts_dev, g.n, 4, "counts_dev"), sp))
 
 
 def simrank_workspace_stats(ws: Workspace) -> simrank_stats:
@@ -363,8 +378,10 @@ def simrank_stratified_async(g: Graph, q: simrank_query, ws: Workspace, out_dev,
     sp = None
     if stream is not None:
         sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
-    _check(lib().simrank_stratified_async(g.handle, C.byref(q), ws.handle, _dev_ptr(out_dev),
-                                          _dev_ptr(out_n_dev), _dev_ptr(wsum_dev), sp))
+    _check(lib().simrank_stratified_async(g.handle, C.byref(q), ws.handle,
+                                          _dev_ptr(out_dev, g.n, 8, "out_dev"),
+                                          _dev_ptr(out_n_dev, g.n, 8, "out_n_dev"),
+                                          _dev_ptr(wsum_dev, g.n, 8, "wsum_dev"), sp))
 
 
 def simrank_stratified_walks(g: Graph, q: simrank_query, vs, js, with_paths: bool = True):

@@ -168,3 +168,35 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                        cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))), timeout=300)
     assert "raised" in r.stdout and "absent.so" in r.stdout, (r.stdout, r.stderr)
+
+
+def test_device_buffers_checked_before_the_call():
+    """The binding refuses device buffers the kernels would overrun or misread:
+    host tensors, strided views, wrong element sizes, fewer than n elements."""
+    import torch
+
+    class Dev:                      # a stand-in for a device tensor
+        def __init__(self, n, itemsize, contiguous=True):
+            self.device = type("D", (), {"type": "cuda"})()
+            self._n, self._s, self._c = n, itemsize, contiguous
+
+        def is_contiguous(self):
+            return self._c
+
+        def element_size(self):
+            return self._s
+
+        def numel(self):
+            return self._n
+
+        def data_ptr(self):
+            return 0x1000
+
+    assert S._dev_ptr(Dev(10, 4), 10, 4, "x") == 0x1000
+    assert S._dev_ptr(None, 10, 4, "x") is None
+    assert S._dev_ptr(0x2000, 10, 4, "x") == 0x2000
+    for bad in (Dev(9, 4), Dev(10, 8), Dev(10, 4, contiguous=False),
+                torch.zeros(10, dtype=torch.int32)):
+        with pytest.raises(S.SimRankError) as e:
+            S._dev_ptr(bad, 10, 4, "x")
+        assert e.value.code == S.SIMRANK_EINVAL
