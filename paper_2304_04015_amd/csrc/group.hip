@@ -53,8 +53,9 @@ namespace {
 #define SRK_GROUP_SLOTS 2
 #endif
 constexpr int GROUP_BLOCK = 1024;
-// GW: words of member lengths per entry the kernel instance holds (2: up to 8
-// members, 8: up to 32); WK: walks (0 plain, 1 stitched, 2 stratified).
+// GW: the instance's member capacity in words of four (2: up to 8 members, 8:
+// up to 32; it sizes the per-member LDS counters and picks the tile shape);
+// WK: walks (0 plain, 1 stitched, 2 stratified).
 __host__ __device__ constexpr int group_tile_j(int GW, int WK) {
     return GW > 2 ? SRK_GROUP32_TILE_J : WK == 2 ? SRK_GROUP_STRAT_TILE_J : SRK_GROUP_TILE_J;
 }
@@ -71,7 +72,7 @@ static_assert(group_tile_nodes(2, 2) < 65536 && group_tile_nodes(2, 2) > 9 * MAX
 static_assert(group_tile_nodes(8, 2) < 65536 && group_tile_nodes(8, 2) > 33 * MAX_CAP, "tile shape");
 static_assert(GROUP_MAX == 32, "length words");
 
-// The kernel instance's length words for groups of G members.
+// The kernel instance (its GW) for groups of G members.
 __host__ __device__ inline int group_gw(int32_t G) { return G <= 8 ? 2 : 8; }
 
 // Length of member q in an entry's length words (byte q).
@@ -199,11 +200,12 @@ __global__ __launch_bounds__(1024) void k_group_units(const GroupDesc *__restric
 // persistent blocks take units (group, tile of its compacted walks, chunk of
 // vb nodes with in-edges) from a device cursor, stage the tile's positions in
 // LDS, and hand the pairs (v, entry) of a unit, v-major, to the waves in chunks
-// of 64.  A lane keeps NS pairs in flight; a pair carries the entry's member
-// lengths and the mask of members still tested.  A step reads the members'
-// positions of that step, then compares.  Counts go to 16-bit LDS counters per
-// (member, node) (a unit holds at most TJ < 2^16 walks), flushed to the
-// members' counts once per unit.  WK = 1 (stitched): the walk's first 2^k
+// of 64.  A lane keeps NS pairs in flight; a pair carries the LDS offset of
+// its entry's block for the next step and the mask of members still tested.
+// A step reads the positions of the members present at that step, then
+// compares.  Counts go to 16-bit LDS counters per (member, node) (a unit
+// holds at most TJ < 2^16 walks), flushed to the members' counts once per
+// unit.  WK = 1 (stitched): the walk's first 2^k
 // steps are its own draws, the rest is read from the segment index, one load
 // per iteration, as in the single-query kernel.  WK = 2 (stratified): walk j
 // of v is the fixed-length walk of slot pi_v(j) (the shuffle and the class
