@@ -448,8 +448,13 @@ def bench_tuples(args):
         fel = time.perf_counter() - t1
         res[k] = dict(seconds=el, device_ms=st.ms, tuples=st.moves, meets=st.meets,
                       queries_per_s=k / el, fused_queries_per_s=k / fel,
-                      tuples_per_s=st.moves / (st.ms / 1e3), equal_to_fused=same)
+                      tuples_per_s=st.moves / (st.ms / 1e3), equal_to_fused=same,
+                      sort_ms=st.meet_ms, sort_bytes=st.draws)
     r8 = res[8]
+    # the radix sort dominates the call: its algorithmic bytes (8 per key a
+    # histogram pass reads, 24 per tuple a scatter pass reads and writes) over
+    # its passes' device time (HIP events on the call's stream)
+    sort_gbs = r8["sort_bytes"] / (r8["sort_ms"] / 1e3) / 1e9
     result = {
         "metric": METRIC,
         "value": r8["tuples_per_s"],
@@ -470,6 +475,15 @@ def bench_tuples(args):
         },
         "k8": res[8],
         "k32": res[32],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "radix sort passes (k_rs_hist + k_rs_scatter), 8 sources",
+            "achieved": sort_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": sort_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+        },
     }
     print(json.dumps(result))
     G.free()

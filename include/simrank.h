@@ -257,7 +257,9 @@ int simrank_stratified_walks(const simrank_graph *g, const simrank_query *q, con
  * units of 2^-40, sums[q][s_q] = 0 (equal to simrank_single_source_stratified's
  * wsum).  Nodes are processed in chunks whose tuples fit a 2^28-entry buffer.
  * st_opt: moves = steps of the nodes' walks (= tuples), meets = meeting pairs,
- * ms = device time.  EINVAL for stitched queries, k outside [1, 32], queries
+ * ms = device time; for this call meet_ms is the device time of the radix
+ * sort's passes (summed over the chunks) and draws the bytes they move (8 per
+ * key a histogram pass reads, 24 per tuple a scatter pass reads and writes).  EINVAL for stitched queries, k outside [1, 32], queries
  * that differ in anything but s, or a source out of range.
  */
 int simrank_tuple_meets(const simrank_graph *g, const simrank_query *qs, int32_t k,

@@ -391,16 +391,18 @@ extern "C" int simrank_tuple_meets(const simrank_graph *g, const simrank_query *
     const int32_t N = p0.R, L = p0.L;
     SRK_HIP(hipSetDevice(g->device));
     hipStream_t st = g->stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    SRK_HIP(hipEventCreate(&e0));
-    SRK_HIP(hipEventCreate(&e1));
+    // e0 / e1 around the call, s0 / s1 around each chunk's radix sort
     struct EvGuard {
-        hipEvent_t a, b;
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
         ~EvGuard() {
-            if (a) (void)hipEventDestroy(a);
-            if (b) (void)hipEventDestroy(b);
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
         }
-    } evg{e0, e1};
+    } evg;
+    for (hipEvent_t &x : evg.e) SRK_HIP(hipEventCreate(&x));
+    hipEvent_t e0 = evg.e[0], e1 = evg.e[1], s0 = evg.e[2], s1 = evg.e[3];
+    double sort_ms = 0.0;
+    uint64_t sort_bytes = 0;
     SRK_HIP(hipEventRecord(e0, st));
 
     const size_t n = (size_t)g->n;
@@ -521,7 +523,9 @@ extern "C" int simrank_tuple_meets(const simrank_graph *g, const simrank_query *
             uint64_t *kin = (uint64_t *)k0.p, *kout = (uint64_t *)k1.p;
             uint32_t *vin = (uint32_t *)v0.p, *vout = (uint32_t *)v1.p;
             const int64_t tiles = (count + RS_TILE - 1) / RS_TILE;
-            for (int shift = 0; shift < key_bits; shift += 8) {
+            SRK_HIP(hipEventRecord(s0, st));
+            int passes = 0;
+            for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
                 k_rs_hist<<<(unsigned)tiles, RS_BLOCK, 0, st>>>(kin, count, shift, (uint32_t *)hist.p,
                                                                tiles);
                 if ((rc = scan_exclusive_u32_to_i64((const uint32_t *)hist.p, 256 * tiles,
@@ -532,7 +536,11 @@ extern "C" int simrank_tuple_meets(const simrank_graph *g, const simrank_query *
                 std::swap(kin, kout);
                 std::swap(vin, vout);
             }
+            SRK_HIP(hipEventRecord(s1, st));
             SRK_HIP(hipGetLastError());
+            // a histogram pass reads each 8-byte key; a scatter pass reads and
+            // writes each key and its 4-byte payload
+            sort_bytes += (uint64_t)passes * (uint64_t)count * (8u + 24u);
             // PREDECESSOR: running maximum of (position + 1) over the sources' tuples
             k_tw_last_init<<<grid_for(count, 256), 256, 0, st>>>(kin, count, (uint32_t *)last.p);
             if ((rc = scan_inclusive_max_u32((uint32_t *)last.p, count, st))) return rc;
@@ -552,6 +560,9 @@ extern "C" int simrank_tuple_meets(const simrank_graph *g, const simrank_query *
                                        hipMemcpyDeviceToHost, st));
                 SRK_HIP(hipStreamSynchronize(st));
                 src_count = count - first_src;
+                float sms = 0.f;
+                SRK_HIP(hipEventElapsedTime(&sms, s0, s1));
+                sort_ms += sms;
             }
             total_moves += (uint64_t)(count - src_count);
         }
@@ -569,7 +580,8 @@ extern "C" int simrank_tuple_meets(const simrank_graph *g, const simrank_query *
         *st_opt = simrank_stats{};
         st_opt->pairs = (uint64_t)(g->n - 1) * (uint64_t)N * (uint64_t)k;
         st_opt->moves = total_moves;
-        st_opt->draws = 0;
+        st_opt->draws = sort_bytes;        // bytes the sort passes move (see simrank.h)
+        st_opt->meet_ms = sort_ms;
         st_opt->meets = c[C_MEETS];
         st_opt->ms = ms;
         st_opt->R = N;

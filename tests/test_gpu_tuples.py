@@ -64,8 +64,12 @@ def test_many_chunks_and_sources():
     srcs = _sources(g, 32, 3)
     qs = [S.make_query(s, c=0.6, seed=SEED, walk_cap=64, R=3000) for s in srcs]
     sums, st = S.simrank_tuple_meets(G, qs)
-    _say(f"tuple form 2^17: {st.moves} tuples, {st.meets} meets, {st.ms:.1f} ms")
+    _say(f"tuple form 2^17: {st.moves} tuples, {st.meets} meets, {st.ms:.1f} ms, "
+         f"sort {st.meet_ms:.1f} ms / {st.draws} bytes")
     assert st.moves > (1 << 28)          # more tuples than one chunk holds
+    # the sort's time and bytes: every tuple (sources' copies included) passes
+    # through at least one histogram and one scatter pass
+    assert 0 < st.meet_ms < st.ms and st.draws >= 32 * st.moves
     for q in (0, 13, 31):
         fused = S.simrank_single_source_ex(G, qs[q])[1]
         assert np.array_equal(sums[q], fused.astype(np.uint64)), q
