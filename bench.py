@@ -712,6 +712,17 @@ def bench_batching(args):
         "batch": {"moves": st.moves, "draws": st.draws, "device_ms": st.ms, "pairs": st.pairs},
         "per_graph": per_graph,
     }
+    # the meet kernels dominate the plan: 8 algorithmic bytes per move (the
+    # gathered slot) over the plan's device time (HIP events around the
+    # captured graph on its stream)
+    achieved = BYTES_PER_MOVE * (st.moves + st.tail_steps) / (st.ms / 1e3) / 1e9
+    result["roofline"] = {
+        "bound": "hbm",
+        "kernel": ("k_meet_group and k_meet over the plan's queries" if plan.n_groups
+                   else "k_meet over all the plan's queries, one launch") + " (whole plan's device time)",
+        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+    }
     print(json.dumps(result))
     plan.free()
     for ws in wss:
