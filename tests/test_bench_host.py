@@ -1,0 +1,32 @@
+"""Host logic of the benchmark (no GPU): the byte counters are reported only
+while they belong to the current meet-kernel sources, and more than one GPU
+is refused before anything touches a device."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_traffic_only_for_the_current_kernel_sources(tmp_path):
+    fp = bench.kernel_fingerprint()
+    assert len(fp) == 16 and int(fp, 16) >= 0
+    good = tmp_path / "t.json"
+    good.write_text(json.dumps({"source_sha256_16": fp, "bytes_per_launch": 123.0}))
+    assert bench.measured_traffic(str(good)) == 123.0
+    stale = tmp_path / "s.json"
+    stale.write_text(json.dumps({"source_sha256_16": "0" * 16, "bytes_per_launch": 123.0}))
+    assert bench.measured_traffic(str(stale)) is None
+    broken = tmp_path / "b.json"
+    broken.write_text("{")
+    assert bench.measured_traffic(str(broken)) is None
+    assert bench.measured_traffic(str(tmp_path / "missing.json")) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
