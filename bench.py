@@ -117,7 +117,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards over nodes v with no exchange; see the design notes)",
+              "(the path would shard over nodes v with no exchange: each GPU regenerates "
+              "the source walks and counts its own slice of the nodes)",
               file=sys.stderr)
         sys.exit(2)
 

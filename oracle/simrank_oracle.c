@@ -22,7 +22,7 @@
  *   4 = step of a fixed-length walk of the length-stratified estimator,
  *   5 = round keys of a node's walk shuffle.
  *
- * Readings of the paper that the oracle fixes (each listed in the design notes):
+ * Readings of the paper that the oracle fixes:
  *  - a walk at step t first draws; it stops if x0 >= T, T = floor(sqrt(c)*2^32)
  *    (Section 2.2: stop with probability 1 - sqrt(c)); otherwise it stops at a
  *    node without in-neighbours (the paper is silent; a zero column of W), else
