@@ -11,10 +11,16 @@ with the graph already resident in HBM.
 
 Prints one JSON line.  `value` is walk steps per second (moves along in-edges
 made by the meet kernel, plus the source walks' steps); `queries_per_s` is
-single-source queries per second.  `roofline` reports the fused walk + meet
-kernel: algorithmic bytes (8 bytes per move: the gathered edge slot) over its
-launch time measured with HIP events on the stream it runs on.  `cpu_baseline`
-times the CPU oracle on a bounded sample of the same workload.
+single-source queries per second with the estimates left in device memory,
+`queries_per_s_with_d2h` the same with each estimate copied to pinned host
+memory.  `batched` runs the same 8 queries as one captured batch plan (a seed
+per query, and the line's shared seed as one query group) against the plain
+one-at-a-time rate.  `roofline` reports the fused walk + meet kernel:
+algorithmic bytes (12 per move: an 8-byte row read and a 4-byte edge read)
+over its launch time measured with HIP events on the stream it runs on,
+against the published HBM peak; the kernel's real limit, the rate of random
+128-byte line requests the memory system serves, is stated beside it.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -29,7 +35,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s + single-source queries/s at eps=0.02; batched vs plain, % roofline"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_MOVE = 8
+# Algorithmic bytes per walk step: reading the current node's row (offset and
+# degree, 8 bytes) and one edge of it (4 bytes).  The library's gather layout
+# reads the two as one 8-byte slot per step; that figure is reported beside.
+BYTES_PER_MOVE = 12
+BYTES_PER_MOVE_GATHERED = 8
+# Host threads for the threaded CPU baseline: the host share of one GPU.
+CPU_THREADS_CAP = 16
+
+
+def roofline(kernel: str, moves: float, seconds: float, traffic=None, traffic_source=None,
+             bound: str = "random-gather") -> dict:
+    """The roofline object of a walk kernel: algorithmic bytes (BYTES_PER_MOVE
+    per move) per second against the published HBM peak."""
+    achieved = BYTES_PER_MOVE * moves / seconds / 1e9 if seconds > 0 else 0.0
+    r = {
+        "bound": bound,
+        "kernel": kernel,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "bytes_per_move": BYTES_PER_MOVE,
+        "achieved_8B_gather_layout": BYTES_PER_MOVE_GATHERED * moves / seconds / 1e9
+        if seconds > 0 else 0.0,
+    }
+    if traffic_source:
+        r["traffic_source"] = traffic_source
+    return r
 
 
 def kernel_fingerprint() -> str:
@@ -159,11 +193,18 @@ def main():
     wss = [S.simrank_workspace_create(G, R, cfg["L"]) for _ in queries]
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in queries]
     cnts = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in queries]
+    hosts = [torch.empty(g.n, dtype=torch.float64, pin_memory=True) for _ in queries]
 
-    def step():
-        for q, ws, o, c in zip(queries, wss, outs, cnts):
+    def step(d2h: bool = False):
+        for q, ws, o, c, h in zip(queries, wss, outs, cnts, hosts):
             S.simrank_single_source_async(G, q, ws, o, c, stream)
-        return [S.simrank_workspace_stats(ws) for ws in wss]
+            if d2h:
+                with torch.cuda.stream(stream):
+                    h.copy_(o, non_blocking=True)
+        sts = [S.simrank_workspace_stats(ws) for ws in wss]
+        if d2h:
+            stream.synchronize()
+        return sts
 
     for _ in range(max(args.warmup, 1)):
         ref = step()
@@ -181,13 +222,25 @@ def main():
         query_ms += [st.ms for st in sts]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    ref_counts = [c.cpu().numpy().view(np.uint32).copy() for c in cnts]
+
+    # the same queries with each estimate copied to pinned host memory (the
+    # synchronous call's PCIe leg); not part of `value`
+    d2h_steps = max(2, args.steps // 4)
+    step(d2h=True)
+    torch.cuda.synchronize()
+    t_d = time.perf_counter()
+    for _ in range(d2h_steps):
+        step(d2h=True)
+    el_d2h = time.perf_counter() - t_d
+    d2h_equal = all(np.array_equal(h.numpy(), o.cpu().numpy()) for h, o in zip(hosts, outs))
 
     nq = len(queries) * args.steps
     value = steps_per_step * args.steps / elapsed
     moves_per_launch = float(np.mean([st.moves for st in ref]))
     avg_meet_s = float(np.mean(meet_ms)) / 1e3
-    achieved = BYTES_PER_MOVE * moves_per_launch / avg_meet_s / 1e9
     traffic = measured_traffic(args.traffic)
+    plain_qps = nq / elapsed
 
     result = {
         "metric": METRIC,
@@ -210,22 +263,63 @@ def main():
             "n": g.n, "m": g.m, "R": R, "L": cfg["L"], "queries_per_step": len(queries),
             "unit_nodes": tuned if tuned else "default",
         },
-        "queries_per_s": nq / elapsed,
+        "queries_per_s": plain_qps,
+        "queries_per_s_with_d2h": len(queries) * d2h_steps / el_d2h,
+        "d2h_estimates_equal_device": d2h_equal,
         "pairs_per_s": sum(st.pairs for st in ref) * args.steps / elapsed,
         "moves_per_query": moves_per_launch,
         "draws_per_query": float(np.mean([st.draws for st in ref])),
         "meet_kernel_ms": float(np.mean(meet_ms)),
         "query_ms": float(np.mean(query_ms)),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_meet (fused walk + meet + count)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-        },
+        "roofline": roofline(
+            "k_meet<plain> (fused walk + meet + count)", moves_per_launch, avg_meet_s,
+            traffic=traffic,
+            traffic_source=("not measured in this run: bytes per launch from rocprofv3 "
+                            "FETCH_SIZE and WRITE_SIZE of the same kernel source, "
+                            "profiles/traffic_meet_medium.json") if traffic else None),
     }
+    result["roofline"]["bound_detail"] = (
+        "the graph's 133 MB gather array sits in the 256 MB Infinity Cache; the kernel is "
+        "limited by the rate of random 128-byte line requests the memory system serves "
+        "(measured_roofs.line_requests_vs_random_gather), not by HBM bytes")
+
+    # The same 8 queries as one captured batch plan: (a) a walk seed per query
+    # (no two queries share walks), (b) the line's own queries, whose shared
+    # seed makes them one query group; against the one-at-a-time rate above.
+    bsteps = max(2, args.steps // 4)
+    per_seed = [S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
+                             seed=cfg["walk_seed"] + 1 + i, walk_cap=cfg["L"])
+                for i, s in enumerate(sources)]
+    batched = {}
+    for name, qs_b in (("seed_per_query", per_seed), ("shared_seed_groups", queries)):
+        plan = S.BatchPlan([G], qs_b)
+        plan.run(stream)
+        plan.wait()
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        for _ in range(bsteps):
+            plan.run(stream)
+            bst = plan.wait()
+        el_b = time.perf_counter() - t_b
+        if name == "shared_seed_groups":
+            equal = all(np.array_equal(plan.read(i, want_out=False)[1], ref_counts[i])
+                        for i in range(len(queries)))
+        else:   # each against the same query run alone
+            equal = True
+            for i, q in enumerate(qs_b):
+                S.simrank_single_source_async(G, q, wss[i], outs[i], cnts[i], stream)
+                S.simrank_workspace_stats(wss[i])
+                equal &= bool(np.array_equal(plan.read(i, want_out=False)[1],
+                                             cnts[i].cpu().numpy().view(np.uint32)))
+        qps_b = len(qs_b) * bsteps / el_b
+        batched[name] = {"queries_per_s": qps_b, "batched_vs_plain": qps_b / plain_qps,
+                         "groups": plan.n_groups, "runs": bsteps,
+                         "device_ms_per_run": bst.ms,
+                         "walk_steps_per_s": (bst.moves + bst.tail_steps + bst.source_moves)
+                         * bsteps / el_b,
+                         "results_equal_lone": equal}
+        plan.free()
+    result["batched"] = batched
 
     if not args.no_roofs:
         info = G.info()
@@ -272,22 +366,25 @@ def main():
         cnt, w = O.meet_counts_plain(g, s0, cfg["walk_seed"], cfg["c"], cfg["L"], R, vs=vs,
                                      with_work=True)
         dt = time.perf_counter() - t1
-        gpu_cnt = cnts[0].cpu().numpy().view(np.uint32)
-        same = bool(np.array_equal(gpu_cnt[vs], cnt))
+        same = bool(np.array_equal(ref_counts[0][vs], cnt))
         pairs = vs.size * R
         # the same oracle call on the same sample split over host threads (the
-        # call holds no shared state and releases the GIL), at most 16: the
-        # host share of one GPU
+        # call holds no shared state and releases the GIL): as many threads as
+        # this process may use, at most the host share of one GPU
         from concurrent.futures import ThreadPoolExecutor
-        nt = max(1, min(16, len(os.sched_getaffinity(0))))
+        try:
+            usable = len(os.sched_getaffinity(0))
+        except AttributeError:
+            usable = os.cpu_count() or 1
+        nt = max(1, min(CPU_THREADS_CAP, usable))
         parts = np.array_split(vs, nt)
         t2 = time.perf_counter()
         with ThreadPoolExecutor(max_workers=nt) as ex:
-            outs = list(ex.map(lambda p: O.meet_counts_plain(g, s0, cfg["walk_seed"], cfg["c"],
-                                                             cfg["L"], R, vs=p, with_work=True),
-                               parts))
+            outs_mt = list(ex.map(lambda p: O.meet_counts_plain(g, s0, cfg["walk_seed"], cfg["c"],
+                                                                cfg["L"], R, vs=p, with_work=True),
+                                  parts))
         dt_mt = time.perf_counter() - t2
-        same_mt = bool(np.array_equal(np.concatenate([o[0] for o in outs]), cnt))
+        same_mt = bool(np.array_equal(np.concatenate([o[0] for o in outs_mt]), cnt))
         result["cpu_baseline"] = {
             "value": float(w.sum()) / dt,
             "unit": "walk-steps/s",
@@ -296,11 +393,13 @@ def main():
             "sample": f"source {s0}, {vs.size} random nodes with in-edges x R={R} pairs "
                       f"({pairs} pairs, {dt:.1f}s single-threaded); counts equal to the GPU's: {same}",
             "queries_per_s": pairs / dt / ((g.n - 1) * R),
+            "host": {"nproc": os.cpu_count(), "usable_cpus": usable},
             "threads": {
                 "value": float(w.sum()) / dt_mt,
                 "cores": nt,
-                "sample": f"the same sample in {nt} node chunks, one thread each ({dt_mt:.1f}s); "
-                          f"counts equal: {same_mt}",
+                "sample": f"the same sample in {nt} node chunks, one thread each ({dt_mt:.1f}s; "
+                          f"{usable} CPUs usable by this process, at most {CPU_THREADS_CAP} "
+                          f"used: the host share of one GPU); counts equal: {same_mt}",
                 "queries_per_s": pairs / dt_mt / ((g.n - 1) * R),
             },
         }
@@ -373,7 +472,6 @@ def bench_stratified(args):
     st_, pl = res[True], res[False]
     diffs = [float((outn[i] - pout[i]).abs().max()) for i in range(len(sources))]
     value = st_["steps"] / st_["elapsed"]
-    achieved = BYTES_PER_MOVE * st_["moves"] / (st_["meet_ms"] / 1e3) / 1e9
     result = {
         "metric": METRIC,
         "value": value,
@@ -402,15 +500,11 @@ def bench_stratified(args):
         "meet_kernel_ms": st_["meet_ms"],
         "plain_meet_kernel_ms": pl["meet_ms"],
         "max_abs_diff_vs_plain_estimate": max(diffs),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_meet<stratified> (fused walk + meet + weighted count)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_stratified.json")),
-        },
+        "roofline": roofline(
+            "k_meet<stratified> (fused walk + meet + weighted count)", st_["moves"],
+            st_["meet_ms"] / 1e3,
+            traffic=measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_stratified.json")),
+            traffic_source="not measured in this run: profiles/traffic_meet_stratified.json"),
     }
     print(json.dumps(result))
     for ws in wss:
@@ -564,15 +658,9 @@ def bench_stitching(args):
         "query": {"moves": st.moves, "tail_steps": st.tail_steps, "draws": st.draws,
                   "meet_ms": st.meet_ms, "ms": st.ms, "pairs_walked": st.pairs_walked},
         "plain_query": {"moves": stp.moves, "meet_ms": stp.meet_ms, "ms": stp.ms},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_meet<stitched> (fused walk + meet + count)",
-            "achieved": BYTES_PER_MOVE * steps_per_s / 1e9,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": BYTES_PER_MOVE * steps_per_s / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
-        },
+        "roofline": roofline("k_meet<stitched> (fused walk + meet + count)",
+                             st.moves + st.tail_steps, st.meet_ms / 1e3,
+                             bound="random-gather (HBM: the graph exceeds the Infinity Cache)"),
         "measured_roofs": {"footprint_bytes": footprint,
                            "random_gather_8B_per_s": gather["per_s"],
                            "kernel_steps_per_s": steps_per_s,
@@ -716,14 +804,10 @@ def bench_batching(args):
     # the meet kernels dominate the plan: 8 algorithmic bytes per move (the
     # gathered slot) over the plan's device time (HIP events around the
     # captured graph on its stream)
-    achieved = BYTES_PER_MOVE * (st.moves + st.tail_steps) / (st.ms / 1e3) / 1e9
-    result["roofline"] = {
-        "bound": "hbm",
-        "kernel": ("k_meet_group and k_meet over the plan's queries" if plan.n_groups
-                   else "k_meet over all the plan's queries, one launch") + " (whole plan's device time)",
-        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-    }
+    result["roofline"] = roofline(
+        ("k_meet_group and k_meet over the plan's queries" if plan.n_groups
+         else "k_meet over all the plan's queries, one launch") + " (whole plan's device time)",
+        st.moves + st.tail_steps, st.ms / 1e3)
     print(json.dumps(result))
     plan.free()
     for ws in wss:
@@ -785,7 +869,6 @@ def bench_grouped(args):
     lone = np.array_equal(S.simrank_single_source_stratified(G, qs[0])[2] if strat else
                           S.simrank_single_source_ex(G, qs[0])[1], grouped[0])
     kernel_s = (dev_ms / steps) / 1e3
-    achieved = BYTES_PER_MOVE * st.moves / kernel_s / 1e9
     result = {
         "metric": METRIC,
         "value": moves / dt,
@@ -807,15 +890,13 @@ def bench_grouped(args):
         "moves_per_query_ungrouped": fst.moves / nq,
         "results_equal_ungrouped": same,
         "first_equals_lone_query": lone,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("k_meet_group<2, 2, 2>" if strat else "k_meet_group<2, 8, 0>") +
-                      " (whole plan's device time)",
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if strat else
+        "roofline": roofline(
+            ("k_meet_group<2, 2, 2>" if strat else "k_meet_group<2, 8, 0>") +
+            " (whole plan's device time)", st.moves, kernel_s,
+            traffic=None if strat else
             measured_traffic(os.path.join(ROOT, "profiles", "traffic_meet_grouped.json")),
-        },
+            traffic_source=None if strat else
+            "not measured in this run: profiles/traffic_meet_grouped.json"),
     }
     print(json.dumps(result))
     plan.free()
@@ -951,15 +1032,8 @@ def bench_serving(args):
         "server_counts": srv.counts(),
         "index_tuner": {"seg_log2": [2, 3, 4], "meet_ms": index_ms, "choice": index_choice},
         "tuning": tuning,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_meet<stitched> (fused walk + meet + count), requests one at a time",
-            "achieved": BYTES_PER_MOVE * kernel_rate / 1e9,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": BYTES_PER_MOVE * kernel_rate / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
-        },
+        "roofline": roofline("k_meet<stitched> (fused walk + meet + count), requests one at a time",
+                             kmoves, kms / 1e3),
         "measured_roofs": {"footprint_bytes": footprint,
                            "random_gather_8B_per_s": gather["per_s"],
                            "kernel_steps_per_s": kernel_rate,

@@ -30,3 +30,16 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_roofline_object_uses_12_bytes_per_move():
+    """Algorithmic bytes per walk step: an 8-byte row read and a 4-byte edge
+    read; the fraction is against the published 8 TB/s HBM peak."""
+    r = bench.roofline("k", moves=4e9, seconds=0.01, traffic=5e10, traffic_source="profile")
+    assert r["bytes_per_move"] == 12
+    assert abs(r["achieved"] - 12 * 4e9 / 0.01 / 1e9) < 1e-6
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12
+    assert abs(r["achieved_8B_gather_layout"] - 8 * 4e9 / 0.01 / 1e9) < 1e-6
+    assert r["peak"] == 8000.0 and r["unit"] == "GB/s" and r["traffic"] == 5e10
+    assert r["traffic_source"] == "profile" and r["bound"] == "random-gather"
+    assert bench.roofline("k", 1.0, 0.0)["achieved"] == 0.0

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_threads as OT
 from paper_2304_04015_amd import inputs
 from paper_2304_04015_amd import simrank as S
 
@@ -237,6 +238,34 @@ def test_shared_seed_group_full_size(nq, mode):
     for i, q in enumerate(qs):
         assert np.array_equal(plan.read(i, want_out=False)[1], S.simrank_single_source_ex(G, q)[1]), i
     plan.free()
+
+
+def test_group_of_32_medium_workload_vs_oracle():
+    """32 queries of the medium workload's shape on its own graph (R-MAT
+    n = 2^20, eps 0.02, R = 9,502, cap 64) with one seed form one query group;
+    every member's counts on 512 random nodes with in-edges and the 32 highest
+    in-degree nodes equal the oracle's for its source (run over host
+    threads), and its estimate is count / R."""
+    cfg = inputs.C2
+    g = inputs.workload_graph(cfg)
+    G = S.load_csr(g)
+    srcs = [int(x) for x in inputs.sources_with_in_edges(g, 32, 76)]
+    qs = [S.make_query(s, c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"], seed=cfg["walk_seed"],
+                       walk_cap=cfg["L"]) for s in srcs]
+    plan = S.BatchPlan([G], qs)
+    assert plan.n_groups == 1
+    plan.run()
+    st = plan.wait()
+    _say(f"group of 32 on the medium graph: {st.ms:.1f} ms, {st.moves} moves")
+    smp0 = OT.sample_nodes(g, 512, 32, 0, seed=77)
+    for i, s in enumerate(srcs):
+        out, cnt = plan.read(i)
+        smp = np.union1d(smp0, [s]).astype(np.int32)
+        want = OT.meet_counts_plain(g, s, cfg["walk_seed"], cfg["c"], cfg["L"], 9502, smp)
+        assert np.array_equal(cnt[smp], want), i
+        assert np.array_equal(out[smp], np.where(smp == s, 1.0, want / 9502.0)), i
+    plan.free()
+    G.free()
 
 
 def test_tile_and_unit_settings_keep_results(graphs):

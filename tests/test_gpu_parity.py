@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_threads as OT
 from oracle import exact
 from paper_2304_04015_amd import inputs
 from paper_2304_04015_amd import simrank as S
@@ -183,26 +184,26 @@ def c2():
 
 def test_c2_full_size_sampled(c2):
     """Full-size medium workload (R-MAT n=2^20, R=9502, L=64) in the launch
-    configuration the benchmark times; counts of sampled nodes (the 16 highest
-    in-degree nodes, 48 random nodes with in-edges, 8 without) against the
-    oracle, for 3 of the 8 sources."""
+    configuration the benchmark times, for all 8 of its sources: counts of
+    4,096 random nodes with in-edges, the 256 highest in-degree nodes and 8
+    nodes without in-edges against the oracle (run over host threads), and
+    the estimate of every sampled node equal to count / R."""
     cfg, g, G = c2
     sources = inputs.sources_with_in_edges(g, cfg["n_sources"], cfg["source_seed"])
+    assert len(sources) == 8
     deg = g.in_degree()
-    rng = np.random.default_rng(5)
-    act = np.nonzero(deg > 0)[0]
-    sample = np.unique(np.concatenate([
-        np.argsort(deg)[-16:], rng.choice(act, 48, replace=False),
-        rng.choice(np.nonzero(deg == 0)[0], 8, replace=False)])).astype(np.int32)
-    for s in sources[:3]:
-        _say(f"C2 source {s}")
+    sample = OT.sample_nodes(g, 4096, 256, 8, seed=5)
+    for s in sources:
+        _say(f"C2 source {s}: GPU")
         q = S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
                          seed=cfg["walk_seed"], walk_cap=cfg["L"])
         out, cnt, st = _counts(G, q)
         assert st.R == 9502
         smp = np.union1d(sample, [s]).astype(np.int32)
-        want = O.meet_counts_plain(g, int(s), cfg["walk_seed"], cfg["c"], cfg["L"], st.R, vs=smp)
+        _say(f"  oracle on {smp.size} nodes, {OT.host_threads()} threads")
+        want = OT.meet_counts_plain(g, int(s), cfg["walk_seed"], cfg["c"], cfg["L"], st.R, smp)
         assert np.array_equal(cnt[smp], want)
+        assert np.array_equal(out[smp], np.where(smp == s, 1.0, want / float(st.R)))
         assert cnt[s] == st.R
         assert np.all(cnt[deg == 0][np.nonzero(deg == 0)[0] != s] == 0)
         _say(f"  moves={st.moves} draws={st.draws} meet_ms={st.meet_ms:.2f} ms={st.ms:.2f}")

@@ -5,6 +5,8 @@ import time
 import numpy as np
 import pytest
 
+import oracle as O
+import oracle_threads as OT
 from paper_2304_04015_amd import inputs
 from paper_2304_04015_amd import simrank as S
 
@@ -50,6 +52,44 @@ def test_results_in_the_mix_equal_lone(served):
         assert np.array_equal(o, o1)
         assert info.latency_s >= info.queue_s >= 0.0
         assert info.stats.moves > 0 or c1.sum() == info.stats.R
+    srv.destroy()
+
+
+@pytest.mark.parametrize("group_max", [0, 8])
+def test_served_results_equal_oracle(served, group_max):
+    """Plain and stitched requests served alone (a seed per request) and in
+    query groups (requests sharing a seed): every served count vector equals
+    the oracle's for all 16,384 nodes (the Monte Carlo estimator of Section
+    2.2 with the pairing of Section 3.2; stitched walks by serial traversal of
+    the segment chain), and each estimate is count / R."""
+    g, G = served
+    rng = np.random.default_rng(40 + group_max)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    srcs = [int(x) for x in rng.choice(act, 6, replace=False)]
+    shared = group_max > 0
+    qs = []
+    for i, s in enumerate(srcs):
+        mode = S.MODE_STITCHED if i >= 4 else S.MODE_PLAIN
+        seed = (0x5EB0 + (i >= 4)) if shared else 0x5EC0 + i
+        qs.append(S.make_query(s, c=0.6, eps=0.05, delta=1e-3, seed=seed, mode=mode))
+    srv = S.Server(G, max_slots=6, max_R=9502, max_L=64, group_max=group_max)
+    tickets = [srv.submit(q) for q in qs]
+    P = O.pool_sizes(g, 1.0)
+    allv = np.arange(g.n, dtype=np.int32)
+    for t, q in zip(tickets, qs):
+        o, c, info = srv.wait(t)
+        R = info.stats.R
+        assert R == 1521
+        if q.mode == S.MODE_STITCHED:
+            want = OT.meet_counts_stitched(g, q.s, q.seed, ISEED, 0.6, 64, 8, P, R, allv)
+        else:
+            want = OT.meet_counts_plain(g, q.s, q.seed, 0.6, 64, R, allv)
+        assert np.array_equal(c, want), (q.s, q.mode)
+        assert np.array_equal(o, np.where(allv == q.s, 1.0, want / float(R)))
+    k = srv.counts()
+    assert k["done"] == len(qs) and k["failed"] == 0
+    if shared:
+        assert k["grouped"] >= 2
     srv.destroy()
 
 

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_threads as OT
 from paper_2304_04015_amd import inputs
 from paper_2304_04015_amd import simrank as S
 
@@ -174,7 +175,9 @@ def test_c3_stitching_at_scale():
     oracle's direct generation (each segment regenerated from the CSR under the
     same Philox keys): the index size, 4096 sampled slots (segment, successor),
     all R source walks, 2^20 sampled stitched walks (v, j), and the stitched
-    query's meet counts on 48 sampled nodes."""
+    query's meet counts and estimates on 2,048 random nodes with in-edges, the
+    64 highest in-degree nodes and 8 without in-edges (the oracle run over
+    host threads)."""
     cfg = inputs.C3
     _say("generating the R-MAT scale-24 graph")
     g = inputs.workload_graph(cfg)
@@ -221,11 +224,12 @@ def test_c3_stitching_at_scale():
     assert (plens > (1 << k)).sum() > 10000
     _say("stitched query")
     out, cnt, st = S.simrank_single_source_ex(G, q)
-    smp = np.union1d(rng.choice(act, 40, replace=False), np.argsort(g.in_degree())[-8:])
-    smp = np.union1d(smp, [s]).astype(np.int32)
-    want = O.meet_counts_stitched(g, s, cfg["walk_seed"], cfg["index_seed"], cfg["c"], cfg["L"],
-                                  1 << k, P, R, vs=smp)
+    smp = OT.sample_nodes(g, 2048, 64, 8, seed=25, extra=[s])
+    _say(f"stitched counts in the oracle: {smp.size} nodes, {OT.host_threads()} threads")
+    want = OT.meet_counts_stitched(g, s, cfg["walk_seed"], cfg["index_seed"], cfg["c"], cfg["L"],
+                                   1 << k, P, R, smp)
     assert np.array_equal(cnt[smp], want)
+    assert np.array_equal(out[smp], np.where(smp == s, 1.0, want / float(R)))
     _say(f"query: moves={st.moves} tail_steps={st.tail_steps} meet_ms={st.meet_ms:.1f}")
 
 

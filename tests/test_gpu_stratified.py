@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_threads as OT
 from paper_2304_04015_amd import inputs
 from paper_2304_04015_amd import simrank as S
 
@@ -106,6 +107,35 @@ def test_paper_parameters_medium_graph_sampled():
     assert np.array_equal(out[smp], o_out) and np.array_equal(out_n[smp], o_out_n)
     # estimates are probabilities up to the weights' z / N factor
     assert np.all(out_n >= 0) and np.all(out_n <= 1.0 + 1e-12)
+
+
+def test_paper_parameters_medium_workload_sampled():
+    """The stratified benchmark's configuration: the medium R-MAT graph
+    (n = 2^20) with Algorithm 2's own z for eps = 0.02 and Algorithm 1's cap,
+    N = 18,234 walks per node, phi = 54, for 2 of the workload's sources.
+    Weighted sums and both estimates of 1,024 random nodes with in-edges, the
+    64 highest in-degree nodes and 8 without in-edges equal the oracle's
+    (run over host threads)."""
+    cfg = inputs.C2
+    g = inputs.workload_graph(cfg)
+    G = S.load_csr(g)
+    sources = inputs.sources_with_in_edges(g, cfg["n_sources"], cfg["source_seed"])
+    smp0 = OT.sample_nodes(g, 1024, 64, 8, seed=6)
+    for s in (int(sources[0]), int(sources[5])):
+        q = S.make_stratified_query(s, c=cfg["c"], eps=cfg["eps"], seed=cfg["walk_seed"])
+        P = _oracle_params(g, q)
+        assert (P.phi, P.N) == (54, 18234)
+        _say(f"stratified medium: source {s}, N={P.N} phi={P.phi}")
+        out, out_n, wsum, st = S.simrank_single_source_stratified(G, q)
+        smp = np.union1d(smp0, [s]).astype(np.int32)
+        _say(f"  oracle on {smp.size} nodes, {OT.host_threads()} threads")
+        want = OT.strat_sums(g, s, cfg["walk_seed"], P, smp)
+        assert np.array_equal(wsum[smp], want)
+        o_out, o_out_n = O.strat_estimates(want, s, P, vs=smp)
+        assert np.array_equal(out[smp], o_out) and np.array_equal(out_n[smp], o_out_n)
+        assert wsum[s] == 0 and out[s] == 1.0
+        assert st.R == P.N and st.L == P.phi
+    G.free()
 
 
 def test_edge_cases():
