@@ -189,6 +189,23 @@ int simrank_single_source_async(const simrank_graph *g, const simrank_query *q,
                                 simrank_workspace *ws, double *out_dev, uint32_t *counts_dev,
                                 void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the query of
+ * simrank_single_source_async without a workspace and without any allocation.
+ * Its scratch (source walks, tiles, descriptor, counters: about 9 MB) is a
+ * fixed device array that each GPU the library runs on holds from the first
+ * such call there until the process ends.  Plain and stitched queries with
+ * R <= 65536 and R * L <= 2^20 (the medium workload's R = 9502, L = 64 fits);
+ * EINVAL beyond that and for stratified queries.  out_dev: device double[n] or
+ * NULL; counts_dev: device uint32[n], required; both caller-owned and
+ * overwritten.  Enqueues on `stream` (hipStream_t; NULL = default stream) and
+ * returns without waiting; results equal simrank_single_source_async's.  All
+ * calls on one GPU share its scratch: a call must not overlap another on the
+ * same GPU (calls on one stream are ordered; across streams or threads they
+ * race).  No stats. */
+int simrank_single_source_noalloc(const simrank_graph *g, const simrank_query *q,
+                                  double *out_dev, uint32_t *counts_dev, void *stream);
+
 /* Waits for the workspace's last call and fills *st (moves, draws, meets...;
  * ms = device time between the call's first and last kernel). */
 int simrank_workspace_stats(simrank_workspace *ws, simrank_stats *st);

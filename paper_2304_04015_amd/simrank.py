@@ -131,6 +131,7 @@ def lib() -> C.CDLL:
         "simrank_workspace_free": [vp],
         "simrank_single_source_async": [vp, P(simrank_query), vp, vp, vp, vp],
         "simrank_workspace_stats": [vp, P(simrank_stats)],
+        "simrank_single_source_noalloc": [vp, P(simrank_query), vp, vp, vp],
         "simrank_walks": [vp, P(simrank_query), vp, vp, i64, vp, vp],
         "simrank_derive_stratified": [P(simrank_query), i32, P(simrank_strat_params)],
         "simrank_single_source_stratified": [vp, P(simrank_query), vp, vp, vp, P(simrank_stats)],
@@ -326,6 +327,18 @@ def simrank_single_source_async(g: Graph, q: simrank_query, ws: Workspace, out_d
     _check(lib().simrank_single_source_async(g.handle, C.byref(q), ws.handle,
                                              _dev_ptr(out_dev, g.n, 8, "out_dev"),
                                              _dev_ptr(counts_dev, g.n, 4, "counts_dev"), sp))
+
+
+def simrank_single_source_noalloc(g: Graph, q: simrank_query, out_dev, counts_dev,
+                                  stream=None) -> None:
+    """The allocation-free query: as simrank_single_source_async, without a
+    workspace (the library's fixed per-GPU scratch)."""
+    sp = None
+    if stream is not None:
+        sp = int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+    _check(lib().simrank_single_source_noalloc(g.handle, C.byref(q),
+                                               _dev_ptr(out_dev, g.n, 8, "out_dev"),
+                                               _dev_ptr(counts_dev, g.n, 4, "counts_dev"), sp))
 
 
 def simrank_workspace_stats(ws: Workspace) -> simrank_stats:
