@@ -125,6 +125,9 @@ def parse():
                     help="grouped: number of same-seed queries on the medium graph")
     ap.add_argument("--group-kind", default="plain", choices=["plain", "stratified"],
                     help="grouped: plain queries (groups of up to 32) or stratified ones (up to 8)")
+    ap.add_argument("--served-mode", default="stitched", choices=["stitched", "plain"],
+                    help="serving: walks of the requests (stitched through the resident index, "
+                         "or plain)")
     ap.add_argument("--shared-seed", action="store_true",
                     help="batching: one walk seed per graph instead of one per query, so that "
                          "the queries of a graph share their walks from every node (query groups)")
@@ -140,6 +143,9 @@ def parse():
                     help="medium: run the work-unit tuner on the graph before timing")
     ap.add_argument("--no-roofs", action="store_true",
                     help="skip the measured gather / Philox / copy ceilings")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="medium: skip the batched leg (so that every launch of the meet "
+                         "kernel is one query, e.g. under the profiler's counters)")
     ap.add_argument("--scale", type=int, default=0,
                     help="R-MAT scale of the graph (0: the medium workload's 20)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_meet_medium.json"),
@@ -286,12 +292,13 @@ def main():
     # The same 8 queries as one captured batch plan: (a) a walk seed per query
     # (no two queries share walks), (b) the line's own queries, whose shared
     # seed makes them one query group; against the one-at-a-time rate above.
-    bsteps = max(2, args.steps // 4)
+    bsteps = 0 if args.no_batched else max(2, args.steps // 4)
     per_seed = [S.make_query(int(s), c=cfg["c"], eps=cfg["eps"], delta=cfg["delta"],
                              seed=cfg["walk_seed"] + 1 + i, walk_cap=cfg["L"])
                 for i, s in enumerate(sources)]
     batched = {}
-    for name, qs_b in (("seed_per_query", per_seed), ("shared_seed_groups", queries)):
+    for name, qs_b in (() if args.no_batched else
+                       (("seed_per_query", per_seed), ("shared_seed_groups", queries))):
         plan = S.BatchPlan([G], qs_b)
         plan.run(stream)
         plan.wait()
@@ -599,10 +606,13 @@ def bench_stitching(args):
     if args.scale:
         cfg["scale"] = args.scale
     torch.cuda.set_device(0)
+    copy_probe(args)
     t0 = time.time()
     g = inputs.workload_graph(cfg)
     print(f"# graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s", file=sys.stderr)
+    t_load = time.perf_counter()
     G = S.load_csr(g)
+    load_s = time.perf_counter() - t_load
     builds = []
     for _ in range(max(1, args.steps)):
         builds.append(S.simrank_build_index(G, seg_log2=cfg["seg_log2"], kappa=cfg["kappa"],
@@ -635,6 +645,15 @@ def bench_stitching(args):
     footprint = 8 * (gi["m"] + gi["n"] - gi["n_active"])
     gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
     build_ms = float(np.mean([b["build_ms"] for b in builds]))
+    seg_ms = float(np.mean([b["segments_ms"] for b in builds]))
+    dbl_ms = float(np.mean([b["doubling_ms"] for b in builds]))
+    nseg = info["segments"]
+    seg_len = 1 << cfg["seg_log2"]
+    # algorithmic bytes: a segment walk's moves (12 B each) and its row, length
+    # and successor (4 * 2^k + 1 + 4 B); a doubling round reads one random
+    # 4-byte successor and copies 4 * 2^r bytes of chain per slot
+    seg_bytes = BYTES_PER_MOVE * info["build_moves"] + nseg * (4 * seg_len + 5)
+    dbl_bytes = sum(nseg * (4 + 4 + 4 * (1 << r) * 2) for r in range(info["levels"]))
     walk_steps = st.moves + st.tail_steps + st.source_moves
     steps_per_s = (st.moves + st.tail_steps) / (st.meet_ms / 1e3)
     result = {
@@ -654,6 +673,20 @@ def bench_stitching(args):
             "build_ms": build_ms, "build_moves": info["build_moves"],
             "segments_per_s": info["segments"] / (build_ms * 1e-3),
             "build_moves_per_s": info["build_moves"] / (build_ms * 1e-3),
+            "graph_load_s": load_s,
+            "segments_kernel": {
+                "ms": seg_ms,
+                "moves_per_s": info["build_moves"] / (seg_ms * 1e-3),
+                "moves_vs_random_gather": info["build_moves"] / (seg_ms * 1e-3) / gather["per_s"],
+                "achieved_GBps": seg_bytes / (seg_ms * 1e-3) / 1e9,
+                "frac": seg_bytes / (seg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            },
+            "doubling_kernels": {
+                "ms": dbl_ms,
+                "rounds": info["levels"],
+                "achieved_GBps": dbl_bytes / (dbl_ms * 1e-3) / 1e9 if dbl_ms > 0 else 0.0,
+                "frac": dbl_bytes / (dbl_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if dbl_ms > 0 else 0.0,
+            },
         },
         "query": {"moves": st.moves, "tail_steps": st.tail_steps, "draws": st.draws,
                   "meet_ms": st.meet_ms, "ms": st.ms, "pairs_walked": st.pairs_walked},
@@ -909,13 +942,14 @@ def bench_serving(args):
     index resident in HBM (segment length 2^k chosen among k = 2, 3, 4 by the
     segment-length tuner, then nodes per unit and walks per tile by the tuner).
     Requests: sources drawn proportionally to in-degree, eps uniform in
-    {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks.  First the
-    plain capacity (requests back to back, one at a time); then Poisson arrivals
-    at 0.5, 0.8, 1.0 and 1.2 times that rate into the server (4 slots):
-    achieved queries/s and p50 / p99 latency per level.  --group-max G: the
-    requests share one walk seed and the server (max(4, G) slots) admits those
-    waiting together as query groups of up to G; offered loads 0.5 to 4 times
-    the plain capacity."""
+    {0.05, 0.02}, delta = 1e-3, L = 64, stitched walks, a walk seed per
+    request.  First the plain capacity (requests back to back, one at a time,
+    each estimate copied to the host); then Poisson arrivals at 0.5, 0.8, 1.0,
+    1.2, 1.5 and 2 times that rate into the continuous-batching server (at most
+    16 requests in flight): achieved queries/s and p50 / p99 latency per
+    level.  --group-max G: the requests share one walk seed and the server
+    admits those waiting together as query groups of up to G; offered loads
+    0.5 to 4 times the plain capacity."""
     import numpy as np
     import torch
 
@@ -938,14 +972,17 @@ def bench_serving(args):
         seed = 0x2304040150000500 + (0 if args.group_max >= 2 else i)
         return S.make_query(s, c=cfg["c"], eps=float(rng.choice(cfg["eps_choices"])),
                             delta=cfg["delta"], seed=seed, walk_cap=cfg["L"],
-                            mode=S.MODE_STITCHED)
+                            mode=S.MODE_STITCHED if args.served_mode == "stitched"
+                            else S.MODE_PLAIN)
 
     # the index's segment length and the work partition, chosen by the tuners
     # on one request of the workload (the index left built is the fastest one)
     tq = make(0)
     tq.eps = 0.02                     # the larger R of the mix
+    tq.mode = S.MODE_STITCHED         # the index tuner times stitched queries
     index_choice, index_ms = S.simrank_tune_index(G, tq, seg_log2=(2, 3, 4), kappa=1.0,
                                                   c=cfg["c"], seed=0x2304040150000023)
+    tq.mode = S.MODE_STITCHED if args.served_mode == "stitched" else S.MODE_PLAIN
     tuning = S.simrank_tune_ex(G, tq)
     # plain capacity: one request at a time, back to back
     warm = [make(i) for i in range(2)]
@@ -975,11 +1012,11 @@ def bench_serving(args):
     gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
     kernel_rate = kmoves / (kms / 1e3)
     grouped = args.group_max >= 2
-    srv = S.Server(G, max_slots=max(4, args.group_max), max_R=9502, max_L=cfg["L"],
+    srv = S.Server(G, max_slots=max(16, args.group_max), max_R=9502, max_L=cfg["L"],
                    group_max=args.group_max)
     levels = []
     k = 1000
-    for load in ((0.5, 1.0, 2.0, 3.0, 4.0) if grouped else (0.5, 0.8, 1.0, 1.2)):
+    for load in ((0.5, 1.0, 2.0, 3.0, 4.0) if grouped else (0.5, 0.8, 1.0, 1.2, 1.5, 2.0)):
         qps = load * capacity
         reqs = [make(k + i) for i in range(args.requests)]
         k += args.requests
@@ -1017,19 +1054,21 @@ def bench_serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"serving: R-MAT n=2^{cfg['scale']}, avg degree 16, index "
-                               "resident; sources by in-degree, eps in {.05,.02}, stitched; " +
+                               f"resident; sources by in-degree, eps in {{.05,.02}}, {args.served_mode}; " +
                                (f"one walk seed, query groups of up to {args.group_max}; Poisson "
                                 "arrivals at 0.5-4x plain capacity; "
-                                f"{max(4, args.group_max)} slots" if grouped else
-                                "a seed per request; Poisson arrivals at 0.5-1.2x plain "
-                                "capacity; 4 slots"),
+                                f"{max(16, args.group_max)} requests in flight at most" if grouped
+                                else "a seed per request; Poisson arrivals at 0.5-2x plain "
+                                "capacity; continuous batching, 16 requests in flight at most"),
                    "n": g.n, "m": g.m, "requests_per_level": args.requests,
                    "group_max": args.group_max},
         "queries_per_s": top["achieved_qps"],
         "plain_queries_per_s": capacity,
         "served_vs_plain": top["achieved_qps"] / capacity,
+        "served_vs_plain_by_load": {str(lv["load"]): lv["achieved_qps"] / capacity for lv in levels},
         "levels": levels,
         "server_counts": srv.counts(),
+        "server_load": srv.load(),
         "index_tuner": {"seg_log2": [2, 3, 4], "meet_ms": index_ms, "choice": index_choice},
         "tuning": tuning,
         "roofline": roofline("k_meet<stitched> (fused walk + meet + count), requests one at a time",

@@ -66,8 +66,8 @@ typedef struct simrank_workspace simrank_workspace; /* opaque; per-call scratch 
 
 /* One single-source query (Algorithm 1 input: G, s, c, delta, eps). */
 typedef struct simrank_query {
-    int32_t s;           /* source node, 0 <= s < n */
     int32_t graph;       /* simrank_batch only: index into its graph array */
+    int32_t s;           /* source node, 0 <= s < n */
     double c;            /* decay factor, 0 < c < 1 */
     double eps;          /* absolute error target, c^(L+1) < eps < 1 */
     double delta;        /* failure probability, 0 < delta < 1 */
@@ -132,6 +132,8 @@ typedef struct simrank_index_summary {
     int32_t levels;      /* doubling rounds run: log2(ceil(max cap / 2^k)) */
     double build_ms;     /* device time of the last build */
     uint64_t build_moves;/* steps taken while building the segments */
+    double segments_ms;  /* of build_ms: the segment walks (one per slot, with successors) */
+    double doubling_ms;  /* of build_ms: the pointer-doubling rounds */
 } simrank_index_summary;
 
 /* ---------------------------------------------------------------- graphs */
@@ -400,59 +402,89 @@ int simrank_tune_index(simrank_graph *g, const simrank_query *q, const simrank_i
 
 /* --------------------------------------------------------------- serving */
 
-/* A request loop over one device-resident graph (and its index).  Requests
- * are queued by simrank_server_submit and admitted by a worker thread into
- * slots as slots free up; a slot (workspace, device and pinned host buffers,
- * own stream) holds one running request, and as many slots are made as the
- * device-memory budget admits (at most max_slots), so requests that arrive
- * while others run start as soon as a slot frees and run concurrently on the
- * device.  Each result equals what simrank_single_source_ex returns for the
- * same query alone. */
+/* A request loop over one device-resident graph (and its index) with
+ * continuous batching.  simrank_server_submit queues a request; a worker
+ * thread admits queued requests oldest first as soon as a ring entry (at most
+ * max_slots requests in flight) and the request's own device memory (its R, L
+ * and mode decide how much, taken from the server's pool of hbm_budget bytes)
+ * are free.  An admitted request's source walks and compaction are prepared
+ * on the device and its work units (tiles of source walks x chunks of nodes)
+ * are published into a device ring; persistent meet kernels take units from
+ * every published request of their kind, oldest first, and exit when none is
+ * left, so requests that arrive while others run join the work on the device
+ * without waiting for it to end.  The block that finishes a request's last
+ * unit writes its estimate and flags the request in pinned host memory; the
+ * worker copies the results to the host and retires it.  Plain, stitched and
+ * stratified requests are served; each result equals what the lone call
+ * returns for the same query (simrank_single_source_ex, or
+ * simrank_single_source_stratified). */
 typedef struct simrank_server simrank_server;
 
 typedef struct simrank_server_params {
-    int32_t max_slots;    /* 1..64 concurrent requests */
-    int32_t max_R;        /* largest R a request may need */
-    int32_t max_L;        /* largest walk cap a request may use */
-    int32_t group_max;    /* 0 or 1: every request runs alone.  2..32: requests
-                             with equal mode, seed, c and cap that wait together
-                             are admitted as one query group of up to group_max
-                             (and at most the free slots), which takes each
-                             walk (v, j) once for all of them (Section 3's walk
-                             (v, j) does not depend on the source); while the
-                             group runs, new requests wait to form the next
-                             one.  A grouped request's stats are its share
-                             (1/G) of its group's work and the group's device
-                             time. */
-    int64_t hbm_budget;   /* device bytes the slots may take; 0: half the free memory */
+    int32_t max_slots;    /* 1..64 requests in flight at once */
+    int32_t max_R;        /* largest R (stratified: N) a request may need */
+    int32_t max_L;        /* largest walk cap (stratified: phi) a request may use */
+    int32_t group_max;    /* 0 or 1: every request runs alone.  2..32: plain or
+                             stitched requests with equal mode, seed, c and cap
+                             that wait together are admitted as one query group
+                             of up to group_max, which takes each walk (v, j)
+                             once for all of them (Section 3's walk (v, j) does
+                             not depend on the source); one group runs at a
+                             time, beside the lone requests.  A grouped
+                             request's stats are its share (1/G) of its group's
+                             work and the group's device time. */
+    int64_t hbm_budget;   /* device bytes for the requests in flight (the pool);
+                             0: half the free memory.  At most max_slots requests
+                             of (max_R, max_L) are reserved for. */
 } simrank_server_params;
 
 typedef struct simrank_request_info {
-    double queue_s;       /* submit -> start of its kernels being enqueued */
+    double queue_s;       /* submit -> admission (its preparation enqueued) */
     double latency_s;     /* submit -> results in host memory */
-    simrank_stats stats;  /* work and device time of the request */
+    simrank_stats stats;  /* work of the request; ms and meet_ms: admission ->
+                             completion on the host clock (a lone request shares
+                             its kernels with others), or its group's device time */
 } simrank_request_info;
 
-/* The graph must outlive the server.  ENOMEM when the budget admits no slot;
- * EINVAL for group_max outside [0, 32]. */
+/* The graph must outlive the server.  ENOMEM when the budget admits no
+ * request of (max_R, max_L); EINVAL for max_slots outside [1, 64] or
+ * group_max outside [0, 32]. */
 int simrank_server_create(simrank_graph *g, const simrank_server_params *p,
                           simrank_server **server_out);
-/* Slots made and device bytes per slot. */
+/* Requests of (max_R, max_L) the pool holds at once (at most max_slots), and
+ * device bytes one such plain request takes. */
 int simrank_server_info(const simrank_server *server, int32_t *slots, int64_t *slot_bytes);
 /* Requests finished and failed so far, query groups launched and the
  * requests they held (each pointer may be NULL). */
 int simrank_server_counts(simrank_server *server, uint64_t *done, uint64_t *failed,
                           uint64_t *groups, uint64_t *grouped);
-/* Validates and queues a query (q->graph ignored); returns at once with a ticket. */
+/* Most requests in flight at once so far, the pool's size and peak use in
+ * bytes, and the kernel launches made (persistent meet kernels and groups);
+ * each pointer may be NULL. */
+int simrank_server_load(simrank_server *server, int32_t *inflight_peak, int64_t *pool_bytes,
+                        int64_t *pool_peak, uint64_t *launches);
+/* Validates and queues a query (q->graph ignored); returns at once with a
+ * ticket.  EINVAL when it needs R or L beyond the server's maximum, ENOMEM
+ * when its buffers exceed the whole pool. */
 int simrank_server_submit(simrank_server *server, const simrank_query *q, uint64_t *ticket);
-/* Waits up to timeout_s seconds (< 0: no limit) for the request, copies its
- * estimate (host double[n], may be NULL) and counts (host uint32[n], may be
- * NULL) and fills info (may be NULL); the ticket is then retired.  ESTATE on
- * timeout (the ticket stays valid); EINVAL for an unknown or retired ticket
- * (of two waits on one ticket, one receives the result, the other EINVAL).
- * Safe to call from several threads at once. */
+/* *state: 0 queued, 1 running, 2 finished (a wait returns at once); EINVAL
+ * for an unknown or retired ticket. */
+int simrank_server_poll(simrank_server *server, uint64_t ticket, int32_t *state);
+/* Waits up to timeout_s seconds (< 0: no limit) for a plain or stitched
+ * request, copies its estimate (host double[n], may be NULL) and counts (host
+ * uint32[n], may be NULL) and fills info (may be NULL); the ticket is then
+ * retired.  ESTATE on timeout (the ticket stays valid); EINVAL for an unknown
+ * or retired ticket (of two waits on one ticket, one receives the result, the
+ * other EINVAL) and for a stratified request (nothing retired).  Safe to call
+ * from several threads at once. */
 int simrank_server_wait(simrank_server *server, uint64_t ticket, double timeout_s,
                         double *out_host, uint32_t *counts_host, simrank_request_info *info);
+/* simrank_server_wait for a stratified request: out, out_n and wsum as
+ * simrank_single_source_stratified returns them (host arrays of n, each may
+ * be NULL).  EINVAL for a plain or stitched request (nothing retired). */
+int simrank_server_wait_stratified(simrank_server *server, uint64_t ticket, double timeout_s,
+                                   double *out_host, double *out_n_host, uint64_t *wsum_host,
+                                   simrank_request_info *info);
 /* Finishes the queued and running requests, then frees the server.  No other
  * call on the server may run during or after it. */
 int simrank_server_destroy(simrank_server *server);

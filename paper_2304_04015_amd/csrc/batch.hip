@@ -30,21 +30,6 @@ int32_t walk_kind(int mode) {
     return mode == SIMRANK_MODE_STITCHED ? 1 : mode == SIMRANK_MODE_STRATIFIED ? 2 : 0;
 }
 
-// Device bytes one query needs in a plan (stratified queries: class table,
-// walk classes, weighted sums and the second estimate instead of counts).
-size_t query_bytes(const simrank_params &p, int mode, int32_t n) {
-    const size_t RL = (size_t)p.R * (size_t)p.L;
-    size_t b = align_up(4 * RL) + align_up((size_t)p.R) + align_up(4 * (size_t)p.R) +
-               align_up(4 * ((size_t)p.R + 1)) + align_up(4 * RL) +
-               align_up(4 * ((size_t)max_tiles_for(p.R, p.L) + 1)) + align_up(32) +
-               align_up(8 * (size_t)n);
-    if (mode == SIMRANK_MODE_STRATIFIED)
-        b += align_up(sizeof(StratTab)) + align_up((size_t)p.R) + 2 * align_up(8 * (size_t)n);
-    else
-        b += align_up(4 * (size_t)n);
-    return b;
-}
-
 // Groups of queries of one kind that share (graph, seed, continue threshold,
 // cap; stratified: z, N and phi): each such set of two or more queries is
 // split into ceil(size / GROUP_MAX) groups of nearly equal size, in query
@@ -198,6 +183,25 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         groups.swap(kept);
     }
     const int32_t ngr = (int32_t)groups.size();
+    // Each kind's meet launch numbers the work units of all its queries in 32
+    // bits (unit offsets and the persistent cursor, which the grid's blocks
+    // advance past the end once each): refuse a plan whose units could wrap.
+    {
+        int64_t kind_units[N_KINDS] = {0, 0, 0};
+        for (int32_t i = 0; i < nq; ++i) {
+            if (group_of[i] >= 0) continue;
+            const Graph *g = graphs[qs[i].graph];
+            const int64_t vb = default_unit_nodes(g);
+            const int kind = modes[i] == SIMRANK_MODE_STITCHED ? K_STITCHED
+                             : modes[i] == SIMRANK_MODE_STRATIFIED ? K_STRAT : K_PLAIN;
+            kind_units[kind] += (int64_t)max_tiles_for(ps[i].R, ps[i].L) * ((g->n_active + vb - 1) / vb);
+        }
+        for (int k = 0; k < N_KINDS; ++k)
+            if (kind_units[k] >= (int64_t)0xffffffffu - (1 << 20))
+                return fail(SIMRANK_EINVAL, "the batch's queries of one kind have " +
+                                                std::to_string(kind_units[k]) +
+                                                " work units, beyond 2^32: split the batch");
+    }
     simrank_batch_plan *p = new simrank_batch_plan();
     p->device = graphs[qs[0].graph]->device;
     p->nq = nq;
@@ -209,7 +213,7 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
     size_t total = 0;
-    for (int32_t i = 0; i < nq; ++i) total += query_bytes(ps[i], modes[i], graphs[qs[i].graph]->n);
+    for (int32_t i = 0; i < nq; ++i) total += request_bytes(ps[i], modes[i], graphs[qs[i].graph]->n);
     for (int32_t k = 0; k < ngr; ++k) {
         GroupDesc gd{};
         gd.Rmax = (int32_t)g_Rmax[k];
@@ -250,30 +254,16 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
         const simrank_params &pp = ps[i];
         QueryDesc &d = p->desc[i];
         describe_query(g, &qs[i], pp, modes[i], default_unit_nodes(g), &d);
-        const size_t RL = (size_t)pp.R * (size_t)pp.L;
-        d.sw = (uint32_t *)take(4 * RL);
-        d.slen = (uint8_t *)take((size_t)pp.R);
-        d.jj = (uint32_t *)take(4 * (size_t)pp.R);
-        d.joff = (uint32_t *)take(4 * ((size_t)pp.R + 1));
-        d.swc = (uint32_t *)take(4 * RL);
-        d.tiles = (uint32_t *)take(4 * ((size_t)max_tiles_for(pp.R, pp.L) + 1));
-        d.meta = (uint32_t *)take(32);
-        d.out = (double *)take(8 * (size_t)g->n);
+        carve_request(pp, modes[i], g->n, take(request_bytes(pp, modes[i], g->n)), &d);
         if (modes[i] == SIMRANK_MODE_STRATIFIED) {
             StratParams sp;
             StratTab tab{};
             if ((rc = strat_params(&qs[i], g->n, &sp, &tab))) return bail(rc);
-            d.tab = (const StratTab *)take(sizeof(StratTab));
-            d.scls = (uint8_t *)take((size_t)pp.R);
-            d.wsum = (unsigned long long *)take(8 * (size_t)g->n);
-            d.out_n = (double *)take(8 * (size_t)g->n);
             d.z = sp.z;
             d.sa = sp.sa;
             d.sb = sp.sb;
             e = hipMemcpy((void *)d.tab, &tab, sizeof(StratTab), hipMemcpyHostToDevice);
             if (e != hipSuccess) return bail(fail(SIMRANK_EDEVICE, hipGetErrorString(e)));
-        } else {
-            d.cnt = (uint32_t *)take(4 * (size_t)g->n);
         }
         p->graphs[i] = g;
         if (modes[i] == SIMRANK_MODE_STITCHED) p->index_gen[i] = g->index_gen;
@@ -462,7 +452,7 @@ extern "C" int simrank_batch(simrank_graph *const *graphs, int32_t ngraphs,
         size_t used = 0;
         int32_t i1 = i0;
         while (i1 < nq) {
-            const size_t b = query_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) +
+            const size_t b = request_bytes(ps[i1], modes[i1], graphs[qs[i1].graph]->n) +
                              sizeof(QueryDesc) + 64 +
                              4 * (size_t)ps[i1].R * ps[i1].L + 16 * (size_t)ps[i1].R +
                              1024;   // its share of a group's buffers

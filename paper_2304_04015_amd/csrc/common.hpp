@@ -43,9 +43,9 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 //  - stratified (medium graph; its LDS also holds classes, shuffle keys and a
 //    queue of prepared pairs): 1024 threads, 6144 / 20480: 99.6 ms, against
 //    114.1 ms with 512 threads and 1024 / 4096;
-//  - stitched (n = 2^24, beyond the Infinity Cache, tails read from the index:
-//    it needs more pairs in flight per CU): 512 threads, 2048 / 8192: 963 ms,
-//    against 984 ms with 1024 / 4096 and 1200 ms with the plain kind's shape.
+//  - stitched: the plain kind's block and positions per tile (its private
+//    heads are plain walks), with room in LDS for the waves' tail queues
+//    (16 waves x 128 x 8 bytes): tiles of up to 6144 walks / 24576 positions.
 #ifndef SRK_TILE_J
 #define SRK_TILE_J 8192
 #endif
@@ -56,13 +56,13 @@ enum Kind : int32_t { K_PLAIN = 0, K_STITCHED = 1, K_STRAT = 2, N_KINDS = 3 };
 #define SRK_MEET_BLOCK 1024
 #endif
 #ifndef SRK_STITCH_TILE_J
-#define SRK_STITCH_TILE_J 2048
+#define SRK_STITCH_TILE_J 6144
 #endif
 #ifndef SRK_STITCH_TILE_NODES
-#define SRK_STITCH_TILE_NODES 8192
+#define SRK_STITCH_TILE_NODES 24576
 #endif
 #ifndef SRK_STITCH_MEET_BLOCK
-#define SRK_STITCH_MEET_BLOCK 512
+#define SRK_STITCH_MEET_BLOCK 1024
 #endif
 #ifndef SRK_STRAT_TILE_J
 #define SRK_STRAT_TILE_J 6144
@@ -107,6 +107,8 @@ struct Graph {
     uint2 *E = nullptr;           // [m_slots]
     uint32_t *node_of = nullptr;  // [m_slots] node id owning slot o (valid at o(v))
     int32_t *active = nullptr;    // [n_active] nodes with deg >= 1, ascending
+    uint32_t *dbar = nullptr;     // [n] rows of the CSR that list v (v's in-degree in the
+                                  //     reversed graph), counted at ingest
     hipStream_t stream = nullptr; // stream of the synchronous calls
     Index *index = nullptr;
     uint64_t index_gen = 0;       // counts replacements of the index (plans check it)
@@ -133,6 +135,7 @@ struct Index {
     uint32_t *chain = nullptr;    // [segments][width] slots of the long walk from sigma
     int64_t bytes = 0;
     double build_ms = 0;
+    double segments_ms = 0, doubling_ms = 0;   // parts of build_ms
     uint64_t build_moves = 0;
 };
 
@@ -288,6 +291,43 @@ size_t group_buffers(GroupDesc *gd, int64_t sum_RL, char *base);
 // Enqueues a query set's groups: compaction, unit offsets, the group meet
 // kernel (after the members' source walks, before their estimates).
 int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t st);
+
+// ------------------------------------------------------------ serving ring
+// The server's in-flight requests (server.hip) sit in a ring of entries that
+// persistent meet kernels take work units from.  An entry is published by the
+// last kernel of its request's preparation: the fields first, then `claim` =
+// seq << 32 (release).  A block claims unit u of an entry by moving `claim`
+// from (seq, u) to (seq, u + 1) with compare-and-swap, so a claim can never
+// land on a later request that reuses the entry.  The block that finishes the
+// entry's last unit writes the estimate and then the entry's flag in host
+// memory (the request's seq).
+constexpr int RING_MAX = 64;
+struct RingCtl {
+    unsigned long long claim;   // (seq << 32) | units claimed; 0 = never published
+    uint32_t n_units;           // tiles x node chunks of the request
+    uint32_t done;              // units finished
+    int32_t kind;               // Kind of the meet kernel that takes it
+    uint32_t seq;               // the request's sequence number (nonzero)
+    uint32_t pad[2];
+};
+struct StreamRing {
+    QueryDesc *desc;                 // device [RING_MAX]
+    RingCtl *ctl;                    // device [RING_MAX]
+    unsigned long long *counters;    // device [RING_MAX][8]: work counters per entry
+    uint32_t *flags;                 // pinned host [RING_MAX], written by the device
+    int32_t entries;                 // entries in use, <= RING_MAX
+};
+// Serving (query.hip): enqueue on `st` the preparation of ring entry `slot`
+// for the request described by d (its buffers attached): descriptor, init,
+// source walks, compaction, publication.  Launch a persistent meet kernel of
+// `kind` that takes units from every published entry of that kind and exits
+// when none is left.  Bytes of device memory a request needs for its buffers.
+int enqueue_ring_request(const QueryDesc &d, const StreamRing &ring, int32_t slot, uint32_t seq,
+                         hipStream_t st);
+int launch_ring_meet(int kind, const StreamRing &ring, hipStream_t st);
+size_t request_bytes(const simrank_params &p, int mode, int32_t n);
+// Carves a request's buffers (request_bytes of them) from base into d.
+void carve_request(const simrank_params &p, int mode, int32_t n, char *base, QueryDesc *d);
 
 // Per-query scratch.
 struct Workspace {

@@ -58,20 +58,25 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// One pair in flight on a lane.
+// One pair in flight on a lane.  The six unused words keep the layout the
+// plain kind's hot loop was measured with: the compiler's register assignment
+// follows the struct, and without them the plain kernel takes 3% longer at
+// n = 2^24 (74 instead of 68 VGPRs, extra register moves).
 struct Slot {
     uint32_t pos;    // packed: LDS offset of walk (s, j) (16 bits) | its length << 16 | node index << 24
     uint32_t t;      // steps taken
     uint32_t o, d;   // current node: slot offset in E and in-degree
     WalkDraws rng;
     bool busy;
-    uint32_t ph;     // stitched: 0 head; entering the tail: 1 node id, 2 pool offsets,
-                     // 3 segment length; 4 tail step; next segment: 5 chain, 6 its length
-    uint32_t tsig, tm, tu, tseg, tsl;   // stitched tail: entry slot, chain index, position, segment, its length
-    uint32_t aux;    // stratified: class of walk (s, j) << 8 | class of walk (v, j)
+    uint32_t unused[6];
+    uint32_t aux;    // stratified: class of walk (s, j) << 8 | class of walk (v, j);
+                     // stitched: the tile entry of walk (s, j)
 };
 
 constexpr uint32_t ITEM_CHUNK = 64;
+// Pairs waiting for their stitched tails, per wave: a ring, a power of two
+// above 63 + 64 (a wave drains 64 as soon as 64 wait, after each slot's push).
+constexpr uint32_t TAIL_Q = 128;
 
 // ------------------------------------------------- walk shuffle (stratified)
 //

@@ -44,9 +44,11 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t val) {
 }
 
 // One thread per edge; the owning row is found by binary search over in_off.
+// dbar[u] counts the rows that list u (the pool sizes of the stitched index
+// follow it).
 __global__ void k_edges(const int32_t *__restrict__ off, const int32_t *__restrict__ src,
                         int32_t n, int64_t m, const uint2 *__restrict__ nodes,
-                        uint2 *__restrict__ E) {
+                        uint2 *__restrict__ E, uint32_t *__restrict__ dbar) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     int32_t lo = 0, hi = n;  // find v with off[v] <= e < off[v+1]
@@ -58,7 +60,9 @@ __global__ void k_edges(const int32_t *__restrict__ off, const int32_t *__restri
     // share its offset and lose the search)
     const int32_t v = lo;
     const uint2 row = nodes[v];
-    E[(int64_t)row.x + (e - off[v])] = nodes[src[e]];
+    const int32_t u = src[e];
+    E[(int64_t)row.x + (e - off[v])] = nodes[u];
+    atomicAdd(&dbar[u], 1u);
 }
 
 }  // namespace
@@ -92,6 +96,7 @@ static void graph_release(simrank_graph *g) {
     device_free(g->E);
     device_free(g->node_of);
     device_free(g->active);
+    device_free(g->dbar);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
@@ -158,6 +163,7 @@ extern "C" int simrank_load_graph(int32_t n, int64_t m, const int32_t *in_off,
                              &g->bytes));
         SRK_TRY(device_alloc((void **)&g->active, sizeof(int32_t) * (size_t)(n_active ? n_active : 1),
                              &g->bytes));
+        SRK_TRY(device_alloc((void **)&g->dbar, sizeof(uint32_t) * (size_t)n, &g->bytes));
         SRK_TRY(device_alloc((void **)&d_off, sizeof(int32_t) * (size_t)(n + 1), nullptr));
         SRK_TRY(device_alloc((void **)&d_src, sizeof(int32_t) * (size_t)(m ? m : 1), nullptr));
         SRK_TRY(device_alloc((void **)&d_slots, sizeof(uint32_t) * (size_t)n, nullptr));
@@ -174,9 +180,11 @@ extern "C" int simrank_load_graph(int32_t n, int64_t m, const int32_t *in_off,
         SRK_TRY(scan_exclusive_u32_to_i64(d_has, n, d_apos, d_tot + 1, st));
         k_fill_u32<<<1024, 256, 0, st>>>(g->node_of, g->m_slots, NIL);
         k_fill_u32<<<1024, 256, 0, st>>>((uint32_t *)g->E, 2 * g->m_slots, NIL);
+        k_fill_u32<<<1024, 256, 0, st>>>(g->dbar, n, 0u);
         k_nodes<<<grid_for(n, 256), 256, 0, st>>>(d_off, d_o, n, d_apos, g->nodes, g->node_of,
                                                    g->active);
-        if (m) k_edges<<<grid_for(m, 256), 256, 0, st>>>(d_off, d_src, n, m, g->nodes, g->E);
+        if (m) k_edges<<<grid_for(m, 256), 256, 0, st>>>(d_off, d_src, n, m, g->nodes, g->E,
+                                                        g->dbar);
         SRK_TRYHIP(hipGetLastError());
         int64_t tot[2];
         SRK_TRYHIP(hipMemcpyAsync(tot, d_tot, sizeof(tot), hipMemcpyDeviceToHost, st));

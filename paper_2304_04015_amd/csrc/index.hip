@@ -3,8 +3,9 @@
 // long walks from short ones in few rounds (Theorem 2, Section 4.1).
 //
 //   P(y)      = ceil(kappa * dbar(y)), dbar(y) = number of in-edge rows that
-//               list y (walks arrive at y along those edges); pools are
-//               sampled with replacement, so they never run out
+//               list y (walks arrive at y along those edges; counted once at
+//               graph ingest); pools are sampled with replacement, so they
+//               never run out
 //   slot sigma = pool_off[y] + i, i < P(y): a sqrt(c)-walk of at most 2^k
 //               steps from y keyed (y, i, t, 1) under the index seed
 //   succ(sigma) = pool_off[z] + pick(draw(y, i, 0, 3).x0, P(z)) if the
@@ -16,6 +17,14 @@
 #include "common.hpp"
 #include "philox.hpp"
 
+// Segments in flight per lane and consecutive slots per wave of k_segments.
+#ifndef SRK_SEG_SLOTS
+#define SRK_SEG_SLOTS 3
+#endif
+#ifndef SRK_SEG_CHUNK
+#define SRK_SEG_CHUNK 2048
+#endif
+
 namespace srk {
 namespace {
 
@@ -23,16 +32,6 @@ __global__ void k_fill_u32i(uint32_t *__restrict__ p, int64_t n, uint32_t val) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = val;
-}
-
-// dbar(y): one thread per edge slot; dummy slots of nodes without in-edges
-// carry o = NIL.
-__global__ void k_dbar(const uint2 *__restrict__ E, const uint32_t *__restrict__ node_of,
-                       int64_t m_slots, uint32_t *__restrict__ dbar) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m_slots) return;
-    const uint32_t o = E[e].x;
-    if (o != NIL) atomicAdd(&dbar[node_of[o]], 1u);
 }
 
 __global__ void k_pool_sizes(const uint32_t *__restrict__ dbar, int32_t n, double kappa,
@@ -70,58 +69,158 @@ struct SegArgs {
     uint32_t T;
     int32_t seg_len, width;
     int64_t segments;
+    int64_t chunk;       // consecutive slots per wave
 };
 
-// One segment per thread.  Consecutive slots belong to the same node y, so a
-// wave's first steps share y's row.  The segment's positions are kept in
-// registers and written four at a time (one 16-byte store per lane: a wave's
-// rows form one contiguous span) instead of one scattered word per step.
+// One segment being built on a lane.
+struct SegSlot {
+    uint32_t sig;        // its slot
+    uint32_t y;          // the node whose pool holds it
+    uint32_t o, d;       // current position (slot offset in E, in-degree)
+    uint32_t t;          // moves made
+    uint32_t ph;         // SEG_*: what the slot waits for
+    WalkDraws w;         // the segment's draws (walk index = i, its rank in y's pool)
+};
+
+// Phases of a segment slot.  Every phase but IDLE issues one load per
+// iteration, so a lane keeps NS independent loads in flight.
+enum : uint32_t {
+    SEG_IDLE = 0,
+    SEG_OWNER = 1,   // read owner[sig]                    -> y
+    SEG_START = 2,   // read pool_off[y] and nodes[y]       -> i, first position
+    SEG_WALK = 3,    // one step: draw, then read E[o + pick] -> next position
+    SEG_END = 4,     // the segment made all 2^k moves: read node_of[o] -> z
+    SEG_SUCC = 5     // read pool_off[z], pool_off[z + 1]  -> successor slot
+};
+
+// Segments of the index.  Each wave builds a chunk of consecutive slots; every
+// lane keeps NS segments in flight and takes the next slot of the chunk as soon
+// as one of its segments is finished (ballot + rank), so lanes do not idle while
+// the longest segment of a wave is still walking, and every lane has NS
+// independent loads outstanding per iteration.  Consecutive slots belong to the
+// same node y, so the first steps of a chunk share rows in the CU's L1.  A
+// segment's row is first filled with NIL and then receives one position per
+// move.  succ(sigma) is picked from the pool of the node where an open segment
+// ends.
+template <int NS>
 __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
-    const int64_t sigma = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t len = 0;
-    if (sigma < a.segments) {
-        const uint32_t y = a.owner[sigma];
-        const uint32_t i = (uint32_t)(sigma - a.pool_off[y]);
-        uint32_t *row = a.seg + (size_t)sigma * a.seg_len;
-        uint2 cur = a.nodes[y];
-        WalkDraws w = walk_draws_begin(y, i, a.key, DOM_SEGMENT);
-        bool alive = true;
-        for (int32_t t0 = 0; t0 < a.seg_len; t0 += 4) {
-            uint32_t p[4] = {NIL, NIL, NIL, NIL};
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t c0 = wave * a.chunk;
+    if (c0 >= a.segments) return;
+    const int64_t c1 = min(c0 + a.chunk, a.segments);
+    int64_t cursor = c0;
+    const uint32_t L = (uint32_t)a.seg_len;
+    uint32_t moves = 0;
+    SegSlot sl[NS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (alive && t0 + q < a.seg_len) {
-                    const uint2 x = walk_draw_next(w, a.key);   // step t0 + q + 1
-                    if (x.x >= a.T || cur.y == 0) {
-                        alive = false;
-                    } else {
-                        cur = a.E[cur.x + pick32(x.y, cur.y)];
-                        p[q] = cur.x;
-                        ++len;
-                    }
+    for (int q = 0; q < NS; ++q) sl[q].ph = SEG_IDLE;
+
+    for (;;) {
+        // refill idle slots from the wave's chunk
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const uint64_t need = __ballot(sl[q].ph == SEG_IDLE);
+            const int64_t left = c1 - cursor;
+            if (need == 0ull || left <= 0) continue;
+            const uint32_t want = (uint32_t)__popcll(need);
+            const uint32_t take = left < (int64_t)want ? (uint32_t)left : want;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (((need >> lane) & 1ull) && rank < take) {
+                sl[q].sig = (uint32_t)(cursor + rank);
+                sl[q].ph = SEG_OWNER;
+            }
+            cursor += take;
+        }
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) any |= sl[q].ph != SEG_IDLE;
+        if (__ballot(any) == 0ull) break;   // the chunk is done
+
+        // issue: one load per busy slot
+        uint2 e[NS];
+        uint32_t u[NS];
+        int64_t b0[NS], b1[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            SegSlot &s = sl[q];
+            switch (s.ph) {
+            case SEG_OWNER: u[q] = a.owner[s.sig]; break;
+            case SEG_START: b0[q] = a.pool_off[s.y]; e[q] = a.nodes[s.y]; break;
+            case SEG_WALK: {
+                const uint2 x = walk_draw_next(s.w, a.key);   // step t + 1
+                if (x.x >= a.T || s.d == 0u) {
+                    s.ph = SEG_IDLE;                           // closed before 2^k moves
+                    a.seg_lens[s.sig] = (uint8_t)s.t;
+                    a.succ[s.sig] = NIL;
+                    if (a.width == 1) a.chain[s.sig] = s.sig;
+                } else {
+                    e[q] = a.E[s.o + pick32(x.y, s.d)];
                 }
+                break;
             }
-            if (a.seg_len >= 4) {
-                *(uint4 *)(row + t0) = make_uint4(p[0], p[1], p[2], p[3]);
-            } else {
-                for (int32_t q = 0; q < a.seg_len; ++q) row[q] = p[q];
+            case SEG_END: u[q] = a.node_of[s.o]; break;
+            case SEG_SUCC: b0[q] = a.pool_off[s.y]; b1[q] = a.pool_off[s.y + 1]; break;
+            default: break;
             }
         }
-        a.seg_lens[sigma] = (uint8_t)len;
-        uint32_t nx = NIL;
-        if ((int32_t)len == a.seg_len) {
-            const uint32_t z = a.node_of[cur.x];
-            const int64_t b = a.pool_off[z];
-            const int64_t P = a.pool_off[z + 1] - b;
-            const uint4 x = philox4x32_10(y, i, 0u, DOM_SUCC, a.key);
-            nx = (uint32_t)(b + (int64_t)pick64(x.x, (uint64_t)P));
+        // consume
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            SegSlot &s = sl[q];
+            switch (s.ph) {
+            case SEG_OWNER:
+                s.y = u[q];
+                s.ph = SEG_START;
+                break;
+            case SEG_START: {
+                const uint32_t i = (uint32_t)((int64_t)s.sig - b0[q]);
+                s.w = walk_draws_begin(s.y, i, a.key, DOM_SEGMENT);
+                s.o = e[q].x;
+                s.d = e[q].y;
+                s.t = 0;
+                uint32_t *row = a.seg + (size_t)s.sig * L;
+                if (L >= 4) {
+                    for (uint32_t k = 0; k < L; k += 4)
+                        *(uint4 *)(row + k) = make_uint4(NIL, NIL, NIL, NIL);
+                } else {
+                    for (uint32_t k = 0; k < L; ++k) row[k] = NIL;
+                }
+                s.ph = SEG_WALK;
+                break;
+            }
+            case SEG_WALK:
+                s.o = e[q].x;
+                s.d = e[q].y;
+                a.seg[(size_t)s.sig * L + s.t] = s.o;
+                ++s.t;
+                ++moves;
+                if (s.t == L) s.ph = SEG_END;
+                break;
+            case SEG_END:
+                // keep the walk index for the successor draw; y becomes z
+                s.o = s.y;      // the segment's own node, for the draw below
+                s.y = u[q];
+                s.ph = SEG_SUCC;
+                break;
+            case SEG_SUCC: {
+                const uint32_t i = s.w.j;
+                const uint4 x = philox4x32_10(s.o, i, 0u, DOM_SUCC, a.key);
+                const uint32_t nx = (uint32_t)(b0[q] + (int64_t)pick64(x.x, (uint64_t)(b1[q] - b0[q])));
+                a.seg_lens[s.sig] = (uint8_t)L;
+                a.succ[s.sig] = nx;
+                if (a.width == 1) a.chain[s.sig] = s.sig;
+                s.ph = SEG_IDLE;
+                break;
+            }
+            default: break;
+            }
         }
-        a.succ[sigma] = nx;
-        if (a.width == 1) a.chain[sigma] = (uint32_t)sigma;   // no doubling round writes it
     }
-    unsigned long long m = len;
+    unsigned long long m = moves;
     for (int d = 32; d > 0; d >>= 1) m += __shfl_xor(m, d, 64);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(a.moves, m);
+    if (lane == 0 && m) atomicAdd(a.moves, m);
 }
 
 // Round r of pointer doubling: chain[s][h + i] = chain[J[s]][i] for i < h = 2^r,
@@ -230,15 +329,17 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
     ix->seed = p->seed;
     const int32_t n = g->n;
     int rc = SIMRANK_OK;
-    uint32_t *dbar = nullptr, *owner = nullptr, *Ja = nullptr, *Jb = nullptr, *flag = nullptr;
+    uint32_t *owner = nullptr, *Ja = nullptr, *Jb = nullptr, *flag = nullptr;
     int64_t *P = nullptr, *tot = nullptr;
     unsigned long long *moves = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, es0 = nullptr, es1 = nullptr;
     auto cleanup = [&]() {
-        device_free(dbar); device_free(owner); device_free(Ja); device_free(Jb);
+        device_free(owner); device_free(Ja); device_free(Jb);
         device_free(flag); device_free(P); device_free(tot); device_free(moves);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        if (es0) (void)hipEventDestroy(es0);
+        if (es1) (void)hipEventDestroy(es1);
     };
     auto bail = [&](int code) {
         cleanup();
@@ -260,18 +361,17 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
 
     IX_HIP(hipEventCreate(&e0));
     IX_HIP(hipEventCreate(&e1));
-    IX_TRY(device_alloc((void **)&dbar, 4 * (size_t)n, nullptr));
+    IX_HIP(hipEventCreate(&es0));
+    IX_HIP(hipEventCreate(&es1));
     IX_TRY(device_alloc((void **)&P, 8 * (size_t)n, nullptr));
     IX_TRY(device_alloc((void **)&tot, 8 * 2, nullptr));
     IX_TRY(device_alloc((void **)&flag, 4, nullptr));
     IX_TRY(device_alloc((void **)&moves, 8, nullptr));
     IX_TRY(device_alloc((void **)&ix->pool_off, 8 * ((size_t)n + 1), &ix->bytes));
     IX_HIP(hipEventRecord(e0, st));
-    k_fill_u32i<<<1024, 256, 0, st>>>(dbar, n, 0u);
     k_fill_u32i<<<1, 64, 0, st>>>(flag, 1, 0u);
     k_fill_u32i<<<1, 64, 0, st>>>((uint32_t *)moves, 2, 0u);
-    k_dbar<<<grid_for(g->m_slots, 256), 256, 0, st>>>(g->E, g->node_of, g->m_slots, dbar);
-    k_pool_sizes<<<grid_for(n, 256), 256, 0, st>>>(dbar, n, p->kappa, P, flag);
+    k_pool_sizes<<<grid_for(n, 256), 256, 0, st>>>(g->dbar, n, p->kappa, P, flag);
     IX_TRY(scan_exclusive_i64(P, n, ix->pool_off, tot, st));
     IX_HIP(hipMemcpyAsync(ix->pool_off + n, tot, 8, hipMemcpyDeviceToDevice, st));
     int64_t total = 0;
@@ -298,8 +398,11 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
         IX_TRY(scan_inclusive_max_u32(owner, total, st));
         SegArgs sa{g->nodes, g->E, g->node_of, ix->pool_off, owner, ix->seg, ix->seg_lens,
                    ix->succ, ix->chain, moves, make_key(p->seed), ix->T, ix->seg_len, ix->width,
-                   total};
-        k_segments<<<grid_for(total, 256), 256, 0, st>>>(sa);
+                   total, SRK_SEG_CHUNK};
+        const int64_t waves = (total + SRK_SEG_CHUNK - 1) / SRK_SEG_CHUNK;
+        IX_HIP(hipEventRecord(es0, st));
+        k_segments<SRK_SEG_SLOTS><<<grid_for(waves * 64, 256), 256, 0, st>>>(sa);
+        IX_HIP(hipEventRecord(es1, st));
         const uint32_t *J = ix->succ;
         for (int32_t r = 0; r < ix->levels; ++r) {
             uint32_t *Jn = (r + 1 < ix->levels) ? ((r & 1) ? Jb : Ja) : nullptr;
@@ -313,9 +416,15 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
     unsigned long long mv = 0;
     IX_HIP(hipMemcpyAsync(&mv, moves, 8, hipMemcpyDeviceToHost, st));
     IX_HIP(hipStreamSynchronize(st));
-    float ms = 0.f;
+    float ms = 0.f, sms = 0.f, dms = 0.f;
     IX_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (total > 0) {
+        IX_HIP(hipEventElapsedTime(&sms, es0, es1));
+        IX_HIP(hipEventElapsedTime(&dms, es1, e1));
+    }
     ix->build_ms = ms;
+    ix->segments_ms = sms;
+    ix->doubling_ms = dms;
     ix->build_moves = mv;
     cleanup();
     g->index = ix;
@@ -335,6 +444,8 @@ extern "C" int simrank_index_info(const simrank_graph *g, simrank_index_summary 
     out->levels = ix->levels;
     out->build_ms = ix->build_ms;
     out->build_moves = ix->build_moves;
+    out->segments_ms = ix->segments_ms;
+    out->doubling_ms = ix->doubling_ms;
     return SIMRANK_OK;
 }
 

@@ -43,21 +43,24 @@ __global__ void k_init(const QueryDesc *__restrict__ qd, unsigned long long *__r
 // s_hat(s, v) = cnt[v] / R; the pair (s, s) meets at step 0 for every j.
 // Stratified (Algorithm 2): s~(s, v) = wsum[v] 2^-40 / z, and the variant
 // normalised by the N pairs, s~(s, v) N / z; both are 1 at v = s.
+__device__ __forceinline__ void estimate_one(const QueryDesc &d, int64_t v) {
+    if (strat_kind(d.kind)) {
+        const double x = (double)d.wsum[v] * 9.094947017729282379150390625e-13;   // 2^-40
+        const double e = x / d.z;
+        if (d.out) d.out[v] = (v == d.s) ? 1.0 : e;
+        if (d.out_n) d.out_n[v] = (v == d.s) ? 1.0 : e * ((double)d.R / d.z);
+        return;
+    }
+    if (v == d.s) d.cnt[v] = (uint32_t)d.R;
+    if (d.out) d.out[v] = (v == d.s) ? 1.0 : (double)d.cnt[v] / (double)d.R;
+}
+
 // grid (x over nodes, y = query)
 __global__ void k_estimate(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.y];
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        if (strat_kind(d.kind)) {
-            const double x = (double)d.wsum[v] * 9.094947017729282379150390625e-13;   // 2^-40
-            const double e = x / d.z;
-            if (d.out) d.out[v] = (v == d.s) ? 1.0 : e;
-            if (d.out_n) d.out_n[v] = (v == d.s) ? 1.0 : e * ((double)d.R / d.z);
-            continue;
-        }
-        if (v == d.s) d.cnt[v] = (uint32_t)d.R;
-        if (d.out) d.out[v] = (v == d.s) ? 1.0 : (double)d.cnt[v] / (double)d.R;
-    }
+         v += (int64_t)gridDim.x * blockDim.x)
+        estimate_one(d, v);
 }
 
 // ------------------------------------------------------------ source walks
@@ -222,12 +225,77 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 // then a tail read from the segment index) or K_STRAT (the stratified
 // estimator's fixed-length walks: walk j of v has the class of slot pi_v(j),
 // takes no stop draw, and a meet adds Lemma 5's weight of the two classes).
+//
+// Stitched walks run their private heads (the first 2^k steps, the plain
+// walk's own draws) exactly as plain walks do.  A pair whose head made all its
+// moves with both walks alive and apart is not continued on its slot: it goes
+// to the wave's tail queue in LDS (unit-local node, tile entry, position) and
+// the slot takes a new pair.  Whenever the queue holds a wave's worth of
+// pairs, and once more when the unit's pairs are done, the wave follows 64
+// queued tails at once through the index (the end node's pool slot drawn with
+// (v, j, 0, 2), then the chain of segments), comparing with the tile in LDS.
+// Heads thus keep the plain kernel's shape and rate, and the rarer tails do
+// not hold slots of their own.
 
-template <int KIND, int NS>
+// Serving (STREAM): wave 0 of a block claims the next unit from the ring:
+// among published entries of the kernel's kind with unclaimed units, the
+// oldest (smallest seq); the claim is a compare-and-swap of its (seq, claimed)
+// word.  A failed swap means another block took that unit: look again.  The
+// entry's words are read with device-coherent atomic loads and no fence: the
+// block fences only when it moves to a request it has not worked on (below),
+// so its caches keep the graph's rows from unit to unit.  A claim whose unit
+// lies beyond the entry's size as read again after the swap (possible only
+// if the scan read a size older than the entry's publication) is dropped.
+// *o_slot = RING_MAX when no entry has units left.
+template <int KIND>
+__device__ void ring_claim(const StreamRing &ring, int lane, uint32_t *o_slot, uint32_t *o_unit,
+                           uint32_t *o_seq) {
+    for (;;) {
+        unsigned long long key = ~0ull, c = 0ull;
+        if (lane < ring.entries) {
+            RingCtl &e = ring.ctl[lane];
+            c = __hip_atomic_load(&e.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t seq = (uint32_t)(c >> 32), cl = (uint32_t)c;
+            if (seq != 0u &&
+                __hip_atomic_load(&e.kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KIND &&
+                cl < __hip_atomic_load(&e.n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                key = ((unsigned long long)seq << 32) | (uint32_t)lane;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off, 64);
+            key = o < key ? o : key;
+        }
+        if (key == ~0ull) {
+            if (lane == 0) *o_slot = RING_MAX;
+            return;
+        }
+        const int best = (int)(uint32_t)key;
+        const unsigned long long cb = __shfl(c, best, 64);
+        unsigned long long prev = 0ull;
+        uint32_t nu = 0u;
+        if (lane == 0) {
+            prev = atomicCAS(&ring.ctl[best].claim, cb, cb + 1ull);
+            nu = __hip_atomic_load(&ring.ctl[best].n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        prev = __shfl(prev, 0, 64);
+        nu = __shfl(nu, 0, 64);
+        if (prev == cb && (uint32_t)cb < nu) {
+            if (lane == 0) {
+                *o_slot = (uint32_t)best;
+                *o_unit = (uint32_t)cb;
+                *o_seq = (uint32_t)(cb >> 32);
+            }
+            return;
+        }
+    }
+}
+
+template <int KIND, int NS, bool STREAM>
 __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *__restrict__ qd, int32_t nq,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t *__restrict__ cursor,
-                                                     unsigned long long *__restrict__ counters) {
+                                                     unsigned long long *__restrict__ counters,
+                                                     StreamRing ring) {
     constexpr bool STITCHED = KIND == K_STITCHED;
     constexpr bool STRAT = KIND == K_STRAT;
     constexpr int TJ = tile_j_of(KIND), TN = tile_nodes_of(KIND);
@@ -237,7 +305,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
     __shared__ uint32_t s_cnt[STRAT ? 1 : MEET_VB];
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
-    __shared__ uint32_t s_unit, s_item;
+    __shared__ uint32_t s_unit, s_item, s_slot, s_seq, s_last;
     // stratified: classes of the tile's source walks, class starts, the
     // shuffle keys of the unit's nodes, weighted sums
     __shared__ uint8_t s_cls[STRAT ? TJ : 1];
@@ -245,29 +313,50 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
     __shared__ uint4 s_fk[STRAT ? MEET_VB : 1];
     __shared__ unsigned long long s_w[STRAT ? MEET_VB : 1];
     __shared__ uint2 s_q[STRAT ? meet_block_of(KIND) : 1];   // 64 prepared pairs per wave
+    // stitched: per-wave ring of pairs waiting for their tails, (vl << 16 | k, o)
+    __shared__ uint2 s_tq[STITCHED ? (meet_block_of(KIND) / 64) * TAIL_Q : 1];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t n_units = ustart[nq];
+    const uint32_t n_units = STREAM ? 0u : ustart[nq];
+    uint32_t tq_head = 0, tq_tail = 0;   // stitched: the wave's tail ring (wave-uniform)
     uint32_t cur_q = 0xffffffffu, cur_tile = 0xffffffffu;
     uint32_t K = 0;
     uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_tail = 0, st_pairs = 0;
 
     for (;;) {
-        if (threadIdx.x == 0) s_unit = atomicAdd(cursor, 1u);
-        __syncthreads();
-        const uint32_t unit = s_unit;
-        if (unit >= n_units) break;
-        // query of the unit: the last q with ustart[q] <= unit
-        int32_t lo = 0, hi = nq;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (ustart[mid] <= unit) lo = mid; else hi = mid;
+        uint32_t unit = 0, tag_s = 0;
+        if constexpr (STREAM) {
+            if (threadIdx.x < 64) ring_claim<KIND>(ring, lane, &s_slot, &s_unit, &s_seq);
+            __syncthreads();
+            if (s_slot >= (uint32_t)RING_MAX) break;
+            unit = s_unit;
+            tag_s = s_seq;
+            // a request this block has not worked on: see its descriptor and
+            // buffers as its publication left them
+            if (tag_s != cur_q) __threadfence();
+        } else {
+            if (threadIdx.x == 0) s_unit = atomicAdd(cursor, 1u);
+            __syncthreads();
+            unit = s_unit;
+            if (unit >= n_units) break;
+        }
+        int32_t lo = 0;
+        if constexpr (STREAM) {
+            lo = (int32_t)s_slot;
+        } else {
+            // query of the unit: the last q with ustart[q] <= unit
+            int32_t hi = nq;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (ustart[mid] <= unit) lo = mid; else hi = mid;
+            }
         }
         const int32_t q = lo;
+        const uint32_t local = STREAM ? unit : unit - ustart[q];
+        const uint32_t tag = STREAM ? tag_s : (uint32_t)q;
         const QueryDesc &d = qd[q];
         const int32_t n_chunks = (int32_t)uni((uint32_t)d.n_chunks);
         const int32_t vb = (int32_t)uni((uint32_t)d.vb);
-        const uint32_t local = unit - ustart[q];
         const uint32_t tile = local / (uint32_t)n_chunks;
         const uint32_t chunk = local - tile * (uint32_t)n_chunks;
         const PhiloxKey key{uni(d.k0), uni(d.k1)};
@@ -275,7 +364,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
         const int32_t src = (int32_t)uni((uint32_t)d.s);
         const uint32_t NN = uni((uint32_t)d.R), sa = uni((uint32_t)d.sa), sb = uni((uint32_t)d.sb);
         const int32_t phi = (int32_t)uni((uint32_t)d.L);
-        if ((uint32_t)q != cur_q || tile != cur_tile) {
+        if (tag != cur_q || tile != cur_tile) {
             const uint32_t k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
             const uint32_t nb = d.joff[k0], ne = d.joff[k1];
             K = k1 - k0;
@@ -290,7 +379,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             if (STRAT)
                 for (uint32_t i = threadIdx.x; i < (uint32_t)phi + 2; i += blockDim.x)
                     s_ccum[i] = d.tab->ccum[i];
-            cur_q = (uint32_t)q;
+            cur_q = tag;
             cur_tile = tile;
         }
         const int32_t vbase = (int32_t)chunk * vb;
@@ -316,10 +405,49 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
 
         Slot sl[NS];
 #pragma unroll
-        for (int qq = 0; qq < NS; ++qq) {
-            sl[qq].busy = false;
-            sl[qq].ph = 0;
-        }
+        for (int qq = 0; qq < NS; ++qq) sl[qq].busy = false;
+
+        // Stitched: follow the tails of the first `c` queued pairs (one per
+        // lane) through the index; meets go to the unit's LDS counters.
+        auto drain_tails = [&](uint32_t c) {
+            if (lane < (int)c) {
+                const uint2 r = s_tq[wave * TAIL_Q + ((tq_head + (uint32_t)lane) & (TAIL_Q - 1))];
+                const uint32_t vl = r.x >> 16, k = r.x & 0xffffu;
+                const uint32_t base = s_off[k];
+                const uint32_t len = (uint32_t)s_off[k + 1] - base;
+                const uint32_t seg_len = (uint32_t)d.ix.seg_len, width = (uint32_t)d.ix.width;
+                const uint32_t y = d.ix.node_of[r.y];
+                const int64_t pb = d.ix.pool_off[y];
+                const int64_t pe = d.ix.pool_off[y + 1];
+                const uint4 x = philox4x32_10(s_vid[vl], s_j[k], 0u, DOM_ENTRY, key);
+                const uint32_t sigma = (uint32_t)(pb + (int64_t)pick64(x.x, (uint64_t)(pe - pb)));
+                const uint32_t *crow = d.ix.chain + (size_t)sigma * width;
+                uint32_t t = seg_len;
+                bool done = false;
+                for (uint32_t mm = 0; mm < width && !done; ++mm) {
+                    const uint32_t sg = crow[mm];
+                    if (sg == NIL) break;
+                    const uint32_t sln = d.ix.seg_lens[sg];
+                    const uint32_t *srow = d.ix.seg + (size_t)sg * seg_len;
+                    for (uint32_t u = 0; u < sln; ++u) {
+                        ++t;
+                        ++st_tail;
+                        if (srow[u] == s_nodes[base + t - 1]) {
+                            atomicAdd(&s_cnt[vl], 1u);
+                            ++st_meets;
+                            done = true;
+                            break;
+                        }
+                        if (t == len) {
+                            done = true;
+                            break;
+                        }
+                    }
+                    if (sln < seg_len) break;
+                }
+            }
+            tq_head += c;
+        };
 
         for (;;) {
             // ---- refill idle slots from the block's cursor; a lane whose item
@@ -428,7 +556,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                                 sl[qq].o = row.x;
                                 sl[qq].d = row.y;
                                 sl[qq].busy = true;
-                                sl[qq].ph = 0;
+                                if (STITCHED) sl[qq].aux = k;
                                 filled = true;
                                 ++st_pairs;
                             }
@@ -449,7 +577,12 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             // A refill round can hand out only pairs with nothing to walk: a
             // wave leaves only once the block's cursor is drained.
             if (__ballot(any) == 0ull) {
-                if (drained && qh == qn) break;
+                if (drained && qh == qn) {
+                    if constexpr (STITCHED) {
+                        while (tq_tail != tq_head) drain_tails(min(64u, tq_tail - tq_head));
+                    }
+                    break;
+                }
                 continue;
             }
 
@@ -460,7 +593,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             for (int qq = 0; qq < NS; ++qq) {
                 go[qq] = false;
                 at[qq] = 0;
-                if (sl[qq].busy && !(STITCHED && sl[qq].ph)) {
+                if (sl[qq].busy) {
                     ++sl[qq].t;
                     const uint2 x = walk_draw_next(sl[qq].rng, key);
                     ++st_draws;
@@ -472,26 +605,14 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                     }
                 }
             }
-            // one load per slot: a head step's gather, or the load its stitched
-            // tail phase needs, so that their latencies overlap
+            // all gathers of the lane's slots, then the compares
             uint2 e[NS];
-            uint32_t tv[NS];
-            int64_t tb[NS], te[NS];
 #pragma unroll
-            for (int qq = 0; qq < NS; ++qq) {
+            for (int qq = 0; qq < NS; ++qq)
                 if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
-                if (STITCHED && sl[qq].busy && sl[qq].ph) {
-                    const Slot &w = sl[qq];
-                    switch (w.ph) {
-                    case 1: tv[qq] = d.ix.node_of[w.o]; break;
-                    case 2: tb[qq] = d.ix.pool_off[w.tsig]; te[qq] = d.ix.pool_off[w.tsig + 1]; break;
-                    case 3:
-                    case 6: tv[qq] = d.ix.seg_lens[w.tseg]; break;
-                    case 4: tv[qq] = d.ix.seg[(size_t)w.tseg * d.ix.seg_len + w.tu]; break;
-                    default: tv[qq] = d.ix.chain[(size_t)w.tsig * d.ix.width + w.tm + 1]; break;
-                    }
-                }
-            }
+            bool tails[NS];
+#pragma unroll
+            for (int qq = 0; qq < NS; ++qq) tails[qq] = false;
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
                 if (!go[qq]) continue;
@@ -510,63 +631,21 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                 } else if (w.t == len || w.d == 0u) {
                     w.busy = false;
                 } else if (STITCHED && w.t == (uint32_t)d.ix.seg_len) {
-                    w.ph = 1;   // the head made all its moves: enter a pool slot of this node
+                    w.busy = false;   // the head made all its moves: its tail is queued
+                    tails[qq] = true;
                 }
             }
-            // ---- stitched tails: entry slot, then one step read from the index
-            // per iteration, and the chain of segments
-            if (STITCHED) {
+            if constexpr (STITCHED) {
+                // queue the pairs whose heads ended open (tails[qq]), then
+                // follow queued tails while a wave's worth is waiting
 #pragma unroll
                 for (int qq = 0; qq < NS; ++qq) {
-                    Slot &w = sl[qq];
-                    if (!(w.busy && w.ph) || go[qq]) continue;
-                    switch (w.ph) {
-                    case 1:   // the end node's id
-                        w.tsig = tv[qq];
-                        w.ph = 2;
-                        break;
-                    case 2: { // its pool: slot picked by draw (v, j, 0, DOM_ENTRY)
-                        const uint4 x = philox4x32_10(s_vid[w.pos >> 24], w.rng.j, 0u, DOM_ENTRY, key);
-                        w.tsig = (uint32_t)(tb[qq] + (int64_t)pick64(x.x, (uint64_t)(te[qq] - tb[qq])));
-                        w.tseg = w.tsig;
-                        w.tm = 0;
-                        w.ph = 3;
-                        break;
-                    }
-                    case 3:
-                    case 6:   // a segment's length
-                        w.tsl = tv[qq];
-                        w.tu = 0;
-                        w.ph = 4;
-                        if (w.tsl == 0u) w.busy = false;
-                        break;
-                    case 4: { // one tail step
-                        ++w.t;
-                        ++st_tail;
-                        w.o = tv[qq];
-                        ++w.tu;
-                        const uint32_t base = w.pos & 0xffffu, len = (w.pos >> 16) & 0xffu;
-                        if (w.o == s_nodes[base + w.t - 1]) {
-                            atomicAdd(&s_cnt[w.pos >> 24], 1u);
-                            ++st_meets;
-                            w.busy = false;
-                        } else if (w.t == len) {
-                            w.busy = false;
-                        } else if (w.tu == w.tsl) {
-                            if (w.tsl < (uint32_t)d.ix.seg_len || w.tm + 1 >= (uint32_t)d.ix.width)
-                                w.busy = false;
-                            else
-                                w.ph = 5;
-                        }
-                        break;
-                    }
-                    default:  // the chain's next segment
-                        ++w.tm;
-                        w.tseg = tv[qq];
-                        if (w.tseg == NIL) w.busy = false;
-                        else w.ph = 6;
-                        break;
-                    }
+                    const uint64_t m = __ballot(tails[qq]);
+                    if (tails[qq])
+                        s_tq[wave * TAIL_Q + ((tq_tail + lane_rank(m)) & (TAIL_Q - 1))] =
+                            make_uint2(((sl[qq].pos >> 24) << 16) | sl[qq].aux, sl[qq].o);
+                    tq_tail += (uint32_t)__popcll(m);
+                    if (tq_tail - tq_head >= 64u) drain_tails(64u);
                 }
             }
         }
@@ -580,7 +659,46 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
                 if (c) atomicAdd(&d.cnt[s_vid[i]], c);
             }
         }
+        if constexpr (STREAM) {
+            // the unit's work goes to its entry's counters; the block that
+            // finishes the entry's last unit writes the estimate and raises
+            // the entry's flag in host memory
+            unsigned long long w0 = st_moves, w1 = st_draws, w2 = st_meets, w3 = st_tail,
+                               w4 = st_pairs;
+            for (int dd = 32; dd > 0; dd >>= 1) {
+                w0 += __shfl_xor(w0, dd, 64);
+                w1 += __shfl_xor(w1, dd, 64);
+                w2 += __shfl_xor(w2, dd, 64);
+                w3 += __shfl_xor(w3, dd, 64);
+                w4 += __shfl_xor(w4, dd, 64);
+            }
+            unsigned long long *ec = ring.counters + (size_t)q * 8;
+            if (lane == 0) {
+                if (w0) atomicAdd(&ec[C_MOVES], w0);
+                if (w1) atomicAdd(&ec[C_DRAWS], w1);
+                if (w2) atomicAdd(&ec[C_MEETS], w2);
+                if (w3) atomicAdd(&ec[C_TAIL], w3);
+                if (w4) atomicAdd(&ec[C_PAIRS], w4);
+            }
+            st_moves = st_draws = st_meets = st_tail = st_pairs = 0;
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t old = atomicAdd(&ring.ctl[q].done, 1u);
+                s_last = (old + 1u == ring.ctl[q].n_units) ? 1u : 0u;
+            }
+            __syncthreads();
+            if (s_last) {
+                __threadfence();
+                for (int64_t v = threadIdx.x; v < d.n; v += blockDim.x) estimate_one(d, v);
+                __threadfence_system();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&ring.flags[q], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
     }
+    if constexpr (STREAM) return;
 
     unsigned long long v0 = st_moves, v1 = st_draws, v2 = st_meets, v3 = st_tail, v4 = st_pairs;
     for (int dd = 32; dd > 0; dd >>= 1) {
@@ -697,7 +815,7 @@ __global__ __launch_bounds__(256) void k_walks_strat(StratWalkArgs a) {
 #define SRK_MEET_SLOTS 2
 #endif
 #ifndef SRK_MEET_SLOTS_STITCHED
-#define SRK_MEET_SLOTS_STITCHED 1
+#define SRK_MEET_SLOTS_STITCHED 2
 #endif
 
 #ifndef SRK_MEET_SLOTS_STRAT
@@ -706,13 +824,13 @@ __global__ __launch_bounds__(256) void k_walks_strat(StratWalkArgs a) {
 
 // Resident blocks of a meet-kernel instance on the whole device (computed
 // once per process; a function-local static is initialised thread-safely).
-template <int KIND, int NS>
+template <int KIND, int NS, bool STREAM>
 int meet_grid_blocks() {
     static const int blocks = [] {
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<KIND, NS>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_meet<KIND, NS, STREAM>,
                                                            meet_block_of(KIND), 0);
         if (cus <= 0) cus = 256;
         if (per <= 0) per = 1;
@@ -723,11 +841,44 @@ int meet_grid_blocks() {
 
 template <int KIND, int NS>
 void launch_meet(const QuerySet &qs, hipStream_t st) {
-    const int blocks = (int)std::min<int64_t>(qs.units_bound[KIND], meet_grid_blocks<KIND, NS>());
+    const int blocks = (int)std::min<int64_t>(qs.units_bound[KIND], meet_grid_blocks<KIND, NS, false>());
     const uint32_t *ustart = qs.units + (size_t)KIND * (qs.nq + 1);
     uint32_t *cursor = qs.units + (size_t)N_KINDS * (qs.nq + 1) + KIND;
-    k_meet<KIND, NS><<<blocks, meet_block_of(KIND), 0, st>>>(qs.desc, qs.nq, ustart, cursor,
-                                                             qs.counters);
+    k_meet<KIND, NS, false><<<blocks, meet_block_of(KIND), 0, st>>>(qs.desc, qs.nq, ustart, cursor,
+                                                                    qs.counters, StreamRing{});
+}
+
+template <int KIND, int NS>
+void launch_meet_ring(const StreamRing &ring, hipStream_t st) {
+    k_meet<KIND, NS, true><<<meet_grid_blocks<KIND, NS, true>(), meet_block_of(KIND), 0, st>>>(
+        ring.desc, ring.entries, nullptr, nullptr, ring.counters, ring);
+}
+
+// Publication of a ring entry, the last kernel of its request's preparation:
+// the entry's unit count (tiles x node chunks, from the compaction), then its
+// (seq, 0) claim word.  A request with nothing to walk is finished here:
+// estimate, then its flag.  One block.
+__global__ __launch_bounds__(256) void k_publish(StreamRing ring, int32_t slot, uint32_t seq) {
+    const QueryDesc &d = ring.desc[slot];
+    const uint32_t nu = d.meta[2] * (uint32_t)d.n_chunks;
+    if (nu > 0u) {
+        if (threadIdx.x == 0) {
+            RingCtl &c = ring.ctl[slot];
+            c.n_units = nu;
+            c.done = 0u;
+            c.kind = d.kind;
+            c.seq = seq;
+            __threadfence();
+            __hip_atomic_store(&c.claim, (unsigned long long)seq << 32, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    for (int64_t v = threadIdx.x; v < d.n; v += blockDim.x) estimate_one(d, v);
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&ring.flags[slot], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 }  // namespace
@@ -810,6 +961,75 @@ int launch_query_set(const QuerySet &qs, hipStream_t st, hipEvent_t ev_meet0, hi
     k_estimate<<<dim3(gx_n, nq), 256, 0, st>>>(qs.desc);
     SRK_HIP(hipGetLastError());
     return SIMRANK_OK;
+}
+
+// Preparation of a served request in ring entry `slot`.  Every kernel is
+// small (one wave per SIMD at most) so that it fits beside a running
+// persistent meet kernel on the same CUs.
+int enqueue_ring_request(const QueryDesc &d, const StreamRing &ring, int32_t slot, uint32_t seq,
+                         hipStream_t st) {
+    QueryDesc *qd = ring.desc + slot;
+    unsigned long long *ctr = ring.counters + (size_t)slot * 8;
+    const unsigned gx_n = std::min<unsigned>(grid_for(std::max(d.n, 1), 256), 1024u);
+    k_set_desc<<<1, 1, 0, st>>>(qd, d);
+    k_init<<<dim3(gx_n, 1), 256, 0, st>>>(qd, ctr);
+    k_source_walks<<<dim3(grid_for(d.R, 256), 1), 256, 0, st>>>(qd, ctr);
+    k_compact<<<1, 256, 0, st>>>(qd);
+    k_publish<<<1, 256, 0, st>>>(ring, slot, seq);
+    SRK_HIP(hipGetLastError());
+    return SIMRANK_OK;
+}
+
+int launch_ring_meet(int kind, const StreamRing &ring, hipStream_t st) {
+    if (kind == K_PLAIN) launch_meet_ring<K_PLAIN, SRK_MEET_SLOTS>(ring, st);
+    else if (kind == K_STITCHED) launch_meet_ring<K_STITCHED, SRK_MEET_SLOTS_STITCHED>(ring, st);
+    else launch_meet_ring<K_STRAT, SRK_MEET_SLOTS_STRAT>(ring, st);
+    SRK_HIP(hipGetLastError());
+    return SIMRANK_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device bytes of one query's buffers (stratified queries: class table, walk
+// classes, weighted sums and the second estimate instead of counts).
+size_t request_bytes(const simrank_params &p, int mode, int32_t n) {
+    const size_t RL = (size_t)p.R * (size_t)p.L;
+    size_t b = align256(4 * RL) + align256((size_t)p.R) + align256(4 * (size_t)p.R) +
+               align256(4 * ((size_t)p.R + 1)) + align256(4 * RL) +
+               align256(4 * ((size_t)max_tiles_for(p.R, p.L) + 1)) + align256(32) +
+               align256(8 * (size_t)n);
+    if (mode == SIMRANK_MODE_STRATIFIED)
+        b += align256(sizeof(StratTab)) + align256((size_t)p.R) + 2 * align256(8 * (size_t)n);
+    else
+        b += align256(4 * (size_t)n);
+    return b;
+}
+
+void carve_request(const simrank_params &p, int mode, int32_t n, char *base, QueryDesc *d) {
+    char *cur = base;
+    auto take = [&](size_t b) {
+        char *r = cur;
+        cur += align256(b);
+        return r;
+    };
+    const size_t RL = (size_t)p.R * (size_t)p.L;
+    d->sw = (uint32_t *)take(4 * RL);
+    d->slen = (uint8_t *)take((size_t)p.R);
+    d->jj = (uint32_t *)take(4 * (size_t)p.R);
+    d->joff = (uint32_t *)take(4 * ((size_t)p.R + 1));
+    d->swc = (uint32_t *)take(4 * RL);
+    d->tiles = (uint32_t *)take(4 * ((size_t)max_tiles_for(p.R, p.L) + 1));
+    d->meta = (uint32_t *)take(32);
+    d->out = (double *)take(8 * (size_t)n);
+    if (mode == SIMRANK_MODE_STRATIFIED) {
+        d->tab = (const StratTab *)take(sizeof(StratTab));
+        d->scls = (uint8_t *)take((size_t)p.R);
+        d->wsum = (unsigned long long *)take(8 * (size_t)n);
+        d->out_n = (double *)take(8 * (size_t)n);
+        d->cnt = nullptr;
+    } else {
+        d->cnt = (uint32_t *)take(4 * (size_t)n);
+    }
 }
 
 // ---------------------------------------------------------------- host side

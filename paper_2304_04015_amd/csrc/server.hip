@@ -1,22 +1,34 @@
-// Serving: a request loop over one device-resident graph (and its index).
+// Serving: continuous batching of single-source requests over one
+// device-resident graph (and its stitched index).
 //
-// Requests are queued by simrank_server_submit and admitted by a worker thread
-// into slots as slots free up.  A slot is a workspace, device buffers for the
-// estimate and the counts, pinned host buffers and its own stream; the number
-// of slots is what the device-memory budget admits.  An admitted request is
-// enqueued whole on its slot's stream (query kernels, then the copy of its
-// results to the slot's pinned buffers, then an event), so requests that arrive
-// while others run are started as soon as a slot is free and their kernels
-// overlap on the device.  With group_max >= 2, plain or stitched requests that
-// share (mode, seed, c, cap) and are waiting together are admitted as one
-// query group (group.hip) into as many slots: one launch on the first slot's
-// stream walks each (v, j) once for all of them.  While a group runs, the
-// requests that arrive wait and form the next group.  Each result equals the
-// lone query's.
+// Requests are queued by simrank_server_submit and admitted by a worker
+// thread, oldest first, as soon as a ring entry and the request's own device
+// memory are free: each request takes request_bytes(R, L, n) from the
+// server's device pool (admission by memory, sized per request).  An admitted
+// request is prepared on the preparation stream (descriptor, source walks,
+// compaction) and published into the ring (common.hpp); persistent meet
+// kernels, one launch per kind after each round of admissions, alternating
+// between two streams, take work units from every published entry of their
+// kind, oldest first, and exit when no unit is left.  Requests that arrive
+// while others run are therefore admitted while the GPU works, and their
+// units join the running kernel's stream of units: their work overlaps the
+// running requests' on the device, and one request's last units overlap the
+// next one's first.  The block that finishes a request's last unit writes its
+// estimate and raises its flag in pinned host memory; the worker then copies
+// the results to the host (staging buffers, copy stream) and retires the
+// request.  Plain, stitched and stratified requests are served.
+//
+// With group_max >= 2, plain or stitched requests that share (mode, seed, c,
+// cap) and wait together are admitted as one query group (group.hip), which
+// walks each (v, j) once for all of them; a group is one launch on a worker
+// stream (one group in flight at a time).  Every result equals the lone
+// query's.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -32,6 +44,54 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// First-fit allocator over the server's device pool (offsets, 256-byte
+// granules); free blocks are merged with their neighbours.
+class PoolAlloc {
+  public:
+    explicit PoolAlloc(size_t bytes = 0) {
+        if (bytes) free_[0] = bytes;
+        total_ = bytes;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t peak() const { return peak_; }
+    size_t total() const { return total_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t total_ = 0, used_ = 0, peak_ = 0;
+};
+
 struct Request {
     uint64_t ticket = 0;
     simrank_query q{};
@@ -41,43 +101,56 @@ struct Request {
     int rc = 0;
     std::string err;
     double t_submit = 0, t_start = 0, t_done = 0;
-    std::vector<double> out;
+    std::vector<double> out, out_n;
     std::vector<uint32_t> cnt;
+    std::vector<unsigned long long> wsum;
     simrank_stats st{};
+    // worker-side
+    int32_t slot = -1;      // ring entry (lone requests)
+    uint32_t seq = 0;
+    size_t mem_off = 0, mem_bytes = 0;
+    QueryDesc d{};
+    int phase = 0;          // 1 on the device, 2 results being copied
+    int stage = -1;         // staging set while copying
+    bool grouped = false;
+    int32_t group_size = 1;
+    int32_t group_pos = 0;
 };
 
-struct Slot {
-    bool grouped = false;           // its request runs in the server's group
-    int32_t group_size = 1;
-    Workspace ws;
-    double *out_dev = nullptr;
-    uint32_t *cnt_dev = nullptr;
-    double *out_host = nullptr;     // pinned
-    uint32_t *cnt_host = nullptr;   // pinned
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    Request *req = nullptr;
+// Pinned host buffers for one request's results, with the copy's event.
+struct Staging {
+    double *out = nullptr, *out_n = nullptr;
+    uint32_t *cnt = nullptr;
+    unsigned long long *wsum = nullptr;
+    unsigned long long *ctr = nullptr;   // [8]
+    hipEvent_t ev = nullptr;
+    bool busy = false;
 };
 
 // The one group in flight: descriptors of its members and of the group
-// (pinned staging copies and device arrays), the unit tables and counters of
-// its launch, and the group's compaction buffers, sized for group_max members
-// of (max_R, max_L).
+// (pinned staging copies and device arrays), unit tables, counters and the
+// group's compaction buffers, sized for gmax members of (max_R, max_L).
 struct GroupRun {
     QueryDesc *desc_host = nullptr, *desc_dev = nullptr;
     GroupDesc *gdesc_host = nullptr, *gdesc_dev = nullptr;
     uint32_t *units = nullptr, *gunits = nullptr;
     unsigned long long *counters = nullptr;
     char *buffers = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the group's kernels
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<Request *> members;
     bool busy = false;
-    int32_t lead = -1;                         // slot whose stream runs it
 };
 
-// Requests of one group share the walks from every node.
 bool same_walks(const Request *a, const Request *b) {
     return a->mode == b->mode && a->q.seed == b->q.seed && a->p.T == b->p.T && a->p.L == b->p.L;
 }
+
+int kind_of(int mode) {
+    return mode == SIMRANK_MODE_STITCHED ? K_STITCHED : mode == SIMRANK_MODE_STRATIFIED ? K_STRAT
+                                                                                           : K_PLAIN;
+}
+
+constexpr int N_STAGING = 4;
 
 }  // namespace
 }  // namespace srk
@@ -87,8 +160,23 @@ using namespace srk;
 struct simrank_server {
     simrank_graph *g = nullptr;
     simrank_server_params prm{};
-    std::vector<Slot> slots;
-    int64_t slot_bytes = 0;
+    int32_t entries = 0;                 // ring entries (requests in flight), <= RING_MAX
+    int64_t slot_bytes = 0;              // bytes of a (max_R, max_L) plain request
+    // device pool and ring
+    char *pool = nullptr;
+    PoolAlloc alloc;
+    StreamRing ring{};
+    uint32_t *flags_host = nullptr;      // pinned, written by the device
+    StratTab *tabs_host = nullptr;       // pinned [RING_MAX] class tables of stratified requests
+    std::vector<Request *> slot_req;     // request in each ring entry
+    uint32_t next_seq = 1;
+    hipStream_t prep = nullptr, copy = nullptr, work[2] = {nullptr, nullptr};
+    int next_work = 0;
+    hipEvent_t ev_prep = nullptr;
+    Staging stage[N_STAGING];
+    GroupRun grp;
+    int32_t gmax = 0;
+    // host-side queue (mutex)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
@@ -96,41 +184,135 @@ struct simrank_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
-    uint64_t n_done = 0, n_failed = 0;
-    GroupRun grp;
-    int32_t gmax = 0;          // largest group the server forms (its buffers' size)
-    uint64_t n_groups = 0, n_grouped = 0;
+    uint64_t n_done = 0, n_failed = 0, n_groups = 0, n_grouped = 0, n_launches = 0;
+    int32_t inflight_peak = 0;
+    int32_t inflight = 0;                // worker-only
 };
 
-// Attaches a slot's workspace and result buffers to a descriptor.
-static void slot_buffers(Slot &sl, QueryDesc *d) {
-    d->sw = sl.ws.sw;
-    d->slen = sl.ws.slen;
-    d->jj = sl.ws.jj;
-    d->joff = sl.ws.joff;
-    d->swc = sl.ws.swc;
-    d->tiles = sl.ws.tiles;
-    d->meta = sl.ws.meta;
-    d->cnt = sl.cnt_dev;
-    d->out = sl.out_dev;
+// Enqueues the copies of a finished request's results to staging set k.
+static int start_copy(simrank_server *S, Request *r, int k) {
+    Staging &sg = S->stage[k];
+    const size_t n = (size_t)S->g->n;
+    hipStream_t st = S->copy;
+    const QueryDesc &d = r->d;
+    SRK_HIP(hipMemcpyAsync(sg.out, d.out, 8 * n, hipMemcpyDeviceToHost, st));
+    if (r->mode == SIMRANK_MODE_STRATIFIED) {
+        SRK_HIP(hipMemcpyAsync(sg.out_n, d.out_n, 8 * n, hipMemcpyDeviceToHost, st));
+        SRK_HIP(hipMemcpyAsync(sg.wsum, d.wsum, 8 * n, hipMemcpyDeviceToHost, st));
+    } else {
+        SRK_HIP(hipMemcpyAsync(sg.cnt, d.cnt, 4 * n, hipMemcpyDeviceToHost, st));
+    }
+    const unsigned long long *ctr = r->grouped ? S->grp.counters : S->ring.counters + (size_t)r->slot * 8;
+    SRK_HIP(hipMemcpyAsync(sg.ctr, ctr, 64, hipMemcpyDeviceToHost, st));
+    SRK_HIP(hipEventRecord(sg.ev, st));
+    sg.busy = true;
+    r->stage = k;
+    r->phase = 2;
+    return SIMRANK_OK;
 }
 
-// Enqueues the group of requests rs (2..group_max, equal walks) into the free
-// slots idx on the first slot's stream: descriptors, the query set with its
-// group, result copies, each slot's completion event.
-static int launch_group(simrank_server *S, const std::vector<Request *> &rs,
-                        const std::vector<int32_t> &idx) {
+// Moves a copied request's results from its staging set into the request.
+static void finish_copy(simrank_server *S, Request *r) {
+    Staging &sg = S->stage[r->stage];
+    const size_t n = (size_t)S->g->n;
+    r->out.assign(sg.out, sg.out + n);
+    if (r->mode == SIMRANK_MODE_STRATIFIED) {
+        r->out_n.assign(sg.out_n, sg.out_n + n);
+        r->wsum.assign(sg.wsum, sg.wsum + n);
+    } else {
+        r->cnt.assign(sg.cnt, sg.cnt + n);
+    }
+    unsigned long long c[8];
+    std::memcpy(c, sg.ctr, sizeof(c));
+    if (r->grouped)   // a grouped request reports its share of its group's work
+        for (unsigned long long &x : c) x /= (unsigned long long)r->group_size;
+    r->st = simrank_stats{};
+    r->st.pairs = (uint64_t)(S->g->n - 1) * (uint64_t)r->p.R;
+    r->st.pairs_walked = c[C_PAIRS];
+    r->st.moves = c[C_MOVES];
+    r->st.draws = c[C_DRAWS];
+    r->st.meets = c[C_MEETS];
+    r->st.tail_steps = c[C_TAIL];
+    r->st.source_moves = c[C_SRC_MOVES];
+    if (r->grouped) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, S->grp.ev0, S->grp.ev1) != hipSuccess) (void)hipGetLastError();
+        r->st.ms = r->st.meet_ms = ms;
+    } else {
+        // the request shares persistent kernels with others: its span from
+        // the start of its preparation to its completion, on the host clock
+        r->st.ms = r->st.meet_ms = 1e3 * (now_s() - r->t_start);
+    }
+    r->st.R = r->p.R;
+    r->st.L = r->p.L;
+    r->st.T = r->p.T;
+    r->rc = SIMRANK_OK;
+    sg.busy = false;
+    r->stage = -1;
+}
+
+// Returns a retired request's device resources.
+static void release_request(simrank_server *S, Request *r) {
+    if (r->mem_bytes) S->alloc.release(r->mem_off, r->mem_bytes);
+    r->mem_bytes = 0;
+    if (r->slot >= 0) S->slot_req[r->slot] = nullptr;
+    r->slot = -1;
+    --S->inflight;
+}
+
+// Reserves a ring entry (lone requests) and device memory; fills the
+// request's descriptor.  false if either is not available now.
+static bool reserve(simrank_server *S, Request *r, bool lone) {
+    int32_t slot = -1;
+    if (lone) {
+        for (int32_t i = 0; i < S->entries; ++i)
+            if (!S->slot_req[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return false;
+    }
+    const size_t bytes = request_bytes(r->p, r->mode, S->g->n);
+    size_t off = 0;
+    if (!S->alloc.alloc(bytes, &off)) return false;
+    r->mem_off = off;
+    r->mem_bytes = bytes;
+    r->slot = slot;
+    if (lone) S->slot_req[slot] = r;
+    describe_query(S->g, &r->q, r->p, r->mode, default_unit_nodes(S->g), &r->d);
+    carve_request(r->p, r->mode, S->g->n, S->pool + off, &r->d);
+    ++S->inflight;
+    S->inflight_peak = std::max(S->inflight_peak, S->inflight);
+    return true;
+}
+
+// Enqueues a lone request's preparation and publication into its ring entry.
+static int prepare(simrank_server *S, Request *r) {
+    r->seq = S->next_seq++;
+    if (r->mode == SIMRANK_MODE_STRATIFIED) {
+        StratParams sp;
+        StratTab *tab = S->tabs_host + r->slot;
+        int rc = strat_params(&r->q, S->g->n, &sp, tab);
+        if (rc) return rc;
+        r->d.z = sp.z;
+        r->d.sa = sp.sa;
+        r->d.sb = sp.sb;
+        SRK_HIP(hipMemcpyAsync((void *)r->d.tab, tab, sizeof(StratTab), hipMemcpyHostToDevice, S->prep));
+    }
+    return enqueue_ring_request(r->d, S->ring, r->slot, r->seq, S->prep);
+}
+
+// Enqueues the group rs (2..gmax members with equal walks, memory reserved)
+// on a worker stream: descriptors, the group's launch sequence, its events.
+static int launch_group(simrank_server *S, const std::vector<Request *> &rs, hipStream_t st) {
     GroupRun &gr = S->grp;
     const Graph *g = S->g;
     const int32_t G = (int32_t)rs.size();
-    hipStream_t st = S->slots[idx[0]].stream;
-    const int32_t vb = default_unit_nodes(g);
     std::vector<const QueryDesc *> mem(G);
     int64_t sum_RL = 0;
     for (int32_t i = 0; i < G; ++i) {
         QueryDesc &d = gr.desc_host[i];
-        describe_query(g, &rs[i]->q, rs[i]->p, rs[i]->mode, vb, &d);
-        slot_buffers(S->slots[idx[i]], &d);
+        d = rs[i]->d;
         d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED : K_GROUPED;
         mem[i] = &d;
         sum_RL += (int64_t)d.R * d.L;
@@ -159,119 +341,94 @@ static int launch_group(simrank_server *S, const std::vector<Request *> &rs,
     int rc = launch_query_set(qs, st, nullptr, nullptr);
     if (rc) return rc;
     SRK_HIP(hipEventRecord(gr.ev1, st));
-    const size_t n = (size_t)g->n;
-    for (int32_t i = 0; i < G; ++i) {
-        Slot &sl = S->slots[idx[i]];
-        SRK_HIP(hipMemcpyAsync(sl.out_host, sl.out_dev, 8 * n, hipMemcpyDeviceToHost, st));
-        SRK_HIP(hipMemcpyAsync(sl.cnt_host, sl.cnt_dev, 4 * n, hipMemcpyDeviceToHost, st));
-        SRK_HIP(hipEventRecord(sl.done, st));
-    }
+    gr.members = rs;
     gr.busy = true;
-    gr.lead = idx[0];
+    for (int32_t i = 0; i < G; ++i) {
+        rs[i]->grouped = true;
+        rs[i]->group_size = G;
+        rs[i]->group_pos = i;
+    }
     return SIMRANK_OK;
 }
 
-// Copies a finished slot's results and work counters into its request.
-static void collect_results(simrank_server *S, Slot &sl, Request *r) {
-    const size_t n = (size_t)S->g->n;
-    r->out.assign(sl.out_host, sl.out_host + n);
-    r->cnt.assign(sl.cnt_host, sl.cnt_host + n);
-    // a grouped request reports its share (1/G) of its group's work and the
-    // group's device time
-    unsigned long long c[8];
-    hipError_t e = hipMemcpy(c, sl.grouped ? S->grp.counters : sl.ws.counters, sizeof(c),
-                             hipMemcpyDeviceToHost);
-    if (sl.grouped)
-        for (unsigned long long &x : c) x /= (unsigned long long)sl.group_size;
-    float ms = 0.f, mms = 0.f;
-    if (sl.grouped) {
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, S->grp.ev0, S->grp.ev1);
-        mms = ms;
-    } else {
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, sl.ws.ev0, sl.ws.ev1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&mms, sl.ws.evm0, sl.ws.evm1);
-    }
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        r->rc = SIMRANK_EDEVICE;
-        r->err = hipGetErrorString(e);
-        return;
-    }
-    r->st.pairs = (uint64_t)(S->g->n - 1) * (uint64_t)r->p.R;
-    r->st.pairs_walked = c[C_PAIRS];
-    r->st.moves = c[C_MOVES];
-    r->st.draws = c[C_DRAWS];
-    r->st.meets = c[C_MEETS];
-    r->st.tail_steps = c[C_TAIL];
-    r->st.source_moves = c[C_SRC_MOVES];
-    r->st.ms = ms;
-    r->st.meet_ms = mms;
-    r->st.R = r->p.R;
-    r->st.L = r->p.L;
-    r->st.T = r->p.T;
-    r->rc = SIMRANK_OK;
-}
-
-// Enqueues request r alone on slot sl: its kernels, the copies of its results
-// to the slot's pinned buffers, the slot's completion event.
-static int launch_single(simrank_server *S, Slot &sl, Request *r) {
-    const size_t n = (size_t)S->g->n;
-    int rc = enqueue_query(S->g, &r->q, r->p, r->mode, &sl.ws, sl.out_dev, sl.cnt_dev, sl.stream);
-    if (rc) return rc;
-    SRK_HIP(hipMemcpyAsync(sl.out_host, sl.out_dev, 8 * n, hipMemcpyDeviceToHost, sl.stream));
-    SRK_HIP(hipMemcpyAsync(sl.cnt_host, sl.cnt_dev, 4 * n, hipMemcpyDeviceToHost, sl.stream));
-    SRK_HIP(hipEventRecord(sl.done, sl.stream));
-    return SIMRANK_OK;
-}
-
-// The worker.  It alone touches the slots and the group's buffers, and it
-// alone writes a running request's results; the mutex guards the queue, the
-// requests' states and the counters.  A waiter reads a request's results only
-// after its state, set under the mutex, says it ended, so results are copied
-// and kernels enqueued without holding the mutex, and submitters and waiters
-// are never held up by device calls.
+// The worker.  It alone touches the device, the pool, the ring and the
+// staging buffers, and it alone writes a running request's results; the
+// mutex guards the queue, the requests' states and the counters.  A waiter
+// reads a request's results only after its state, set under the mutex, says
+// it ended.
 static void server_loop(simrank_server *S) {
     (void)hipSetDevice(S->g->device);
+    std::vector<Request *> running;          // admitted, not yet retired
     std::vector<Request *> ended, admitted;
-    std::vector<int32_t> idx;
     for (;;) {
         bool progressed = false;
-        uint64_t inflight = 0;
-        // completions
         ended.clear();
-        for (Slot &sl : S->slots) {
-            if (!sl.req) continue;
-            const hipError_t e = hipEventQuery(sl.done);
-            if (e == hipErrorNotReady) {
-                ++inflight;
-                continue;
-            }
-            Request *r = sl.req;
-            if (e == hipSuccess) {
-                collect_results(S, sl, r);
+        // 1. completions: a lone request's flag, the group's event
+        for (Request *r : running) {
+            if (r->phase != 1) continue;
+            bool finished = false;
+            if (r->grouped) {
+                const hipError_t e = hipEventQuery(S->grp.ev1);
+                if (e == hipSuccess) finished = true;
+                else if (e != hipErrorNotReady) {
+                    (void)hipGetLastError();
+                    r->rc = SIMRANK_EDEVICE;
+                    r->err = hipGetErrorString(e);
+                    r->phase = 3;
+                }
             } else {
-                (void)hipGetLastError();
-                r->rc = SIMRANK_EDEVICE;
-                r->err = hipGetErrorString(e);
+                finished = __atomic_load_n(&S->flags_host[r->slot], __ATOMIC_ACQUIRE) == r->seq;
             }
-            r->t_done = now_s();
-            ended.push_back(r);
-            sl.req = nullptr;
-            sl.grouped = false;
+            if (!finished) continue;
+            int k = -1;
+            for (int i = 0; i < N_STAGING; ++i)
+                if (!S->stage[i].busy) {
+                    k = i;
+                    break;
+                }
+            if (k < 0) break;                     // all staging sets are copying
+            const int rc = start_copy(S, r, k);
+            if (rc) {
+                r->rc = rc;
+                r->err = simrank_last_error();
+                r->phase = 3;
+            }
+            progressed = true;
         }
-        // the group is done once none of its slots holds a request
-        if (S->grp.busy) {
-            bool running = false;
-            for (Slot &sl : S->slots) running |= sl.grouped;
-            if (!running) S->grp.busy = false;
+        // 2. copies done
+        for (Request *r : running) {
+            if (r->phase == 2) {
+                const hipError_t e = hipEventQuery(S->stage[r->stage].ev);
+                if (e == hipErrorNotReady) continue;
+                if (e == hipSuccess) {
+                    finish_copy(S, r);
+                } else {
+                    (void)hipGetLastError();
+                    r->rc = SIMRANK_EDEVICE;
+                    r->err = hipGetErrorString(e);
+                    S->stage[r->stage].busy = false;
+                }
+                r->phase = 3;
+            }
+            if (r->phase == 3) {
+                r->t_done = now_s();
+                release_request(S, r);
+                ended.push_back(r);
+            }
         }
-        idx.clear();
-        for (int32_t i = 0; i < (int32_t)S->slots.size(); ++i)
-            if (!S->slots[i].req) idx.push_back(i);
-        // admission: requests leave the queue under the mutex
+        if (!ended.empty()) {
+            running.erase(std::remove_if(running.begin(), running.end(),
+                                         [](Request *r) { return r->phase == 3; }),
+                          running.end());
+            if (S->grp.busy) {
+                bool any = false;
+                for (Request *r : running) any |= r->grouped;
+                if (!any) S->grp.busy = false;
+            }
+        }
+        // 3. admission, oldest first, while a ring entry and memory are free
         admitted.clear();
-        bool group = false;
-        const int32_t gmax = S->gmax;
+        std::vector<Request *> group;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (Request *r : ended) {
@@ -282,37 +439,60 @@ static void server_loop(simrank_server *S) {
                 progressed = true;
                 S->cv_done.notify_all();
             }
-            // Groups (group_max >= 2): one launch in flight at a time.  Once
-            // the device is free, the requests waiting with the same walks as
-            // the first one (up to group_max and the free slots) start as one
-            // group; a request with no partner starts alone.
-            if (gmax >= 2 && !S->queue.empty() && inflight == 0) {
+            if (S->gmax >= 2 && !S->grp.busy && !S->queue.empty()) {
+                // the requests waiting with the same walks as the oldest one
                 Request *head = S->queue.front();
-                const size_t cap = (size_t)std::min<int32_t>(gmax, (int32_t)idx.size());
-                for (Request *r : S->queue)
-                    if (admitted.size() < cap && same_walks(head, r)) admitted.push_back(r);
-                if (admitted.size() >= 2) {
-                    group = true;
-                    for (Request *r : admitted)
-                        S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
-                } else {
-                    admitted.clear();
+                if (head->mode != SIMRANK_MODE_STRATIFIED) {
+                    for (Request *r : S->queue)
+                        if ((int32_t)group.size() < S->gmax && same_walks(head, r)) group.push_back(r);
+                    if (group.size() >= 2) {
+                        size_t kept = 0;
+                        for (Request *r : group) {
+                            if (!reserve(S, r, false)) break;
+                            ++kept;
+                        }
+                        if (kept < 2) {
+                            for (size_t i = 0; i < kept; ++i) {
+                                S->alloc.release(group[i]->mem_off, group[i]->mem_bytes);
+                                group[i]->mem_bytes = 0;
+                                --S->inflight;
+                            }
+                            group.clear();
+                        } else {
+                            group.resize(kept);
+                            for (Request *r : group)
+                                S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+                        }
+                    } else {
+                        group.clear();
+                    }
                 }
             }
-            if (!group) {
-                // one request per free slot; with groups, one alone and only
-                // when nothing runs
-                const size_t cap = gmax >= 2 ? (inflight == 0 ? 1 : 0) : idx.size();
-                while (admitted.size() < std::min(cap, idx.size()) && !S->queue.empty()) {
-                    admitted.push_back(S->queue.front());
-                    S->queue.pop_front();
+            // lone admission, oldest first; with groups, a request that has a
+            // partner with the same walks in the queue waits for a group
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
+                Request *r = *it;
+                bool partner = false;
+                if (S->gmax >= 2 && r->mode != SIMRANK_MODE_STRATIFIED)
+                    for (Request *o : S->queue)
+                        if (o != r && same_walks(o, r)) {
+                            partner = true;
+                            break;
+                        }
+                if (partner) {
+                    ++it;
+                    continue;
                 }
+                if (!reserve(S, r, true)) break;
+                it = S->queue.erase(it);
+                admitted.push_back(r);
             }
             for (Request *r : admitted) r->state = 1;
-            if (admitted.empty()) {
-                if (S->stop && S->queue.empty() && inflight == 0) break;
+            for (Request *r : group) r->state = 1;
+            if (admitted.empty() && group.empty()) {
+                if (S->stop && S->queue.empty() && running.empty()) break;
                 if (!progressed) {
-                    if (inflight == 0 && S->queue.empty())
+                    if (running.empty() && S->queue.empty())
                         S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
                     else
                         S->cv_work.wait_for(lk, std::chrono::microseconds(50));
@@ -320,66 +500,94 @@ static void server_loop(simrank_server *S) {
                 continue;
             }
         }
-        // enqueue on the device, without the mutex
+        // 4. enqueue on the device, without the mutex
         const double t = now_s();
-        for (Request *r : admitted) r->t_start = t;
-        if (group) {
-            idx.resize(admitted.size());
-            const int rc = launch_group(S, admitted, idx);
-            for (size_t i = 0; i < admitted.size(); ++i) {
-                Request *r = admitted[i];
-                if (rc) {
-                    r->rc = rc;
-                    r->err = simrank_last_error();
-                    r->t_done = now_s();
-                } else {
-                    Slot &sl = S->slots[idx[i]];
-                    sl.req = r;
-                    sl.grouped = true;
-                    sl.group_size = (int32_t)admitted.size();
-                }
-            }
+        bool kinds[N_KINDS] = {false, false, false};
+        std::vector<Request *> failed;
+        for (Request *r : admitted) {
+            r->t_start = t;
+            const int rc = prepare(S, r);
             if (rc) {
-                // copies of the staged descriptors may have been enqueued:
-                // let them finish before the staging buffers are reused
-                (void)hipStreamSynchronize(S->slots[idx[0]].stream);
-                S->grp.busy = false;
+                r->rc = rc;
+                r->err = simrank_last_error();
+                failed.push_back(r);
+                continue;
             }
-        } else {
-            for (size_t i = 0; i < admitted.size(); ++i) {
-                Request *r = admitted[i];
-                Slot &sl = S->slots[idx[i]];
-                const int rc = launch_single(S, sl, r);
-                if (rc) {
+            r->phase = 1;
+            kinds[kind_of(r->mode)] = true;
+            running.push_back(r);
+        }
+        int rc_launch = SIMRANK_OK;
+        if (!admitted.empty() && (kinds[0] || kinds[1] || kinds[2])) {
+            // one persistent meet kernel per kind admitted, after the
+            // preparations, on the next worker stream
+            hipStream_t ws = S->work[S->next_work];
+            S->next_work ^= 1;
+            hipError_t e = hipEventRecord(S->ev_prep, S->prep);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ws, S->ev_prep, 0);
+            if (e != hipSuccess) rc_launch = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+            for (int k = 0; k < N_KINDS && !rc_launch; ++k)
+                if (kinds[k]) {
+                    rc_launch = launch_ring_meet(k, S->ring, ws);
+                    ++S->n_launches;
+                }
+        }
+        if (!group.empty()) {
+            for (Request *r : group) r->t_start = t;
+            hipStream_t ws = S->work[S->next_work];
+            S->next_work ^= 1;
+            const int rc = launch_group(S, group, ws);
+            if (rc) {
+                (void)hipStreamSynchronize(ws);
+                for (Request *r : group) {
                     r->rc = rc;
                     r->err = simrank_last_error();
-                    r->t_done = now_s();
-                } else {
-                    sl.req = r;
+                    failed.push_back(r);
                 }
+            } else {
+                for (Request *r : group) {
+                    r->phase = 1;
+                    running.push_back(r);
+                }
+                ++S->n_launches;
             }
+        }
+        if (rc_launch) {
+            // a launch failed: the published requests of this round cannot
+            // be relied on; fail them after their preparation has finished
+            (void)hipStreamSynchronize(S->prep);
+            for (Request *r : admitted)
+                if (r->phase == 1) {
+                    r->rc = rc_launch;
+                    r->err = simrank_last_error();
+                    r->phase = 3;
+                }
+        }
+        for (Request *r : failed) {
+            r->t_done = now_s();
+            release_request(S, r);
         }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            bool failed = false;
-            for (Request *r : admitted)
-                if (r->rc) {
-                    r->state = 3;
-                    ++S->n_failed;
-                    failed = true;
-                }
-            if (group && !failed) {
-                ++S->n_groups;
-                S->n_grouped += admitted.size();
+            for (Request *r : failed) {
+                r->state = 3;
+                ++S->n_failed;
             }
-            if (failed) S->cv_done.notify_all();
+            if (!group.empty() && failed.empty()) {
+                ++S->n_groups;
+                S->n_grouped += group.size();
+            }
+            if (!failed.empty()) S->cv_done.notify_all();
         }
     }
 }
 
 static void server_release(simrank_server *S) {
+    if (S->prep) (void)hipStreamSynchronize(S->prep);
+    for (hipStream_t w : S->work)
+        if (w) (void)hipStreamSynchronize(w);
+    if (S->copy) (void)hipStreamSynchronize(S->copy);
     GroupRun &gr = S->grp;
-    if (gr.lead >= 0 && S->slots[gr.lead].stream) (void)hipStreamSynchronize(S->slots[gr.lead].stream);
     if (gr.desc_host) (void)hipHostFree(gr.desc_host);
     if (gr.gdesc_host) (void)hipHostFree(gr.gdesc_host);
     device_free(gr.desc_dev);
@@ -390,16 +598,23 @@ static void server_release(simrank_server *S) {
     device_free(gr.buffers);
     if (gr.ev0) (void)hipEventDestroy(gr.ev0);
     if (gr.ev1) (void)hipEventDestroy(gr.ev1);
-    for (Slot &sl : S->slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        workspace_release(&sl.ws);
-        device_free(sl.out_dev);
-        device_free(sl.cnt_dev);
-        if (sl.out_host) (void)hipHostFree(sl.out_host);
-        if (sl.cnt_host) (void)hipHostFree(sl.cnt_host);
-        if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    for (Staging &sg : S->stage) {
+        if (sg.out) (void)hipHostFree(sg.out);
+        if (sg.out_n) (void)hipHostFree(sg.out_n);
+        if (sg.cnt) (void)hipHostFree(sg.cnt);
+        if (sg.wsum) (void)hipHostFree(sg.wsum);
+        if (sg.ctr) (void)hipHostFree(sg.ctr);
+        if (sg.ev) (void)hipEventDestroy(sg.ev);
     }
+    device_free(S->pool);
+    device_free(S->ring.desc);
+    device_free(S->ring.ctl);
+    device_free(S->ring.counters);
+    if (S->flags_host) (void)hipHostFree(S->flags_host);
+    if (S->tabs_host) (void)hipHostFree(S->tabs_host);
+    if (S->ev_prep) (void)hipEventDestroy(S->ev_prep);
+    for (hipStream_t st : {S->prep, S->copy, S->work[0], S->work[1]})
+        if (st) (void)hipStreamDestroy(st);
     for (auto &kv : S->all) delete kv.second;
     delete S;
 }
@@ -409,7 +624,8 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
     clear_error();
     if (!g || !p || !out) return fail(SIMRANK_EINVAL, "NULL argument");
     *out = nullptr;
-    if (p->max_slots < 1 || p->max_slots > 64) return fail(SIMRANK_EINVAL, "max_slots must lie in [1, 64]");
+    if (p->max_slots < 1 || p->max_slots > RING_MAX)
+        return fail(SIMRANK_EINVAL, "max_slots must lie in [1, 64]");
     if (p->max_R < 1 || p->max_R > MAX_R) return fail(SIMRANK_EINVAL, "max_R must lie in [1, 2^24]");
     if (p->max_L < 1 || p->max_L > MAX_CAP) return fail(SIMRANK_EINVAL, "max_L must lie in [1, 255]");
     if (p->group_max < 0 || p->group_max > GROUP_MAX)
@@ -418,35 +634,48 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
     simrank_server *S = new simrank_server();
     S->g = g;
     S->prm = *p;
-    const size_t RL = (size_t)p->max_R * (size_t)p->max_L;
-    S->slot_bytes = (int64_t)(8 * RL + 13 * (size_t)p->max_R + 4 * (size_t)max_tiles_for(p->max_R, p->max_L) +
-                              12 * (size_t)g->n + 4096);
+    simrank_params big{p->max_R, p->max_L, 0u, 0};
+    S->slot_bytes = (int64_t)request_bytes(big, SIMRANK_MODE_PLAIN, g->n);
     size_t free_b = 0, tot_b = 0;
     SRK_HIP(hipMemGetInfo(&free_b, &tot_b));
-    int64_t budget = p->hbm_budget > 0 ? std::min<int64_t>(p->hbm_budget, (int64_t)free_b)
-                                       : (int64_t)(free_b / 2);
-    const int64_t fit = budget / std::max<int64_t>(S->slot_bytes, 1);
-    const int32_t nslots = (int32_t)std::min<int64_t>(p->max_slots, fit);
-    if (nslots < 1) {
+    const int64_t budget = p->hbm_budget > 0 ? std::min<int64_t>(p->hbm_budget, (int64_t)free_b)
+                                             : (int64_t)(free_b / 2);
+    if (budget < S->slot_bytes) {
         delete S;
-        return fail(SIMRANK_ENOMEM, "device-memory budget admits no slot of " +
+        return fail(SIMRANK_ENOMEM, "device-memory budget admits no request of " +
                                         std::to_string(S->slot_bytes) + " bytes");
     }
-    S->slots.resize(nslots);
+    const int64_t pool_bytes = std::min<int64_t>(budget, (int64_t)p->max_slots * S->slot_bytes);
+    S->entries = p->max_slots;
+    S->slot_req.assign(S->entries, nullptr);
     int rc = SIMRANK_OK;
-    for (Slot &sl : S->slots) {
-        rc = workspace_init(g, p->max_R, p->max_L, &sl.ws);
-        if (!rc) rc = device_alloc((void **)&sl.out_dev, 8 * (size_t)g->n, nullptr);
-        if (!rc) rc = device_alloc((void **)&sl.cnt_dev, 4 * (size_t)g->n, nullptr);
-        hipError_t e = hipSuccess;
-        if (!rc) e = hipHostMalloc((void **)&sl.out_host, 8 * (size_t)g->n, hipHostMallocDefault);
-        if (!rc && e == hipSuccess) e = hipHostMalloc((void **)&sl.cnt_host, 4 * (size_t)g->n, hipHostMallocDefault);
-        if (!rc && e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (!rc && e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    auto hip = [&](hipError_t e) {
         if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
-        if (rc) break;
+    };
+    rc = device_alloc((void **)&S->pool, (size_t)pool_bytes, nullptr);
+    if (!rc) S->alloc = PoolAlloc((size_t)pool_bytes);
+    if (!rc) rc = device_alloc((void **)&S->ring.desc, sizeof(QueryDesc) * RING_MAX, nullptr);
+    if (!rc) rc = device_alloc((void **)&S->ring.ctl, sizeof(RingCtl) * RING_MAX, nullptr);
+    if (!rc) rc = device_alloc((void **)&S->ring.counters, 64 * RING_MAX, nullptr);
+    if (!rc) hip(hipMemset(S->ring.ctl, 0, sizeof(RingCtl) * RING_MAX));
+    if (!rc) hip(hipHostMalloc((void **)&S->flags_host, 4 * RING_MAX, hipHostMallocCoherent));
+    if (!rc) std::memset(S->flags_host, 0, 4 * RING_MAX);
+    if (!rc) hip(hipHostMalloc((void **)&S->tabs_host, sizeof(StratTab) * RING_MAX, hipHostMallocDefault));
+    S->ring.flags = S->flags_host;
+    S->ring.entries = S->entries;
+    for (hipStream_t *st : {&S->prep, &S->copy, &S->work[0], &S->work[1]})
+        hip(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+    hip(hipEventCreateWithFlags(&S->ev_prep, hipEventDisableTiming));
+    const size_t n = (size_t)g->n;
+    for (Staging &sg : S->stage) {
+        hip(hipHostMalloc((void **)&sg.out, 8 * n, hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&sg.out_n, 8 * n, hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&sg.cnt, 4 * n, hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&sg.wsum, 8 * n, hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&sg.ctr, 64, hipHostMallocDefault));
+        hip(hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming));
     }
-    int32_t gmax = std::min<int32_t>(p->group_max, nslots);
+    int32_t gmax = std::min<int32_t>(p->group_max, p->max_slots);
     // a group's packed positions are addressed in 32 bits
     while (gmax >= 2 &&
            group_pos_words(p->max_R, (int64_t)gmax * p->max_R * p->max_L, p->max_L) >= (int64_t)0xffff0000)
@@ -467,12 +696,10 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
         if (!rc) rc = device_alloc((void **)&gr.units, 4 * units_words(gmax), nullptr);
         if (!rc) rc = device_alloc((void **)&gr.gunits, 4 * group_units_words(1), nullptr);
         if (!rc) rc = device_alloc((void **)&gr.counters, 8 * 8, nullptr);
-        hipError_t e = hipSuccess;
-        if (!rc) e = hipHostMalloc((void **)&gr.desc_host, sizeof(QueryDesc) * gmax, hipHostMallocDefault);
-        if (!rc && e == hipSuccess) e = hipHostMalloc((void **)&gr.gdesc_host, sizeof(GroupDesc), hipHostMallocDefault);
-        if (!rc && e == hipSuccess) e = hipEventCreate(&gr.ev0);
-        if (!rc && e == hipSuccess) e = hipEventCreate(&gr.ev1);
-        if (!rc && e != hipSuccess) rc = fail(SIMRANK_EDEVICE, hipGetErrorString(e));
+        hip(hipHostMalloc((void **)&gr.desc_host, sizeof(QueryDesc) * gmax, hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&gr.gdesc_host, sizeof(GroupDesc), hipHostMallocDefault));
+        hip(hipEventCreate(&gr.ev0));
+        hip(hipEventCreate(&gr.ev1));
     }
     if (rc) {
         server_release(S);
@@ -486,7 +713,8 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
 extern "C" int simrank_server_info(const simrank_server *S, int32_t *slots, int64_t *slot_bytes) {
     clear_error();
     if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
-    if (slots) *slots = (int32_t)S->slots.size();
+    if (slots)
+        *slots = (int32_t)std::min<int64_t>(S->entries, (int64_t)S->alloc.total() / S->slot_bytes);
     if (slot_bytes) *slot_bytes = S->slot_bytes;
     return SIMRANK_OK;
 }
@@ -503,6 +731,18 @@ extern "C" int simrank_server_counts(simrank_server *S, uint64_t *done, uint64_t
     return SIMRANK_OK;
 }
 
+extern "C" int simrank_server_load(simrank_server *S, int32_t *inflight_peak, int64_t *pool_bytes,
+                                   int64_t *pool_peak, uint64_t *launches) {
+    clear_error();
+    if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (inflight_peak) *inflight_peak = S->inflight_peak;
+    if (pool_bytes) *pool_bytes = (int64_t)S->alloc.total();
+    if (pool_peak) *pool_peak = (int64_t)S->alloc.peak();
+    if (launches) *launches = S->n_launches;
+    return SIMRANK_OK;
+}
+
 extern "C" int simrank_server_submit(simrank_server *S, const simrank_query *q, uint64_t *ticket) {
     clear_error();
     if (!S || !q || !ticket) return fail(SIMRANK_EINVAL, "NULL argument");
@@ -510,12 +750,17 @@ extern "C" int simrank_server_submit(simrank_server *S, const simrank_query *q, 
     r->q = *q;
     int rc = query_params(q, S->g->n, &r->p, &r->mode);
     if (!rc && (q->s < 0 || q->s >= S->g->n)) rc = fail(SIMRANK_EINVAL, "source out of range");
-    if (!rc && r->mode == SIMRANK_MODE_STRATIFIED)
-        rc = fail(SIMRANK_EINVAL, "stratified queries are not served");
     if (!rc && (r->p.R > S->prm.max_R || r->p.L > S->prm.max_L))
-        rc = fail(SIMRANK_EINVAL, "query needs R or L beyond the server's slots");
+        rc = fail(SIMRANK_EINVAL, "query needs R or L beyond the server's maximum");
     if (!rc && r->mode == SIMRANK_MODE_STITCHED && (!S->g->index || S->g->index->T != r->p.T))
         rc = fail(SIMRANK_ESTATE, "stitched query without a matching index");
+    if (!rc) {
+        const int64_t units = (int64_t)max_tiles_for(r->p.R, r->p.L) *
+                              ((S->g->n_active + default_unit_nodes(S->g) - 1) / default_unit_nodes(S->g));
+        if (units >= (int64_t)0x7fffffff) rc = fail(SIMRANK_EINVAL, "R * L * n too large for one request");
+    }
+    if (!rc && (int64_t)request_bytes(r->p, r->mode, S->g->n) > (int64_t)S->alloc.total())
+        rc = fail(SIMRANK_ENOMEM, "the request needs more device memory than the server's budget");
     if (rc) {
         delete r;
         return rc;
@@ -536,13 +781,26 @@ extern "C" int simrank_server_submit(simrank_server *S, const simrank_query *q, 
     return SIMRANK_OK;
 }
 
-extern "C" int simrank_server_wait(simrank_server *S, uint64_t ticket, double timeout_s,
-                                   double *out_host, uint32_t *counts_host,
-                                   simrank_request_info *info) {
+extern "C" int simrank_server_poll(simrank_server *S, uint64_t ticket, int32_t *state) {
     clear_error();
-    if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
+    if (!S || !state) return fail(SIMRANK_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(SIMRANK_EINVAL, "unknown ticket");
+    *state = std::min(it->second->state, 2);
+    return SIMRANK_OK;
+}
+
+// Waits for the request and retires its ticket; the results stay with the
+// returned request, which the caller deletes.
+static int wait_request(simrank_server *S, uint64_t ticket, double timeout_s, bool stratified,
+                        Request **out) {
     std::unique_lock<std::mutex> lk(S->mu);
-    if (S->all.find(ticket) == S->all.end()) return fail(SIMRANK_EINVAL, "unknown ticket");
+    auto it0 = S->all.find(ticket);
+    if (it0 == S->all.end()) return fail(SIMRANK_EINVAL, "unknown ticket");
+    if ((it0->second->mode == SIMRANK_MODE_STRATIFIED) != stratified)
+        return fail(SIMRANK_EINVAL, stratified ? "not a stratified request: use simrank_server_wait"
+                                               : "stratified request: use simrank_server_wait_stratified");
     // looked up afresh at every wake-up: another wait on the same ticket may
     // have retired it meanwhile
     auto finished = [&] {
@@ -556,21 +814,54 @@ extern "C" int simrank_server_wait(simrank_server *S, uint64_t ticket, double ti
     }
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return fail(SIMRANK_EINVAL, "ticket retired by another wait");
-    Request *r = it->second;
+    *out = it->second;
     S->all.erase(it);
-    lk.unlock();
-    int rc = SIMRANK_OK;
+    return SIMRANK_OK;
+}
+
+static void fill_info(const Request *r, simrank_request_info *info) {
+    if (!info) return;
+    info->queue_s = r->t_start - r->t_submit;
+    info->latency_s = r->t_done - r->t_submit;
+    info->stats = r->st;
+}
+
+extern "C" int simrank_server_wait(simrank_server *S, uint64_t ticket, double timeout_s,
+                                   double *out_host, uint32_t *counts_host,
+                                   simrank_request_info *info) {
+    clear_error();
+    if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
+    Request *r = nullptr;
+    int rc = wait_request(S, ticket, timeout_s, false, &r);
+    if (rc) return rc;
     if (r->state == 3) {
         rc = fail(r->rc, r->err);
     } else {
         const size_t n = (size_t)S->g->n;
         if (out_host) std::copy(r->out.begin(), r->out.begin() + n, out_host);
         if (counts_host) std::copy(r->cnt.begin(), r->cnt.begin() + n, counts_host);
-        if (info) {
-            info->queue_s = r->t_start - r->t_submit;
-            info->latency_s = r->t_done - r->t_submit;
-            info->stats = r->st;
-        }
+        fill_info(r, info);
+    }
+    delete r;
+    return rc;
+}
+
+extern "C" int simrank_server_wait_stratified(simrank_server *S, uint64_t ticket, double timeout_s,
+                                              double *out_host, double *out_n_host,
+                                              uint64_t *wsum_host, simrank_request_info *info) {
+    clear_error();
+    if (!S) return fail(SIMRANK_EINVAL, "server is NULL");
+    Request *r = nullptr;
+    int rc = wait_request(S, ticket, timeout_s, true, &r);
+    if (rc) return rc;
+    if (r->state == 3) {
+        rc = fail(r->rc, r->err);
+    } else {
+        const size_t n = (size_t)S->g->n;
+        if (out_host) std::copy(r->out.begin(), r->out.begin() + n, out_host);
+        if (out_n_host) std::copy(r->out_n.begin(), r->out_n.begin() + n, out_n_host);
+        if (wsum_host) std::copy(r->wsum.begin(), r->wsum.begin() + n, wsum_host);
+        fill_info(r, info);
     }
     delete r;
     return rc;

@@ -35,7 +35,7 @@ class SimRankError(RuntimeError):
 
 
 class simrank_query(C.Structure):
-    _fields_ = [("s", C.c_int32), ("graph", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
+    _fields_ = [("graph", C.c_int32), ("s", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
                 ("delta", C.c_double), ("seed", C.c_uint64), ("walk_cap", C.c_int32),
                 ("R_override", C.c_int32), ("mode", C.c_int32), ("union_bound", C.c_int32)]
 
@@ -91,7 +91,8 @@ class simrank_rate(C.Structure):
 
 class simrank_index_summary(C.Structure):
     _fields_ = [("segments", C.c_int64), ("bytes", C.c_int64), ("seg_log2", C.c_int32),
-                ("levels", C.c_int32), ("build_ms", C.c_double), ("build_moves", C.c_uint64)]
+                ("levels", C.c_int32), ("build_ms", C.c_double), ("build_moves", C.c_uint64),
+                ("segments_ms", C.c_double), ("doubling_ms", C.c_double)]
 
     def asdict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -160,6 +161,10 @@ def lib() -> C.CDLL:
         "simrank_server_submit": [vp, P(simrank_query), P(C.c_uint64)],
         "simrank_server_wait": [vp, C.c_uint64, dbl, vp, vp, P(simrank_request_info)],
         "simrank_server_destroy": [vp],
+        "simrank_server_poll": [vp, C.c_uint64, P(i32)],
+        "simrank_server_load": [vp, P(i32), P(i64), P(i64), P(C.c_uint64)],
+        "simrank_server_wait_stratified": [vp, C.c_uint64, dbl, vp, vp, vp,
+                                           P(simrank_request_info)],
         "simrank_roofline_gather": [i64, i32, i32, P(simrank_rate)],
         "simrank_roofline_gather_grid": [i64, i32, i32, i32, P(simrank_rate)],
         "simrank_roofline_philox": [P(simrank_rate)],
@@ -559,7 +564,7 @@ class BatchPlan:
 
 
 class Server:
-    """simrank_server_*: continuous admission of single-source requests."""
+    """simrank_server_*: continuous batching of single-source requests."""
 
     def __init__(self, g: Graph, max_slots: int = 4, max_R: int = 9502, max_L: int = 64,
                  hbm_budget: int = 0, group_max: int = 0):
@@ -588,6 +593,21 @@ class Server:
         _check(lib().simrank_server_submit(self.handle, C.byref(q), C.byref(t)))
         return t.value
 
+    def load(self) -> dict:
+        """Most requests in flight at once, the device pool's size and peak use,
+        persistent meet kernels and group launches made."""
+        a, b, c, d = C.c_int32(), C.c_int64(), C.c_int64(), C.c_uint64()
+        _check(lib().simrank_server_load(self.handle, C.byref(a), C.byref(b), C.byref(c),
+                                         C.byref(d)))
+        return dict(inflight_peak=a.value, pool_bytes=b.value, pool_peak=c.value,
+                    launches=d.value)
+
+    def poll(self, ticket: int) -> int:
+        """0 queued, 1 running, 2 finished (its wait returns at once)."""
+        st = C.c_int32()
+        _check(lib().simrank_server_poll(self.handle, ticket, C.byref(st)))
+        return st.value
+
     def wait(self, ticket: int, timeout_s: float = -1.0, want_out: bool = True,
              want_counts: bool = True):
         n = self.graph.n
@@ -598,6 +618,18 @@ class Server:
                                          _ptr(out) if out is not None else None,
                                          _ptr(cnt) if cnt is not None else None, C.byref(info)))
         return out, cnt, info
+
+    def wait_stratified(self, ticket: int, timeout_s: float = -1.0):
+        """A stratified request's (out, out_n, wsum, info)."""
+        n = self.graph.n
+        out = np.empty(n, np.float64)
+        out_n = np.empty(n, np.float64)
+        wsum = np.empty(n, np.uint64)
+        info = simrank_request_info()
+        _check(lib().simrank_server_wait_stratified(self.handle, ticket, float(timeout_s),
+                                                    _ptr(out), _ptr(out_n), _ptr(wsum),
+                                                    C.byref(info)))
+        return out, out_n, wsum, info
 
     def destroy(self) -> None:
         if self.handle and self.handle.value:

@@ -400,3 +400,19 @@ def test_group_edge_cases():
         for i, q in enumerate(qs):
             assert np.array_equal(plan.read(i)[1], S.simrank_single_source_ex(G2, q)[1]), (k, i)
         plan.free()
+
+
+def test_plan_refuses_units_beyond_32_bits():
+    """A kind's work units are numbered in 32 bits across all queries of a
+    plan: 18 queries with R = 2^24 on a 2^20-node ring (each alone below 2^31
+    units, together about 4.5e9) are refused with EINVAL before anything is
+    allocated or launched."""
+    n = 1 << 20
+    src = np.arange(n, dtype=np.int64)
+    g = inputs.from_edges(n, src, (src + 1) % n)
+    G = S.load_csr(g)
+    qs = [S.make_query(i, c=0.6, seed=0xF00 + i, walk_cap=64, R=1 << 24) for i in range(18)]
+    with pytest.raises(S.SimRankError) as e:
+        S.BatchPlan([G], qs, groups=False)
+    assert e.value.code == S.SIMRANK_EINVAL and "2^32" in str(e.value)
+    G.free()

@@ -226,3 +226,115 @@ def test_two_waits_on_one_ticket(served):
     assert np.array_equal(got[0], lone)
     assert errs[0] == S.SIMRANK_EINVAL
     srv.destroy()
+
+
+def test_stratified_and_mixed_requests(served):
+    """Plain, stitched and stratified requests (Algorithms 1-2 at a small z)
+    in one stream of arrivals: each served result equals the lone call's bit
+    for bit, the stratified ones also the oracle's weighted sums; a
+    stratified ticket is refused by the counts wait and a plain one by the
+    stratified wait, without retiring either."""
+    g, G = served
+    rng = np.random.default_rng(51)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    qs = []
+    for i in range(12):
+        s = int(rng.choice(act))
+        if i % 3 == 0:
+            qs.append(S.make_stratified_query(s, c=0.6, eps=0.05, seed=0x5F00 + i, z=1200, phi=12))
+        else:
+            mode = S.MODE_STITCHED if i % 3 == 1 else S.MODE_PLAIN
+            qs.append(S.make_query(s, c=0.6, eps=0.05, delta=1e-3, seed=0x5F00 + i, mode=mode))
+    srv = S.Server(G, max_slots=6, max_R=9502, max_L=64)
+    tickets = []
+    for i, q in enumerate(qs):
+        tickets.append(srv.submit(q))
+        if i % 4 == 3:
+            time.sleep(0.003)
+    for t, q in zip(tickets, qs):
+        if q.mode == S.MODE_STRATIFIED:
+            with pytest.raises(S.SimRankError):
+                srv.wait(t)
+            o, on, w, info = srv.wait_stratified(t)
+            o1, on1, w1, _ = S.simrank_single_source_stratified(G, q)
+            assert np.array_equal(w, w1) and np.array_equal(o, o1) and np.array_equal(on, on1)
+            P = O.strat_params(g.n, 0.6, 0.05, z=1200.0, phi=12)
+            assert np.array_equal(w, OT.strat_sums(g, q.s, q.seed, P, np.arange(g.n)))
+        else:
+            with pytest.raises(S.SimRankError):
+                srv.wait_stratified(t)
+            o, c, info = srv.wait(t)
+            o1, c1, _ = S.simrank_single_source_ex(G, q)
+            assert np.array_equal(c, c1) and np.array_equal(o, o1)
+        assert info.latency_s >= info.queue_s >= 0.0
+    k = srv.counts()
+    assert k["done"] == len(qs) and k["failed"] == 0
+    srv.destroy()
+
+
+def test_arrivals_join_running_work(served):
+    """Continuous batching: requests that arrive while others run are admitted
+    at once (ring entries and memory are free) rather than after the running
+    ones finish, several are in flight together, and each result equals the
+    lone call's.  poll() reports a finished request as 2."""
+    g, G = served
+    rng = np.random.default_rng(61)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    qs = [S.make_query(int(rng.choice(act)), c=0.6, eps=0.02, delta=1e-3, seed=0x6000 + i)
+          for i in range(10)]
+    lone = [S.simrank_single_source_ex(G, q)[1] for q in qs]
+    srv = S.Server(G, max_slots=8, max_R=9502, max_L=64)
+    tickets = [srv.submit(qs[0])]
+    time.sleep(0.002)
+    tickets += [srv.submit(q) for q in qs[1:]]
+    infos = []
+    for t, c1 in zip(tickets, lone):
+        _, c, info = srv.wait(t, want_out=False)
+        assert np.array_equal(c, c1)
+        infos.append(info)
+    ld = srv.load()
+    assert ld["inflight_peak"] >= 2 and ld["launches"] >= 1
+    assert ld["pool_peak"] <= ld["pool_bytes"]
+    # the later arrivals were admitted while the first one still ran
+    first_done = infos[0].latency_s
+    assert min(i.queue_s for i in infos[1:]) < first_done
+    t = srv.submit(qs[0])
+    _, c, _ = srv.wait(t, want_out=False)
+    with pytest.raises(S.SimRankError):
+        srv.poll(t)                      # retired
+    t2 = srv.submit(qs[1])
+    while srv.poll(t2) != 2:
+        time.sleep(0.001)
+    assert np.array_equal(srv.wait(t2, want_out=False)[1], lone[1])
+    srv.destroy()
+
+
+def test_memory_admission_per_request(served):
+    """Admission by each request's own memory: a pool that holds one request
+    of the server's largest R holds several small ones, which then run
+    together; a request larger than the whole pool is refused at submit."""
+    g, G = served
+    probe = S.Server(G, max_slots=1, max_R=9502, max_L=64)
+    big = probe.info()["slot_bytes"]
+    probe.destroy()
+    srv = S.Server(G, max_slots=8, max_R=9502, max_L=64, hbm_budget=int(1.2 * big))
+    rng = np.random.default_rng(71)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    small = [S.make_query(int(rng.choice(act)), c=0.6, eps=0.2, delta=1e-3, seed=0x6100 + i)
+             for i in range(8)]             # R = 95
+    tickets = [srv.submit(q) for q in small]
+    for t, q in zip(tickets, small):
+        assert np.array_equal(srv.wait(t, want_out=False)[1], S.simrank_single_source_ex(G, q)[1])
+    assert srv.load()["inflight_peak"] >= 2
+    tb = srv.submit(S.make_query(int(act[0]), c=0.6, eps=0.02, seed=0x6200))   # fits alone
+    assert srv.wait(tb, want_out=False)[1][int(act[0])] == 9502
+    srv.destroy()
+    # a stratified request of nearly the largest N and cap 64 needs more than
+    # a plain request of the largest R: beyond a pool of exactly that size
+    srv = S.Server(G, max_slots=2, max_R=9502, max_L=64, hbm_budget=big)
+    qz = S.make_stratified_query(int(act[0]), c=0.6, eps=0.05, seed=0x6300, z=9400, phi=64)
+    assert S.simrank_derive_stratified(qz, g.n).N <= 9502
+    with pytest.raises(S.SimRankError) as e:
+        srv.submit(qz)
+    assert e.value.code == S.SIMRANK_ENOMEM
+    srv.destroy()
