@@ -114,7 +114,7 @@ def parse():
                          "stratified: the medium graph and sources with the paper's "
                          "length-stratified estimator (Algorithms 1-2); tuples: the medium "
                          "graph's 8 sources (and 32) through Algorithm 2's tuple form")
-    ap.add_argument("--requests", type=int, default=24, help="serving: requests per load level")
+    ap.add_argument("--requests", type=int, default=32, help="serving: requests per load level")
     ap.add_argument("--queries", type=int, default=512, help="batching: number of queries")
     ap.add_argument("--tune-index", action="store_true",
                     help="stitching: also run the segment-length tuner (k = 2, 3, 4) and report it")
@@ -984,9 +984,10 @@ def bench_serving(args):
                                                   c=cfg["c"], seed=0x2304040150000023)
     tq.mode = S.MODE_STITCHED if args.served_mode == "stitched" else S.MODE_PLAIN
     tuning = S.simrank_tune_ex(G, tq)
-    # plain capacity: one request at a time, back to back
+    # the requests: one list, replayed one at a time (the plain capacity) and
+    # into the server at every load, so that every rate covers the same work
     warm = [make(i) for i in range(2)]
-    cap_q = [make(100 + i) for i in range(12)]
+    cap_q = [make(1000 + i) for i in range(args.requests)]
     ws = S.simrank_workspace_create(G, 9502, cfg["L"])
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
     cnt = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -997,15 +998,19 @@ def bench_serving(args):
     t1 = time.perf_counter()
     steps = 0
     kmoves, kms = 0, 0.0
-    for q in cap_q:
+    lone_counts = []
+    for i, q in enumerate(cap_q):
         S.simrank_single_source_async(G, q, ws, out, cnt, stream)
         st = S.simrank_workspace_stats(ws)
         steps += st.moves + st.tail_steps + st.source_moves
         kmoves += st.moves + st.tail_steps
         kms += st.meet_ms
         _ = out.cpu()                       # results to host, as a served request has
+        if i < 4:
+            lone_counts.append(cnt.cpu().numpy().view(np.uint32).copy())
     plain_s = time.perf_counter() - t1
     capacity = len(cap_q) / plain_s
+    plain_steps_per_s = steps / plain_s
     ws.free()
     gi = G.info()
     footprint = 8 * (gi["m"] + gi["n"] - gi["n_active"])
@@ -1015,12 +1020,13 @@ def bench_serving(args):
     srv = S.Server(G, max_slots=max(16, args.group_max), max_R=9502, max_L=cfg["L"],
                    group_max=args.group_max)
     levels = []
-    k = 1000
-    for load in ((0.5, 1.0, 2.0, 3.0, 4.0) if grouped else (0.5, 0.8, 1.0, 1.2, 1.5, 2.0)):
-        qps = load * capacity
-        reqs = [make(k + i) for i in range(args.requests)]
-        k += args.requests
-        gaps = rng.exponential(1.0 / qps, size=len(reqs))
+    served_equal = True
+    for load in ((0.5, 1.0, 2.0, 3.0, 4.0, "burst") if grouped else
+                 (0.5, 0.8, 1.0, 1.2, 1.5, 2.0, "burst")):
+        # "burst": every request submitted at once (the server's saturated rate)
+        qps = float("inf") if load == "burst" else load * capacity
+        reqs = cap_q
+        gaps = np.zeros(len(reqs)) if load == "burst" else rng.exponential(1.0 / qps, size=len(reqs))
         tickets = []
         t_start = time.perf_counter()
         t_next = t_start
@@ -1031,14 +1037,17 @@ def bench_serving(args):
                 time.sleep(delay)
             tickets.append(srv.submit(q))
         lat, qwait, wsteps = [], [], 0
-        for t in tickets:
-            _, _, info = srv.wait(t, want_counts=False)
+        for i, t in enumerate(tickets):
+            _, c, info = srv.wait(t, want_counts=i < len(lone_counts))
+            if c is not None:
+                served_equal &= bool(np.array_equal(c, lone_counts[i]))
             lat.append(info.latency_s)
             qwait.append(info.queue_s)
             wsteps += info.stats.moves + info.stats.tail_steps + info.stats.source_moves
         t_end = time.perf_counter()
-        levels.append({"load": load, "offered_qps": qps,
+        levels.append({"load": load, "offered_qps": qps if load != "burst" else None,
                        "achieved_qps": len(reqs) / (t_end - t_start),
+                       "served_vs_plain": len(reqs) / (t_end - t_start) / capacity,
                        "walk_steps_per_s": wsteps / (t_end - t_start),
                        "p50_latency_s": float(np.percentile(lat, 50)),
                        "p99_latency_s": float(np.percentile(lat, 99)),
@@ -1065,7 +1074,9 @@ def bench_serving(args):
         "queries_per_s": top["achieved_qps"],
         "plain_queries_per_s": capacity,
         "served_vs_plain": top["achieved_qps"] / capacity,
-        "served_vs_plain_by_load": {str(lv["load"]): lv["achieved_qps"] / capacity for lv in levels},
+        "served_vs_plain_by_load": {str(lv["load"]): lv["served_vs_plain"] for lv in levels},
+        "plain_walk_steps_per_s": plain_steps_per_s,
+        "served_results_equal_lone": served_equal,
         "levels": levels,
         "server_counts": srv.counts(),
         "server_load": srv.load(),

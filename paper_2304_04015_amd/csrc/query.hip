@@ -237,29 +237,33 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 // Heads thus keep the plain kernel's shape and rate, and the rarer tails do
 // not hold slots of their own.
 
-// Serving (STREAM): wave 0 of a block claims the next unit from the ring:
+// Serving (STREAM): wave 0 of a block claims the next units from the ring:
 // among published entries of the kernel's kind with unclaimed units, the
 // oldest (smallest seq); the claim is a compare-and-swap of its (seq, claimed)
-// word.  A failed swap means another block took that unit: look again.  The
-// entry's words are read with device-coherent atomic loads and no fence: the
-// block fences only when it moves to a request it has not worked on (below),
-// so its caches keep the graph's rows from unit to unit.  A claim whose unit
-// lies beyond the entry's size as read again after the swap (possible only
-// if the scan read a size older than the entry's publication) is dropped.
+// word that takes up to RING_RUN consecutive units (consecutive node chunks
+// of one tile).  A failed swap means another block took them: look again.
+// The entry's words are read with device-coherent atomic loads and no fence:
+// the block fences only when it moves to a request it has not worked on
+// (below), so its caches keep the graph's rows from unit to unit.  Units
+// beyond the entry's size as read again after the swap (possible only if the
+// scan read a size older than the entry's publication) are dropped.
 // *o_slot = RING_MAX when no entry has units left.
+constexpr uint32_t RING_RUN = 4;
 template <int KIND>
 __device__ void ring_claim(const StreamRing &ring, int lane, uint32_t *o_slot, uint32_t *o_unit,
-                           uint32_t *o_seq) {
+                           uint32_t *o_count, uint32_t *o_seq) {
     for (;;) {
         unsigned long long key = ~0ull, c = 0ull;
+        uint32_t nu = 0u;
         if (lane < ring.entries) {
             RingCtl &e = ring.ctl[lane];
             c = __hip_atomic_load(&e.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t seq = (uint32_t)(c >> 32), cl = (uint32_t)c;
             if (seq != 0u &&
-                __hip_atomic_load(&e.kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KIND &&
-                cl < __hip_atomic_load(&e.n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                key = ((unsigned long long)seq << 32) | (uint32_t)lane;
+                __hip_atomic_load(&e.kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KIND) {
+                nu = __hip_atomic_load(&e.n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cl < nu) key = ((unsigned long long)seq << 32) | (uint32_t)lane;
+            }
         }
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(key, off, 64);
@@ -271,23 +275,73 @@ __device__ void ring_claim(const StreamRing &ring, int lane, uint32_t *o_slot, u
         }
         const int best = (int)(uint32_t)key;
         const unsigned long long cb = __shfl(c, best, 64);
+        const uint32_t cl = (uint32_t)cb;
+        const uint32_t take = min(RING_RUN, __shfl(nu, best, 64) - cl);
         unsigned long long prev = 0ull;
-        uint32_t nu = 0u;
+        uint32_t nu2 = 0u;
         if (lane == 0) {
-            prev = atomicCAS(&ring.ctl[best].claim, cb, cb + 1ull);
-            nu = __hip_atomic_load(&ring.ctl[best].n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            prev = atomicCAS(&ring.ctl[best].claim, cb, cb + take);
+            nu2 = __hip_atomic_load(&ring.ctl[best].n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         prev = __shfl(prev, 0, 64);
-        nu = __shfl(nu, 0, 64);
-        if (prev == cb && (uint32_t)cb < nu) {
+        nu2 = __shfl(nu2, 0, 64);
+        if (prev == cb && cl < nu2) {
             if (lane == 0) {
                 *o_slot = (uint32_t)best;
-                *o_unit = (uint32_t)cb;
+                *o_unit = cl;
+                *o_count = min(take, nu2 - cl);
                 *o_seq = (uint32_t)(cb >> 32);
             }
             return;
         }
     }
+}
+
+// Serving: a block reports `units` finished units of ring entry `slot`
+// (request `tag`) and the work it did on them (the lanes' counters, which it
+// then clears); the block whose report completes the entry writes the
+// request's estimate and then its flag in host memory.  Block-wide.
+__device__ void ring_report(const StreamRing &ring, const QueryDesc &d, uint32_t slot,
+                            uint32_t tag, uint32_t units, int lane, uint32_t &st_moves,
+                            uint32_t &st_draws, uint32_t &st_meets, uint32_t &st_tail,
+                            uint32_t &st_pairs, uint32_t *s_last) {
+    unsigned long long w0 = st_moves, w1 = st_draws, w2 = st_meets, w3 = st_tail, w4 = st_pairs;
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        w0 += __shfl_xor(w0, dd, 64);
+        w1 += __shfl_xor(w1, dd, 64);
+        w2 += __shfl_xor(w2, dd, 64);
+        w3 += __shfl_xor(w3, dd, 64);
+        w4 += __shfl_xor(w4, dd, 64);
+    }
+    unsigned long long *ec = ring.counters + (size_t)slot * 8;
+    if (lane == 0) {
+        if (w0) atomicAdd(&ec[C_MOVES], w0);
+        if (w1) atomicAdd(&ec[C_DRAWS], w1);
+        if (w2) atomicAdd(&ec[C_MEETS], w2);
+        if (w3) atomicAdd(&ec[C_TAIL], w3);
+        if (w4) atomicAdd(&ec[C_PAIRS], w4);
+    }
+    st_moves = st_draws = st_meets = st_tail = st_pairs = 0;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the size is read coherently: a plain load could return the size of
+        // an earlier request in this entry from a cache and miss the last unit
+        const uint32_t old = atomicAdd(&ring.ctl[slot].done, units);
+        const uint32_t nu =
+            __hip_atomic_load(&ring.ctl[slot].n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_last = (old + units == nu) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (*s_last) {
+        __threadfence();
+        for (int64_t v = threadIdx.x; v < d.n; v += blockDim.x) estimate_one(d, v);
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&ring.flags[slot], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
 }
 
 template <int KIND, int NS, bool STREAM>
@@ -305,7 +359,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
     __shared__ uint32_t s_cnt[STRAT ? 1 : MEET_VB];
     __shared__ uint32_t s_vid[MEET_VB];
     __shared__ uint2 s_vrow[MEET_VB];
-    __shared__ uint32_t s_unit, s_item, s_slot, s_seq, s_last;
+    __shared__ uint32_t s_unit, s_item, s_slot, s_seq, s_last, s_run;
     // stratified: classes of the tile's source walks, class starts, the
     // shuffle keys of the unit's nodes, weighted sums
     __shared__ uint8_t s_cls[STRAT ? TJ : 1];
@@ -319,6 +373,9 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n_units = STREAM ? 0u : ustart[nq];
     uint32_t tq_head = 0, tq_tail = 0;   // stitched: the wave's tail ring (wave-uniform)
+    // serving: the request whose finished units this block has not reported yet
+    uint32_t acc_slot = 0, acc_tag = 0, acc_units = 0;
+    uint32_t run_next = 0, run_left = 0;   // serving: claimed units not yet taken
     uint32_t cur_q = 0xffffffffu, cur_tile = 0xffffffffu;
     uint32_t K = 0;
     uint32_t st_moves = 0, st_draws = 0, st_meets = 0, st_tail = 0, st_pairs = 0;
@@ -326,11 +383,24 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
     for (;;) {
         uint32_t unit = 0, tag_s = 0;
         if constexpr (STREAM) {
-            if (threadIdx.x < 64) ring_claim<KIND>(ring, lane, &s_slot, &s_unit, &s_seq);
-            __syncthreads();
-            if (s_slot >= (uint32_t)RING_MAX) break;
-            unit = s_unit;
-            tag_s = s_seq;
+            if (run_left == 0u) {
+                if (threadIdx.x < 64) ring_claim<KIND>(ring, lane, &s_slot, &s_unit, &s_run, &s_seq);
+                __syncthreads();
+                run_next = s_unit;
+                run_left = s_slot < (uint32_t)RING_MAX ? s_run : 0u;
+            }
+            const uint32_t nslot = s_slot, nseq = s_seq;
+            unit = run_next++;
+            if (run_left) --run_left;
+            // the block reports the units it finished of a request, and their
+            // work, once: when it moves on to another request or runs out
+            if (acc_units && (nslot >= (uint32_t)RING_MAX || nseq != acc_tag)) {
+                ring_report(ring, qd[acc_slot], acc_slot, acc_tag, acc_units, lane,
+                            st_moves, st_draws, st_meets, st_tail, st_pairs, &s_last);
+                acc_units = 0;
+            }
+            if (nslot >= (uint32_t)RING_MAX) break;
+            tag_s = nseq;
             // a request this block has not worked on: see its descriptor and
             // buffers as its publication left them
             if (tag_s != cur_q) __threadfence();
@@ -638,14 +708,19 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             if constexpr (STITCHED) {
                 // queue the pairs whose heads ended open (tails[qq]), then
                 // follow queued tails while a wave's worth is waiting
+                bool any_tail = false;
 #pragma unroll
-                for (int qq = 0; qq < NS; ++qq) {
-                    const uint64_t m = __ballot(tails[qq]);
-                    if (tails[qq])
-                        s_tq[wave * TAIL_Q + ((tq_tail + lane_rank(m)) & (TAIL_Q - 1))] =
-                            make_uint2(((sl[qq].pos >> 24) << 16) | sl[qq].aux, sl[qq].o);
-                    tq_tail += (uint32_t)__popcll(m);
-                    if (tq_tail - tq_head >= 64u) drain_tails(64u);
+                for (int qq = 0; qq < NS; ++qq) any_tail |= tails[qq];
+                if (__ballot(any_tail) != 0ull) {
+#pragma unroll
+                    for (int qq = 0; qq < NS; ++qq) {
+                        const uint64_t m = __ballot(tails[qq]);
+                        if (tails[qq])
+                            s_tq[wave * TAIL_Q + ((tq_tail + lane_rank(m)) & (TAIL_Q - 1))] =
+                                make_uint2(((sl[qq].pos >> 24) << 16) | sl[qq].aux, sl[qq].o);
+                        tq_tail += (uint32_t)__popcll(m);
+                        if (tq_tail - tq_head >= 64u) drain_tails(64u);
+                    }
                 }
             }
         }
@@ -660,42 +735,9 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             }
         }
         if constexpr (STREAM) {
-            // the unit's work goes to its entry's counters; the block that
-            // finishes the entry's last unit writes the estimate and raises
-            // the entry's flag in host memory
-            unsigned long long w0 = st_moves, w1 = st_draws, w2 = st_meets, w3 = st_tail,
-                               w4 = st_pairs;
-            for (int dd = 32; dd > 0; dd >>= 1) {
-                w0 += __shfl_xor(w0, dd, 64);
-                w1 += __shfl_xor(w1, dd, 64);
-                w2 += __shfl_xor(w2, dd, 64);
-                w3 += __shfl_xor(w3, dd, 64);
-                w4 += __shfl_xor(w4, dd, 64);
-            }
-            unsigned long long *ec = ring.counters + (size_t)q * 8;
-            if (lane == 0) {
-                if (w0) atomicAdd(&ec[C_MOVES], w0);
-                if (w1) atomicAdd(&ec[C_DRAWS], w1);
-                if (w2) atomicAdd(&ec[C_MEETS], w2);
-                if (w3) atomicAdd(&ec[C_TAIL], w3);
-                if (w4) atomicAdd(&ec[C_PAIRS], w4);
-            }
-            st_moves = st_draws = st_meets = st_tail = st_pairs = 0;
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const uint32_t old = atomicAdd(&ring.ctl[q].done, 1u);
-                s_last = (old + 1u == ring.ctl[q].n_units) ? 1u : 0u;
-            }
-            __syncthreads();
-            if (s_last) {
-                __threadfence();
-                for (int64_t v = threadIdx.x; v < d.n; v += blockDim.x) estimate_one(d, v);
-                __threadfence_system();
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_store(&ring.flags[q], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            ++acc_units;
+            acc_slot = (uint32_t)q;
+            acc_tag = tag;
         }
     }
     if constexpr (STREAM) return;

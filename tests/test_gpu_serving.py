@@ -338,3 +338,25 @@ def test_memory_admission_per_request(served):
         srv.submit(qz)
     assert e.value.code == S.SIMRANK_ENOMEM
     srv.destroy()
+
+
+def test_entry_reuse_with_other_sizes(served):
+    """Ring entries reused many times by requests of other sizes (R = 1521 and
+    9502, plain and stitched, two entries): every request completes (waits
+    with a time limit) and equals the lone call.  A completion decided on a
+    stale copy of an entry's unit count would never finish, or finish early."""
+    g, G = served
+    rng = np.random.default_rng(81)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    qs = [S.make_query(int(rng.choice(act)), c=0.6, eps=(0.05, 0.02)[i % 2], delta=1e-3,
+                       seed=0x6400 + i, mode=S.MODE_STITCHED if i % 3 == 2 else S.MODE_PLAIN)
+          for i in range(36)]
+    lone = [S.simrank_single_source_ex(G, q)[1] for q in qs]
+    srv = S.Server(G, max_slots=2, max_R=9502, max_L=64)
+    for burst in range(3):
+        chunk = list(range(burst * 12, burst * 12 + 12))
+        tickets = [srv.submit(qs[i]) for i in chunk]
+        for t, i in zip(tickets, chunk):
+            _, c, _ = srv.wait(t, timeout_s=120.0, want_out=False)
+            assert np.array_equal(c, lone[i]), i
+    srv.destroy()
