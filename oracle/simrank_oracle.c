@@ -34,10 +34,12 @@
  *
  * Parity status: Philox, plain walks and plain meet counts are pinned by
  * published known-answer vectors, closed forms and distribution tests.  The
- * stitched-walk functions are pinned only by their special cases (a segment at
+ * stitched-walk functions are pinned by their special cases (a segment at
  * least as long as the walk cap reduces them to plain walks, heads equal plain
- * prefixes, serial traversal); the statistical effect of shared tails has no
- * closed form: parity unpinned for that effect.  The length-stratified
+ * prefixes, serial traversal) and, for the effect of shared pool slots, by the
+ * exact meeting probability of two stitched walks on a six-node graph,
+ * enumerated over every outcome of heads, entry picks and slot contents
+ * (tests/test_oracle_stitched_exact.py).  The length-stratified
  * estimator is pinned by its expectation, computed exactly from first-meeting
  * probabilities (oracle/exact.py), by the permutation property of the shuffle
  * and by the class sizes.

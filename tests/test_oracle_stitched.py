@@ -3,9 +3,9 @@
 What pins it: pool sizes by an independent count; a segment length of at least
 the walk cap reduces a stitched walk to the plain walk bit for bit; the private
 head equals the plain walk's prefix; every move follows an in-edge; segment
-chains re-derived here from single draws.  The statistical effect of shared
-tails has no closed form (parity unpinned for that effect): it is only bounded
-empirically against exact SimRank below.
+chains re-derived here from single draws.  The effect of shared tails is
+pinned exactly on a tiny graph in test_oracle_stitched_exact.py; below it is
+also bounded empirically against exact SimRank.
 """
 import math
 
