@@ -1038,7 +1038,7 @@ def bench_serving(args):
             tickets.append(srv.submit(q))
         lat, qwait, wsteps = [], [], 0
         for i, t in enumerate(tickets):
-            _, c, info = srv.wait(t, want_counts=i < len(lone_counts))
+            _, c, info = srv.wait(t, timeout_s=300.0, want_counts=i < len(lone_counts))
             if c is not None:
                 served_equal &= bool(np.array_equal(c, lone_counts[i]))
             lat.append(info.latency_s)
@@ -1046,6 +1046,8 @@ def bench_serving(args):
             wsteps += info.stats.moves + info.stats.tail_steps + info.stats.source_moves
         t_end = time.perf_counter()
         levels.append({"load": load, "offered_qps": qps if load != "burst" else None,
+                       "arrivals_qps": (len(reqs) / float(np.sum(gaps))) if load != "burst"
+                       else None,
                        "achieved_qps": len(reqs) / (t_end - t_start),
                        "served_vs_plain": len(reqs) / (t_end - t_start) / capacity,
                        "walk_steps_per_s": wsteps / (t_end - t_start),
@@ -1082,7 +1084,8 @@ def bench_serving(args):
         "server_load": srv.load(),
         "index_tuner": {"seg_log2": [2, 3, 4], "meet_ms": index_ms, "choice": index_choice},
         "tuning": tuning,
-        "roofline": roofline("k_meet<stitched> (fused walk + meet + count), requests one at a time",
+        "roofline": roofline(f"k_meet<{args.served_mode}> (fused walk + meet + count), "
+                             "requests one at a time",
                              kmoves, kms / 1e3),
         "measured_roofs": {"footprint_bytes": footprint,
                            "random_gather_8B_per_s": gather["per_s"],

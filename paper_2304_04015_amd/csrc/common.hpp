@@ -294,20 +294,28 @@ int launch_groups(const GroupSet &gs, unsigned long long *counters, hipStream_t 
 
 // ------------------------------------------------------------ serving ring
 // The server's in-flight requests (server.hip) sit in a ring of entries that
-// persistent meet kernels take work units from.  An entry is published by the
-// last kernel of its request's preparation: the fields first, then `claim` =
-// seq << 32 (release).  A block claims unit u of an entry by moving `claim`
-// from (seq, u) to (seq, u + 1) with compare-and-swap, so a claim can never
-// land on a later request that reuses the entry.  The block that finishes the
-// entry's last unit writes the estimate and then the entry's flag in host
-// memory (the request's seq).
+// persistent meet kernels take work units from.  An entry's `claim` word holds
+// everything a block needs to decide whether it may take units from it:
+//   claim = (seq << 2 | kind) << 32 | units not yet claimed,
+// so availability, kind and age come from one atomic read, never from fields
+// that a reuse of the entry may be rewriting.  An entry is published by the
+// last kernel of its request's preparation: the other fields first, then
+// `claim` with all n_units units unclaimed (release).  A block takes up to a
+// run of units by moving the count down with compare-and-swap (acquire), then
+// reads n_units (the first unit it took is n_units minus the count it saw).
+// A swap cannot succeed on an older request's word once the entry has been
+// reused (seq differs), and a fully claimed word (count 0) is never a
+// candidate.  The block that finishes the entry's last unit writes the
+// estimate and then the entry's flag in host memory (the request's seq).
+// seq is nonzero and below 2^30.
 constexpr int RING_MAX = 64;
+constexpr uint32_t RING_SEQ_LIMIT = 1u << 30;
 struct RingCtl {
-    unsigned long long claim;   // (seq << 32) | units claimed; 0 = never published
+    unsigned long long claim;   // see above; 0 = never published
     uint32_t n_units;           // tiles x node chunks of the request
     uint32_t done;              // units finished
     int32_t kind;               // Kind of the meet kernel that takes it
-    uint32_t seq;               // the request's sequence number (nonzero)
+    uint32_t seq;               // the request's sequence number
     uint32_t pad[2];
 };
 struct StreamRing {

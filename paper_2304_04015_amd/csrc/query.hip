@@ -239,14 +239,12 @@ __global__ __launch_bounds__(1024) void k_unit_offsets(const QueryDesc *__restri
 
 // Serving (STREAM): wave 0 of a block claims the next units from the ring:
 // among published entries of the kernel's kind with unclaimed units, the
-// oldest (smallest seq); the claim is a compare-and-swap of its (seq, claimed)
-// word that takes up to RING_RUN consecutive units (consecutive node chunks
-// of one tile).  A failed swap means another block took them: look again.
-// The entry's words are read with device-coherent atomic loads and no fence:
-// the block fences only when it moves to a request it has not worked on
-// (below), so its caches keep the graph's rows from unit to unit.  Units
-// beyond the entry's size as read again after the swap (possible only if the
-// scan read a size older than the entry's publication) are dropped.
+// oldest (smallest seq), all read from the entries' claim words alone; the
+// claim is a compare-and-swap (acquire) that counts down up to RING_RUN
+// consecutive units (consecutive node chunks of one tile).  A failed swap
+// means another block took them, or the entry was republished: look again.
+// The block fences only when it moves to a request it has not worked on
+// (below), so its caches keep the graph's rows from unit to unit.
 // *o_slot = RING_MAX when no entry has units left.
 constexpr uint32_t RING_RUN = 4;
 template <int KIND>
@@ -254,16 +252,11 @@ __device__ void ring_claim(const StreamRing &ring, int lane, uint32_t *o_slot, u
                            uint32_t *o_count, uint32_t *o_seq) {
     for (;;) {
         unsigned long long key = ~0ull, c = 0ull;
-        uint32_t nu = 0u;
         if (lane < ring.entries) {
-            RingCtl &e = ring.ctl[lane];
-            c = __hip_atomic_load(&e.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t seq = (uint32_t)(c >> 32), cl = (uint32_t)c;
-            if (seq != 0u &&
-                __hip_atomic_load(&e.kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KIND) {
-                nu = __hip_atomic_load(&e.n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (cl < nu) key = ((unsigned long long)seq << 32) | (uint32_t)lane;
-            }
+            c = __hip_atomic_load(&ring.ctl[lane].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t tag = (uint32_t)(c >> 32), left = (uint32_t)c;
+            if (tag != 0u && (tag & 3u) == (uint32_t)KIND && left > 0u)
+                key = ((unsigned long long)(tag >> 2) << 32) | (uint32_t)lane;
         }
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(key, off, 64);
@@ -275,25 +268,24 @@ __device__ void ring_claim(const StreamRing &ring, int lane, uint32_t *o_slot, u
         }
         const int best = (int)(uint32_t)key;
         const unsigned long long cb = __shfl(c, best, 64);
-        const uint32_t cl = (uint32_t)cb;
-        const uint32_t take = min(RING_RUN, __shfl(nu, best, 64) - cl);
-        unsigned long long prev = 0ull;
-        uint32_t nu2 = 0u;
+        const uint32_t left = (uint32_t)cb;
+        const uint32_t take = min(RING_RUN, left);
+        bool won = false;
         if (lane == 0) {
-            prev = atomicCAS(&ring.ctl[best].claim, cb, cb + take);
-            nu2 = __hip_atomic_load(&ring.ctl[best].n_units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        prev = __shfl(prev, 0, 64);
-        nu2 = __shfl(nu2, 0, 64);
-        if (prev == cb && cl < nu2) {
-            if (lane == 0) {
+            unsigned long long expect = cb;
+            won = __hip_atomic_compare_exchange_strong(&ring.ctl[best].claim, &expect, cb - take,
+                                                       __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (won) {
+                const uint32_t nu = __hip_atomic_load(&ring.ctl[best].n_units, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
                 *o_slot = (uint32_t)best;
-                *o_unit = cl;
-                *o_count = min(take, nu2 - cl);
-                *o_seq = (uint32_t)(cb >> 32);
+                *o_unit = nu - left;
+                *o_count = take;
+                *o_seq = (uint32_t)(cb >> 34);
             }
-            return;
         }
+        if (__shfl((int)won, 0, 64)) return;
     }
 }
 
@@ -679,7 +671,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             uint2 e[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq)
-                if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
+                if (go[qq]) e[qq] = load_edge(d.E, at[qq], sl[qq].t);
             bool tails[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) tails[qq] = false;
@@ -911,8 +903,8 @@ __global__ __launch_bounds__(256) void k_publish(StreamRing ring, int32_t slot, 
             c.kind = d.kind;
             c.seq = seq;
             __threadfence();
-            __hip_atomic_store(&c.claim, (unsigned long long)seq << 32, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long tag = ((unsigned long long)seq << 2) | (uint32_t)d.kind;
+            __hip_atomic_store(&c.claim, (tag << 32) | nu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }

@@ -19,10 +19,10 @@
 // request.  Plain, stitched and stratified requests are served.
 //
 // With group_max >= 2, plain or stitched requests that share (mode, seed, c,
-// cap) and wait together are admitted as one query group (group.hip), which
-// walks each (v, j) once for all of them; a group is one launch on a worker
-// stream (one group in flight at a time).  Every result equals the lone
-// query's.
+// cap) wait while a request with the same walks runs, and those that then
+// wait together are admitted as one query group (group.hip), which walks each
+// (v, j) once for all of them; a group is one launch on a worker stream (one
+// group in flight at a time).  Every result equals the lone query's.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -288,7 +288,8 @@ static bool reserve(simrank_server *S, Request *r, bool lone) {
 
 // Enqueues a lone request's preparation and publication into its ring entry.
 static int prepare(simrank_server *S, Request *r) {
-    r->seq = S->next_seq++;
+    r->seq = S->next_seq;
+    S->next_seq = S->next_seq + 1 < RING_SEQ_LIMIT ? S->next_seq + 1 : 1u;
     if (r->mode == SIMRANK_MODE_STRATIFIED) {
         StratParams sp;
         StratTab *tab = S->tabs_host + r->slot;
@@ -439,47 +440,61 @@ static void server_loop(simrank_server *S) {
                 progressed = true;
                 S->cv_done.notify_all();
             }
-            if (S->gmax >= 2 && !S->grp.busy && !S->queue.empty()) {
-                // the requests waiting with the same walks as the oldest one
-                Request *head = S->queue.front();
-                if (head->mode != SIMRANK_MODE_STRATIFIED) {
+            // With groups, requests that share their walks with a running
+            // request wait until it has finished; those that then wait
+            // together start as one group (or alone, if only one waits), so
+            // that under load the arrivals gather into groups while the
+            // device works on the previous ones.
+            auto walks_running = [&](const Request *r) {
+                for (const Request *o : running)
+                    if (o->mode != SIMRANK_MODE_STRATIFIED && same_walks(o, r)) return true;
+                return false;
+            };
+            if (S->gmax >= 2 && !S->grp.busy) {
+                for (Request *head : S->queue) {
+                    if (head->mode == SIMRANK_MODE_STRATIFIED || walks_running(head)) continue;
                     for (Request *r : S->queue)
                         if ((int32_t)group.size() < S->gmax && same_walks(head, r)) group.push_back(r);
-                    if (group.size() >= 2) {
-                        size_t kept = 0;
-                        for (Request *r : group) {
-                            if (!reserve(S, r, false)) break;
-                            ++kept;
-                        }
-                        if (kept < 2) {
-                            for (size_t i = 0; i < kept; ++i) {
-                                S->alloc.release(group[i]->mem_off, group[i]->mem_bytes);
-                                group[i]->mem_bytes = 0;
-                                --S->inflight;
-                            }
-                            group.clear();
-                        } else {
-                            group.resize(kept);
-                            for (Request *r : group)
-                                S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
-                        }
-                    } else {
+                    if (group.size() < 2) {
                         group.clear();
+                        continue;
                     }
+                    size_t kept = 0;
+                    for (Request *r : group) {
+                        if (!reserve(S, r, false)) break;
+                        ++kept;
+                    }
+                    if (kept < 2) {
+                        for (size_t i = 0; i < kept; ++i) {
+                            S->alloc.release(group[i]->mem_off, group[i]->mem_bytes);
+                            group[i]->mem_bytes = 0;
+                            --S->inflight;
+                        }
+                        group.clear();
+                    } else {
+                        group.resize(kept);
+                        for (Request *r : group)
+                            S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+                    }
+                    break;   // one group in flight at a time
                 }
             }
-            // lone admission, oldest first; with groups, a request that has a
-            // partner with the same walks in the queue waits for a group
+            // lone admission, oldest first; with groups, a request whose walks
+            // a running request or a group just formed shares, or that has a
+            // partner waiting, waits
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request *r = *it;
-                bool partner = false;
-                if (S->gmax >= 2 && r->mode != SIMRANK_MODE_STRATIFIED)
-                    for (Request *o : S->queue)
+                bool wait = false;
+                if (S->gmax >= 2 && r->mode != SIMRANK_MODE_STRATIFIED) {
+                    wait = walks_running(r);
+                    for (const Request *o : group) wait |= same_walks(o, r);
+                    for (const Request *o : S->queue)
                         if (o != r && same_walks(o, r)) {
-                            partner = true;
+                            wait = true;
                             break;
                         }
-                if (partner) {
+                }
+                if (wait) {
                     ++it;
                     continue;
                 }

@@ -158,6 +158,27 @@ def test_grouped_admission_equals_lone(served):
         S.Server(G, max_slots=2, group_max=33)
 
 
+def test_arrivals_during_a_run_gather_into_a_group(served):
+    """A grouping server: one request starts alone; eight more with the same
+    walks arrive while it runs, wait for it, and start together as one group.
+    Every result equals the lone query's."""
+    g, G = served
+    rng = np.random.default_rng(29)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    qs = [S.make_query(int(rng.choice(act)), c=0.6, eps=0.02 if i == 0 else 0.05, delta=1e-3,
+                       seed=0x5EC0) for i in range(9)]
+    lone = [S.simrank_single_source_ex(G, q)[1] for q in qs]
+    srv = S.Server(G, max_slots=8, max_R=9502, max_L=64, group_max=8)
+    tickets = [srv.submit(q) for q in qs]
+    for t, c1 in zip(tickets, lone):
+        _, c, _ = srv.wait(t, timeout_s=120.0, want_out=False)
+        assert np.array_equal(c, c1)
+    k = srv.counts()
+    assert k["done"] == 9 and k["failed"] == 0
+    assert k["groups"] >= 1 and k["grouped"] >= 8, k
+    srv.destroy()
+
+
 def test_concurrent_submitters_with_groups(served):
     """Four client threads submit and wait at once (plain and stitched requests,
     two seeds) into a grouping server: every result equals the lone query's."""
@@ -341,22 +362,34 @@ def test_memory_admission_per_request(served):
 
 
 def test_entry_reuse_with_other_sizes(served):
-    """Ring entries reused many times by requests of other sizes (R = 1521 and
-    9502, plain and stitched, two entries): every request completes (waits
-    with a time limit) and equals the lone call.  A completion decided on a
-    stale copy of an entry's unit count would never finish, or finish early."""
+    """Ring entries reused many times by requests of other sizes and kinds
+    (plain and stitched with R = 1521 or 9502, stratified with N = 1,150;
+    two entries): every request completes (waits with a time limit) and
+    equals the lone call.  A block that took units of a reused entry under
+    the previous request's tag, or with the previous request's kind, would
+    leave the new request's completion count off by its units (never
+    finishing) or add counts walked with the wrong kernel."""
     g, G = served
     rng = np.random.default_rng(81)
     act = np.nonzero(g.in_degree() > 0)[0]
-    qs = [S.make_query(int(rng.choice(act)), c=0.6, eps=(0.05, 0.02)[i % 2], delta=1e-3,
-                       seed=0x6400 + i, mode=S.MODE_STITCHED if i % 3 == 2 else S.MODE_PLAIN)
-          for i in range(36)]
-    lone = [S.simrank_single_source_ex(G, q)[1] for q in qs]
+    qs = []
+    for i in range(36):
+        s = int(rng.choice(act))
+        if i % 4 == 3:
+            qs.append(S.make_stratified_query(s, c=0.6, eps=0.05, seed=0x6400 + i, z=1200, phi=12))
+        else:
+            qs.append(S.make_query(s, c=0.6, eps=(0.05, 0.02)[i % 2], delta=1e-3, seed=0x6400 + i,
+                                   mode=S.MODE_STITCHED if i % 3 == 2 else S.MODE_PLAIN))
+    lone = [S.simrank_single_source_stratified(G, q)[2] if q.mode == S.MODE_STRATIFIED
+            else S.simrank_single_source_ex(G, q)[1] for q in qs]
     srv = S.Server(G, max_slots=2, max_R=9502, max_L=64)
     for burst in range(3):
         chunk = list(range(burst * 12, burst * 12 + 12))
         tickets = [srv.submit(qs[i]) for i in chunk]
         for t, i in zip(tickets, chunk):
-            _, c, _ = srv.wait(t, timeout_s=120.0, want_out=False)
-            assert np.array_equal(c, lone[i]), i
+            if qs[i].mode == S.MODE_STRATIFIED:
+                got = srv.wait_stratified(t, timeout_s=120.0)[2]
+            else:
+                got = srv.wait(t, timeout_s=120.0, want_out=False)[1]
+            assert np.array_equal(got, lone[i]), i
     srv.destroy()
