@@ -39,30 +39,17 @@ __device__ __forceinline__ T block_excl_sum(T x, T *total) {
     return before + inc - x;
 }
 
-// The walk's gather of edge slot `at` at step t.  SRK_EDGE_LOAD selects the
-// cache policy (0: default, 1: non-temporal, 3: non-temporal from step
-// SRK_NT_STEP on, through a buffer load, for arrays below 4 GB).
+// The walk's gather of an edge slot.  SRK_EDGE_LOAD selects the cache policy
+// (0: default, 1: non-temporal).
 #ifndef SRK_EDGE_LOAD
 #define SRK_EDGE_LOAD 0
 #endif
-#ifndef SRK_NT_STEP
-#define SRK_NT_STEP 4
-#endif
-__device__ __forceinline__ uint2 load_edge(const uint2 *E, uint32_t at, uint32_t t) {
+__device__ __forceinline__ uint2 load_edge(const uint2 *p) {
 #if SRK_EDGE_LOAD == 1
-    (void)t;
-    const uint64_t v = __builtin_nontemporal_load((const uint64_t *)(E + at));
+    const uint64_t v = __builtin_nontemporal_load((const uint64_t *)p);
     return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
-#elif SRK_EDGE_LOAD == 3
-    if (t >= SRK_NT_STEP) {
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void *)E, 0, -1, 0x00020000);
-        return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, at * 8u, 0, 2));
-    }
-    return E[at];
 #else
-    (void)t;
-    return E[at];
+    return *p;
 #endif
 }
 

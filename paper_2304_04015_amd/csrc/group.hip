@@ -471,7 +471,7 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_meet_group(const GroupDesc *__r
             int64_t tb[NS], te[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) {
-                if (go[qq]) e[qq] = load_edge(d.E, at[qq], sl[qq].t);
+                if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
                 if (STITCHED && sl[qq].busy && sl[qq].ph) {
                     const GSlot<GW> &w = sl[qq];
                     switch (w.ph) {

@@ -671,7 +671,7 @@ __global__ __launch_bounds__(meet_block_of(KIND)) void k_meet(const QueryDesc *_
             uint2 e[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq)
-                if (go[qq]) e[qq] = load_edge(d.E, at[qq], sl[qq].t);
+                if (go[qq]) e[qq] = load_edge(d.E + at[qq]);
             bool tails[NS];
 #pragma unroll
             for (int qq = 0; qq < NS; ++qq) tails[qq] = false;
