@@ -66,18 +66,26 @@ def roofline(kernel: str, moves: float, seconds: float, traffic=None, traffic_so
     return r
 
 
+STITCH_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stitching_rmat24.json")
+SEG_SLOTS = 3   # segments in flight per lane of the index build's walk kernel
+
+
 def kernel_fingerprint() -> str:
-    """sha256 (16 hex digits) of the sources the meet kernels are built from."""
+    """sha256 (16 hex digits) of the sources the walk kernels are built from
+    (the meet kernels and the index build)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_04015_amd", "csrc")
     h = b"".join(open(os.path.join(csrc, f), "rb").read()
-                 for f in ("query.hip", "group.hip", "device_common.hpp", "philox.hpp", "common.hpp"))
+                 for f in ("query.hip", "group.hip", "index.hip", "device_common.hpp", "philox.hpp",
+                           "common.hpp"))
     return hashlib.sha256(h).hexdigest()[:16]
 
 
-def measured_traffic(path: str):
-    """HBM bytes per meet launch from the profiler's byte counters (scaled by a
-    copy kernel of known size), if they were taken on the current kernel."""
+def measured_traffic(path: str, kernel: str = None):
+    """HBM bytes per launch from the profiler's byte counters (scaled by a copy
+    kernel of known size), if they were taken on the current kernel sources;
+    `kernel` picks one kernel of a record that holds several (mean over its
+    launches)."""
     if not os.path.exists(path):
         return None
     try:
@@ -86,7 +94,10 @@ def measured_traffic(path: str):
         return None
     if t.get("source_sha256_16") != kernel_fingerprint():
         return None
-    return t.get("bytes_per_launch")
+    if kernel is None:
+        return t.get("bytes_per_launch")
+    b = t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+    return float(sum(b) / len(b)) if b else None
 
 
 def copy_probe(args) -> None:
@@ -676,6 +687,8 @@ def bench_stitching(args):
             "graph_load_s": load_s,
             "segments_kernel": {
                 "ms": seg_ms,
+                "traffic": measured_traffic(STITCH_TRAFFIC, f"k_segments<{SEG_SLOTS}>")
+                if cfg["seg_log2"] == 3 and args.scale == 0 else None,
                 "moves_per_s": info["build_moves"] / (seg_ms * 1e-3),
                 "moves_vs_random_gather": info["build_moves"] / (seg_ms * 1e-3) / gather["per_s"],
                 "achieved_GBps": seg_bytes / (seg_ms * 1e-3) / 1e9,
@@ -683,6 +696,8 @@ def bench_stitching(args):
             },
             "doubling_kernels": {
                 "ms": dbl_ms,
+                "traffic_per_round": measured_traffic(STITCH_TRAFFIC, "k_double")
+                if args.scale == 0 else None,
                 "rounds": info["levels"],
                 "achieved_GBps": dbl_bytes / (dbl_ms * 1e-3) / 1e9 if dbl_ms > 0 else 0.0,
                 "frac": dbl_bytes / (dbl_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if dbl_ms > 0 else 0.0,
@@ -693,6 +708,10 @@ def bench_stitching(args):
         "plain_query": {"moves": stp.moves, "meet_ms": stp.meet_ms, "ms": stp.ms},
         "roofline": roofline("k_meet<stitched> (fused walk + meet + count)",
                              st.moves + st.tail_steps, st.meet_ms / 1e3,
+                             traffic=measured_traffic(STITCH_TRAFFIC, "k_meet<1, 2, false>"),
+                             traffic_source="not measured in this run: bytes per launch from "
+                                            "rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                            "profiles/traffic_stitching_rmat24.json",
                              bound="random-gather (HBM: the graph exceeds the Infinity Cache)"),
         "measured_roofs": {"footprint_bytes": footprint,
                            "random_gather_8B_per_s": gather["per_s"],

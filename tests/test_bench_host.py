@@ -24,6 +24,12 @@ def test_traffic_only_for_the_current_kernel_sources(tmp_path):
     broken.write_text("{")
     assert bench.measured_traffic(str(broken)) is None
     assert bench.measured_traffic(str(tmp_path / "missing.json")) is None
+    multi = tmp_path / "m.json"
+    multi.write_text(json.dumps({"source_sha256_16": fp, "kernels": {
+        "k_a": {"bytes_per_launch": [10.0, 20.0]}, "k_b": {"bytes_per_launch": []}}}))
+    assert bench.measured_traffic(str(multi), "k_a") == 15.0
+    assert bench.measured_traffic(str(multi), "k_b") is None
+    assert bench.measured_traffic(str(multi), "k_c") is None
 
 
 def test_more_than_one_gpu_is_refused():
