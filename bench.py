@@ -67,7 +67,7 @@ def roofline(kernel: str, moves: float, seconds: float, traffic=None, traffic_so
 
 
 STITCH_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stitching_rmat24.json")
-SEG_SLOTS = 3   # segments in flight per lane of the index build's walk kernel
+SEG_SLOTS = 2   # segments in flight per lane of the index build's walk kernel
 
 
 def kernel_fingerprint() -> str:
@@ -687,7 +687,7 @@ def bench_stitching(args):
             "graph_load_s": load_s,
             "segments_kernel": {
                 "ms": seg_ms,
-                "traffic": measured_traffic(STITCH_TRAFFIC, f"k_segments<{SEG_SLOTS}>")
+                "traffic": measured_traffic(STITCH_TRAFFIC, f"k_segments<{SEG_SLOTS}, {seg_len}>")
                 if cfg["seg_log2"] == 3 and args.scale == 0 else None,
                 "moves_per_s": info["build_moves"] / (seg_ms * 1e-3),
                 "moves_vs_random_gather": info["build_moves"] / (seg_ms * 1e-3) / gather["per_s"],

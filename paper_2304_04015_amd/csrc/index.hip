@@ -19,10 +19,14 @@
 
 // Segments in flight per lane and consecutive slots per wave of k_segments.
 #ifndef SRK_SEG_SLOTS
-#define SRK_SEG_SLOTS 3
+#define SRK_SEG_SLOTS 2
 #endif
 #ifndef SRK_SEG_CHUNK
 #define SRK_SEG_CHUNK 2048
+#endif
+// 1: rows of up to 16 positions are assembled in registers and written once.
+#ifndef SRK_SEG_BUFFER
+#define SRK_SEG_BUFFER 1
 #endif
 
 namespace srk {
@@ -72,7 +76,10 @@ struct SegArgs {
     int64_t chunk;       // consecutive slots per wave
 };
 
-// One segment being built on a lane.
+// One segment being built on a lane.  LB > 0: the segment's positions are
+// kept in registers (LB = 2^k words) and its row is written once, whole, when
+// the segment ends.
+template <int LB>
 struct SegSlot {
     uint32_t sig;        // its slot
     uint32_t y;          // the node whose pool holds it
@@ -80,7 +87,31 @@ struct SegSlot {
     uint32_t t;          // moves made
     uint32_t ph;         // SEG_*: what the slot waits for
     WalkDraws w;         // the segment's draws (walk index = i, its rank in y's pool)
+    uint32_t pos[LB > 0 ? LB : 1];   // positions 1..t, NIL after (LB > 0)
 };
+
+// Position t + 1 of a buffered segment (selects, so that the array stays in
+// registers).
+template <int LB>
+__device__ __forceinline__ void seg_put(SegSlot<LB> &s, uint32_t o) {
+#pragma unroll
+    for (int k = 0; k < LB; ++k) s.pos[k] = (s.t == (uint32_t)k) ? o : s.pos[k];
+}
+
+// A buffered segment's whole row, in 16-byte pieces where it has four words
+// or more.
+template <int LB>
+__device__ __forceinline__ void seg_write_row(const SegSlot<LB> &s, uint32_t *seg) {
+    uint32_t *row = seg + (size_t)s.sig * LB;
+    if constexpr (LB >= 4) {
+#pragma unroll
+        for (int k = 0; k < LB; k += 4)
+            *(uint4 *)(row + k) = make_uint4(s.pos[k], s.pos[k + 1], s.pos[k + 2], s.pos[k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < LB; ++k) row[k] = s.pos[k];
+    }
+}
 
 // Phases of a segment slot.  Every phase but IDLE issues one load per
 // iteration, so a lane keeps NS independent loads in flight.
@@ -102,7 +133,7 @@ enum : uint32_t {
 // segment's row is first filled with NIL and then receives one position per
 // move.  succ(sigma) is picked from the pool of the node where an open segment
 // ends.
-template <int NS>
+template <int NS, int LB>
 __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -112,7 +143,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
     int64_t cursor = c0;
     const uint32_t L = (uint32_t)a.seg_len;
     uint32_t moves = 0;
-    SegSlot sl[NS];
+    SegSlot<LB> sl[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) sl[q].ph = SEG_IDLE;
 
@@ -144,7 +175,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
         int64_t b0[NS], b1[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            SegSlot &s = sl[q];
+            SegSlot<LB> &s = sl[q];
             switch (s.ph) {
             case SEG_OWNER: u[q] = a.owner[s.sig]; break;
             case SEG_START: b0[q] = a.pool_off[s.y]; e[q] = a.nodes[s.y]; break;
@@ -152,6 +183,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
                 const uint2 x = walk_draw_next(s.w, a.key);   // step t + 1
                 if (x.x >= a.T || s.d == 0u) {
                     s.ph = SEG_IDLE;                           // closed before 2^k moves
+                    if constexpr (LB > 0) seg_write_row(s, a.seg);
                     a.seg_lens[s.sig] = (uint8_t)s.t;
                     a.succ[s.sig] = NIL;
                     if (a.width == 1) a.chain[s.sig] = s.sig;
@@ -168,7 +200,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
         // consume
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            SegSlot &s = sl[q];
+            SegSlot<LB> &s = sl[q];
             switch (s.ph) {
             case SEG_OWNER:
                 s.y = u[q];
@@ -180,12 +212,17 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
                 s.o = e[q].x;
                 s.d = e[q].y;
                 s.t = 0;
-                uint32_t *row = a.seg + (size_t)s.sig * L;
-                if (L >= 4) {
-                    for (uint32_t k = 0; k < L; k += 4)
-                        *(uint4 *)(row + k) = make_uint4(NIL, NIL, NIL, NIL);
+                if constexpr (LB > 0) {
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) s.pos[k] = NIL;
                 } else {
-                    for (uint32_t k = 0; k < L; ++k) row[k] = NIL;
+                    uint32_t *row = a.seg + (size_t)s.sig * L;
+                    if (L >= 4) {
+                        for (uint32_t k = 0; k < L; k += 4)
+                            *(uint4 *)(row + k) = make_uint4(NIL, NIL, NIL, NIL);
+                    } else {
+                        for (uint32_t k = 0; k < L; ++k) row[k] = NIL;
+                    }
                 }
                 s.ph = SEG_WALK;
                 break;
@@ -193,10 +230,14 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a) {
             case SEG_WALK:
                 s.o = e[q].x;
                 s.d = e[q].y;
-                a.seg[(size_t)s.sig * L + s.t] = s.o;
+                if constexpr (LB > 0) seg_put(s, s.o);
+                else a.seg[(size_t)s.sig * L + s.t] = s.o;
                 ++s.t;
                 ++moves;
-                if (s.t == L) s.ph = SEG_END;
+                if (s.t == L) {
+                    if constexpr (LB > 0) seg_write_row(s, a.seg);
+                    s.ph = SEG_END;
+                }
                 break;
             case SEG_END:
                 // keep the walk index for the successor draw; y becomes z
@@ -401,7 +442,17 @@ extern "C" int simrank_build_index(simrank_graph *g, const simrank_index_params 
                    total, SRK_SEG_CHUNK};
         const int64_t waves = (total + SRK_SEG_CHUNK - 1) / SRK_SEG_CHUNK;
         IX_HIP(hipEventRecord(es0, st));
-        k_segments<SRK_SEG_SLOTS><<<grid_for(waves * 64, 256), 256, 0, st>>>(sa);
+        // rows of up to 16 positions are assembled in registers and written
+        // once; longer ones are written position by position
+        const unsigned gs = grid_for(waves * 64, 256);
+        switch (SRK_SEG_BUFFER ? ix->seg_len : 0) {
+        case 1: k_segments<SRK_SEG_SLOTS, 1><<<gs, 256, 0, st>>>(sa); break;
+        case 2: k_segments<SRK_SEG_SLOTS, 2><<<gs, 256, 0, st>>>(sa); break;
+        case 4: k_segments<SRK_SEG_SLOTS, 4><<<gs, 256, 0, st>>>(sa); break;
+        case 8: k_segments<SRK_SEG_SLOTS, 8><<<gs, 256, 0, st>>>(sa); break;
+        case 16: k_segments<SRK_SEG_SLOTS, 16><<<gs, 256, 0, st>>>(sa); break;
+        default: k_segments<SRK_SEG_SLOTS, 0><<<gs, 256, 0, st>>>(sa); break;
+        }
         IX_HIP(hipEventRecord(es1, st));
         const uint32_t *J = ix->succ;
         for (int32_t r = 0; r < ix->levels; ++r) {
