@@ -55,6 +55,7 @@ extern "C" {
 #define SIMRANK_ENOMEM 2   /* device or host allocation failed, or admission refused */
 #define SIMRANK_EDEVICE 3  /* a HIP call failed */
 #define SIMRANK_ESTATE 4   /* call not valid in the object's state (e.g. no index built) */
+#define SIMRANK_EIO 5      /* a file could not be opened, written or closed */
 
 #define SIMRANK_MODE_PLAIN 0     /* every walk generated step by step */
 #define SIMRANK_MODE_STITCHED 1  /* private head + tail read from the segment index */
@@ -303,6 +304,24 @@ int simrank_index_info(const simrank_graph *g, simrank_index_summary *out);
  * at sigma[i]: sigma[i], succ(sigma[i]), succ^2(sigma[i]), ..., -1 padded. */
 int simrank_index_read(const simrank_graph *g, const int64_t *sigma, int64_t count,
                        int32_t *nodes, int32_t *lens, int64_t *succ, int64_t *chain_opt);
+
+/* Checkpoint and resume of the stitched-walk index (the index of Section
+ * 4.1's segments and Theorem 2's doubled chains, as simrank_build_index
+ * made it), so that a server can restart on the same graph without a
+ * rebuild.  simrank_index_save writes the graph's index to the file at
+ * `path` (a 128-byte header with the graph's fingerprint and a checksum of
+ * every array, then the arrays; about the index's device bytes); ESTATE if no
+ * index is built, EIO if the file cannot be written.  simrank_index_load
+ * reads such a file into device memory and makes it the graph's index,
+ * replacing any earlier one (batch plans made before refuse to run, as after
+ * a rebuild); stitched queries then give the counts they gave with the saved
+ * index.  EINVAL, with the graph's index unchanged, if the file was written
+ * for another graph (n, m or the fingerprint of its gather layout differ), is
+ * truncated or longer than its arrays, or its arrays do not match their
+ * checksums; EIO if it cannot be opened.  Synchronous; the same threading
+ * rule as simrank_build_index. */
+int simrank_index_save(const simrank_graph *g, const char *path);
+int simrank_index_load(simrank_graph *g, const char *path);
 
 /* ----------------------------------------------------------------- batch */
 

@@ -22,10 +22,10 @@ LIB_PATH = os.environ.get("SIMRANK_LIB") or os.path.join(HERE, "libsimrank.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HEADER = os.path.join(INCLUDE, "simrank.h")
 
-SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE = 0, 1, 2, 3, 4
+SIMRANK_OK, SIMRANK_EINVAL, SIMRANK_ENOMEM, SIMRANK_EDEVICE, SIMRANK_ESTATE, SIMRANK_EIO = 0, 1, 2, 3, 4, 5
 MODE_PLAIN, MODE_STITCHED, MODE_STRATIFIED = 0, 1, 2
 PLAN_GROUPS = 1                   # simrank_batch_plan_create_ex flag
-_ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE"}
+_ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EIO"}
 
 
 class SimRankError(RuntimeError):
@@ -142,6 +142,8 @@ def lib() -> C.CDLL:
         "simrank_build_index": [vp, P(simrank_index_params)],
         "simrank_index_info": [vp, P(simrank_index_summary)],
         "simrank_index_read": [vp, vp, i64, vp, vp, vp, vp],
+        "simrank_index_save": [vp, C.c_char_p],
+        "simrank_index_load": [vp, C.c_char_p],
         "simrank_batch": [P(vp), i32, P(simrank_query), i32, P(vp), P(vp), P(simrank_stats)],
         "simrank_batch_plan_create": [P(vp), i32, P(simrank_query), i32, P(vp)],
         "simrank_tune_ex": [vp, P(simrank_query), P(simrank_tuning)],
@@ -440,6 +442,17 @@ def simrank_index_info(g: Graph) -> dict:
     s = simrank_index_summary()
     _check(lib().simrank_index_info(g.handle, C.byref(s)))
     return s.asdict()
+
+
+def simrank_index_save(g: Graph, path: str) -> None:
+    """Writes the graph's stitched index to `path`."""
+    _check(lib().simrank_index_save(g.handle, os.fsencode(path)))
+
+
+def simrank_index_load(g: Graph, path: str) -> None:
+    """Makes the index saved at `path` the graph's index (refused, leaving the
+    current index, if the file does not belong to this graph or is damaged)."""
+    _check(lib().simrank_index_load(g.handle, os.fsencode(path)))
 
 
 def simrank_index_read(g: Graph, sigma, with_chain: bool = True):

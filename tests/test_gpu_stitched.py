@@ -167,6 +167,67 @@ def test_stitched_requires_matching_index(small):
     assert e.value.code == S.SIMRANK_EINVAL
 
 
+def test_index_checkpoint_and_resume(small, tmp_path):
+    """An index saved to a file and loaded into a fresh copy of the graph gives
+    the same entries and the same stitched counts (equal to the oracle's);
+    files for another graph, damaged, truncated or too long are refused with
+    the graph's current index kept."""
+    g = small
+    G = S.load_csr(g)
+    info = S.simrank_build_index(G, seg_log2=3, kappa=1.0, c=0.6, seed=ISEED)
+    s = int(np.argsort(g.in_degree())[-5])
+    q = S.make_query(s, seed=SEED, R=3000, mode=S.MODE_STITCHED)
+    want = S.simrank_single_source_ex(G, q)[1]
+    assert np.array_equal(want, O.meet_counts_stitched(g, s, SEED, ISEED, 0.6, 64, 8,
+                                                       O.pool_sizes(g, 1.0), 3000))
+    sig = np.arange(0, info["segments"], 37, dtype=np.int64)
+    before = S.simrank_index_read(G, sig)
+    path = tmp_path / "index.bin"
+    S.simrank_index_save(G, str(path))
+    G2 = S.load_csr(g)
+    with pytest.raises(S.SimRankError) as e:
+        S.simrank_index_save(G2, str(tmp_path / "none.bin"))
+    assert e.value.code == S.SIMRANK_ESTATE
+    S.simrank_index_load(G2, str(path))
+    after = S.simrank_index_read(G2, sig)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    info2 = S.simrank_index_info(G2)
+    for key in ("segments", "levels", "bytes"):
+        assert info2[key] == info[key], key
+    assert np.array_equal(S.simrank_single_source_ex(G2, q)[1], want)
+
+    data = path.read_bytes()
+    damaged = bytearray(data)
+    damaged[128 + (len(data) - 128) // 2] ^= 0x5A
+    cases = {"damaged": bytes(damaged), "truncated": data[:-3], "too_long": data + b"\0"}
+    for name, blob in cases.items():
+        p = tmp_path / f"{name}.bin"
+        p.write_bytes(blob)
+        with pytest.raises(S.SimRankError) as e:
+            S.simrank_index_load(G2, str(p))
+        assert e.value.code == S.SIMRANK_EINVAL, name
+    # the refused loads left the loaded index in place
+    assert np.array_equal(S.simrank_single_source_ex(G2, q)[1], want)
+    # same n and m, one edge moved: another graph
+    src = g.in_src.copy()
+    a = int(np.nonzero(np.diff(g.in_off) > 1)[0][0])
+    row = src[g.in_off[a]:g.in_off[a + 1]]
+    spare = int(next(u for u in range(g.n) if u not in set(row.tolist())))
+    src[g.in_off[a]] = spare
+    other = inputs.CSR(g.n, g.in_off.copy(), src, "one edge moved")
+    G3 = S.load_csr(other)
+    with pytest.raises(S.SimRankError) as e:
+        S.simrank_index_load(G3, str(path))
+    assert e.value.code == S.SIMRANK_EINVAL
+    with pytest.raises(S.SimRankError) as e:
+        S.simrank_index_load(G3, str(tmp_path / "missing.bin"))
+    assert e.value.code == S.SIMRANK_EIO
+    G3.free()
+    G2.free()
+    G.free()
+
+
 @pytest.mark.slow
 def test_c3_stitching_at_scale():
     """Stitching workload at full size: R-MAT n=2^24, avg degree 16 (~2.6e8
