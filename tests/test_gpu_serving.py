@@ -220,6 +220,21 @@ def test_concurrent_submitters_with_groups(served):
     srv.destroy()
 
 
+def test_destroy_finishes_requests_in_flight(served):
+    """Destroying a server with requests still queued and running drains them
+    and returns; the graph then answers queries as before."""
+    g, G = served
+    qs = _requests(g, 6, 77)
+    srv = S.Server(G, max_slots=2, max_R=9502, max_L=64)
+    for q in qs:
+        srv.submit(q)
+    srv.destroy()
+    q = qs[0]
+    a = S.simrank_single_source_ex(G, q)[1]
+    b = S.simrank_single_source_ex(G, q)[1]
+    assert np.array_equal(a, b)
+
+
 def test_two_waits_on_one_ticket(served):
     """Two threads wait on the same ticket: one receives the result (equal to
     the lone query's), the other an EINVAL for the retired ticket."""
