@@ -235,6 +235,44 @@ def test_destroy_finishes_requests_in_flight(served):
     assert np.array_equal(a, b)
 
 
+def test_serving_workload_size_vs_oracle():
+    """The serving workload's graph (R-MAT n = 2^22, average in-degree 16)
+    with its stitched index (2^4-step segments, kappa = 1): a plain request at
+    eps 0.02 (R = 9,502) and a stitched request at eps 0.05 (R = 1,521) served
+    together; their counts on 512 random nodes with in-edges, the 32 highest
+    in-degree nodes, 8 nodes without in-edges and the sources equal the
+    oracle's (plain walks, and stitched walks traversed serially over segments
+    regenerated from the CSR), and each estimate is count / R."""
+    cfg = inputs.C5
+    g = inputs.workload_graph(cfg)
+    G = S.load_csr(g)
+    iseed = 0x2304040150000023
+    S.simrank_build_index(G, seg_log2=4, kappa=1.0, c=cfg["c"], seed=iseed)
+    srcs = [int(x) for x in inputs.sources_by_degree(g, 2, 81)]
+    qp = S.make_query(srcs[0], c=cfg["c"], eps=0.02, delta=cfg["delta"], seed=0x5F10,
+                      walk_cap=cfg["L"])
+    qs = S.make_query(srcs[1], c=cfg["c"], eps=0.05, delta=cfg["delta"], seed=0x5F11,
+                      walk_cap=cfg["L"], mode=S.MODE_STITCHED)
+    srv = S.Server(G, max_slots=4, max_R=9502, max_L=64)
+    tp, ts = srv.submit(qp), srv.submit(qs)
+    op, cp, _ = srv.wait(tp, timeout_s=120.0)
+    os_, cs, _ = srv.wait(ts, timeout_s=120.0)
+    srv.destroy()
+    smp0 = OT.sample_nodes(g, 512, 32, 8, seed=82)
+    P = O.pool_sizes(g, 1.0)
+    Rp, Rs = S.simrank_derive_params(qp, g.n).R, S.simrank_derive_params(qs, g.n).R
+    assert (Rp, Rs) == (9502, 1521)
+    for q, o, c, R in ((qp, op, cp, Rp), (qs, os_, cs, Rs)):
+        smp = np.union1d(smp0, [q.s]).astype(np.int32)
+        if q.mode == S.MODE_STITCHED:
+            want = OT.meet_counts_stitched(g, q.s, q.seed, iseed, cfg["c"], cfg["L"], 16, P, R, smp)
+        else:
+            want = OT.meet_counts_plain(g, q.s, q.seed, cfg["c"], cfg["L"], R, smp)
+        assert np.array_equal(c[smp], want), q.mode
+        assert np.array_equal(o[smp], np.where(smp == q.s, 1.0, want / float(R))), q.mode
+    G.free()
+
+
 def test_two_waits_on_one_ticket(served):
     """Two threads wait on the same ticket: one receives the result (equal to
     the lone query's), the other an EINVAL for the retired ticket."""
