@@ -268,6 +268,43 @@ def test_group_of_32_medium_workload_vs_oracle():
     G.free()
 
 
+def test_batching_workload_graphs_vs_oracle():
+    """Four graphs of the batching workload (R-MAT, n from 6,544 to 573,161,
+    average in-degree 13 to 27) with a query at each of its eps levels (0.05,
+    0.02, 0.01: R = 1,521, 9,502, 38,005; a seed per query) in one captured
+    plan: every query's counts on 256 random nodes with in-edges, the 16
+    highest in-degree nodes, 4 nodes without in-edges and its source equal the
+    oracle's, and its estimate is count / R."""
+    specs = inputs.batch_graph_specs()
+    cfg = inputs.C4
+    picks = (1, 9, 0, 2)
+    gs = [inputs.batch_graph(specs[i]) for i in picks]
+    Gs = [S.load_csr(g) for g in gs]
+    rng = np.random.default_rng(88)
+    qs = []
+    for gi, g in enumerate(gs):
+        act = np.nonzero(g.in_degree() > 0)[0]
+        for k, eps in enumerate(cfg["eps_choices"]):
+            qs.append(S.make_query(int(rng.choice(act)), c=cfg["c"], eps=eps, delta=cfg["delta"],
+                                   seed=0x6B00 + 3 * gi + k, walk_cap=cfg["L"], graph=gi))
+    plan = S.BatchPlan(Gs, qs)
+    plan.run()
+    st = plan.wait()
+    _say(f"batching-workload graphs, 12 queries: {st.ms:.1f} ms, {st.moves} moves")
+    for i, q in enumerate(qs):
+        g = gs[q.graph]
+        R = S.simrank_derive_params(q, g.n).R
+        out, cnt = plan.read(i)
+        smp = np.union1d(OT.sample_nodes(g, 256, 16, 4, seed=89 + i), [q.s]).astype(np.int32)
+        want = OT.meet_counts_plain(g, q.s, q.seed, cfg["c"], cfg["L"], R, smp)
+        assert np.array_equal(cnt[smp], want), i
+        assert np.array_equal(out[smp], np.where(smp == q.s, 1.0, want / float(R))), i
+    assert sorted({S.simrank_derive_params(q, 10).R for q in qs}) == [1521, 9502, 38005]
+    plan.free()
+    for G in Gs:
+        G.free()
+
+
 def test_tile_and_unit_settings_keep_results(graphs):
     """Walks per tile and nodes per unit, set by hand or by the tuner, change
     the work's partition only: plain, stitched and stratified counts, alone and
