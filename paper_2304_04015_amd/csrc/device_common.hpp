@@ -39,6 +39,44 @@ __device__ __forceinline__ T block_excl_sum(T x, T *total) {
     return before + inc - x;
 }
 
+// Cuts entries [0, E1), entry e holding words [joff[e], joff[e + 1]), into
+// tiles from the front, each the longest run [a, b) with b - a <= TJ and
+// joff[b] - joff[a] <= TN; writes the starts to tiles[0 .. count) and returns
+// the count.  Every tile but the last is full in walks (TJ) or holds more than
+// TN - w words, w the largest entry, so the count stays within 1 + E1 / TJ +
+// joff[E1] / (TN - w).  Called by all 64 lanes of one wave (results uniform);
+// needs w <= TN.  Each run's end is found by a 64-way search: the lanes probe
+// 64 points of the open range at once, so a range of up to 64^2 entries takes
+// two rounds of loads.
+__device__ inline uint32_t cut_tiles(const uint32_t *joff, uint32_t E1, uint32_t TJ, uint32_t TN,
+                                     uint32_t *tiles, int lane) {
+    uint32_t a = 0, nt = 0;
+    while (a < E1) {
+        if (lane == 0) tiles[nt] = a;
+        ++nt;
+        const uint32_t base = joff[a];
+        // the run ends at the largest b in [lo, hi] with joff[b] - base <= TN;
+        // lo = a + 1 always qualifies (one entry fits)
+        uint32_t lo = a + 1, hi = min(a + TJ, E1);
+        while (lo < hi) {
+            const uint32_t span = hi - lo;
+            const uint32_t p = lo + (uint32_t)(((uint64_t)span * (uint32_t)(lane + 1)) >> 6);
+            const bool fits = joff[p] - base <= TN;
+            const uint64_t m = __ballot(fits);   // fits holds for a prefix of the lanes
+            const uint32_t k = (uint32_t)__popcll(m);
+            const uint32_t p_last = uni(__shfl(p, (int)(k ? k - 1 : 0), 64));
+            const uint32_t p_next = uni(__shfl(p, (int)(k < 64 ? k : 63), 64));
+            if (k == 64) lo = hi;
+            else {
+                if (k) lo = p_last;
+                hi = p_next - 1;
+            }
+        }
+        a = lo;
+    }
+    return nt;
+}
+
 // The walk's gather of an edge slot.  SRK_EDGE_LOAD selects the cache policy
 // (0: default, 1: non-temporal).
 #ifndef SRK_EDGE_LOAD

@@ -83,15 +83,14 @@ __device__ __forceinline__ uint32_t byte_of(uint32_t w, int q) { return (w >> (8
 // member's walk j has a step and packs the members' positions of walk j step
 // by step: for each step t up to the longest member walk, the word of members
 // with a position at t, then their positions at t in member order.  Cuts the
-// entries into tiles of at most TJ entries and TN words (a boundary wherever
-// the entry index crosses a multiple of TJ or the packed offset a multiple of
-// NW = TN - (G + 1) L; an entry holds at most (G + 1) L words).  (TJ, TN) is
-// the shape of the kernel instance that runs the group.
+// entries into tiles of at most TJ entries and TN words, each the longest run
+// from the previous one's end (cut_tiles; an entry holds at most (G + 1) L
+// words).  (TJ, TN) is the shape of the kernel instance that runs the group.
 __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restrict__ gd) {
     const GroupDesc &d = gd[blockIdx.x];
     const int32_t Rmax = d.Rmax, L = d.L, G = d.G, gw = d.gw;
     const uint32_t TJ = (uint32_t)group_tile_j(group_gw(G), d.wk);
-    const uint32_t NW = (uint32_t)(group_tile_nodes(group_gw(G), d.wk) - (G + 1) * L);
+    const uint32_t TN = (uint32_t)group_tile_nodes(group_gw(G), d.wk);
     const int32_t per = (Rmax + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t j0 = min(Rmax, (int32_t)threadIdx.x * per), j1 = min(Rmax, j0 + per);
     uint32_t cnt = 0, nodes = 0;
@@ -154,19 +153,14 @@ __global__ __launch_bounds__(1024) void k_group_compact(const GroupDesc *__restr
     }
     if (threadIdx.x == 0) d.joff[E1] = total;
     __syncthreads();
-    uint32_t nbound = 0;
-    for (uint32_t e = kb; e < kb + cnt; ++e)
-        nbound += (e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
-    uint32_t n_tiles;
-    uint32_t tb = block_excl_sum(nbound, &n_tiles);
-    for (uint32_t e = kb; e < kb + cnt; ++e)
-        if ((e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
-            d.tiles[tb++] = e;
-    if (threadIdx.x == 0) {
-        d.tiles[n_tiles] = E1;
-        d.meta[0] = E1;
-        d.meta[1] = total;
-        d.meta[2] = n_tiles;
+    if (threadIdx.x < 64) {
+        const uint32_t n_tiles = cut_tiles(d.joff, E1, TJ, TN, d.tiles, (int)threadIdx.x);
+        if (threadIdx.x == 0) {
+            d.tiles[n_tiles] = E1;
+            d.meta[0] = E1;
+            d.meta[1] = total;
+            d.meta[2] = n_tiles;
+        }
     }
 }
 

@@ -126,16 +126,15 @@ __global__ __launch_bounds__(256) void k_source_walks(const QueryDesc *__restric
 // One block per query.  Keeps the walks with at least one step (a walk of
 // length 0 can only meet at step 0, i.e. only the source itself), packs their
 // positions back to back (swc), and cuts the packed list into tiles that fit
-// the meet kernel's LDS: with the kind's shape (TJ walks, TN positions), a tile
-// boundary falls wherever the entry index crosses a multiple of TJ or the
-// packed offset crosses a multiple of NW = TN - L, so a tile holds at most TJ
-// walks and at most NW - 1 + L <= TN positions.
+// the meet kernel's LDS: with the kind's shape (TJ walks, TN positions), each
+// tile is the longest run of walks from the previous one's end that holds at
+// most TJ walks and TN positions (cut_tiles).
 __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ qd) {
     const QueryDesc &d = qd[blockIdx.x];
     if (d.kind >= K_GROUPED) return;   // compacted with its group
     const int32_t R = d.R, L = d.L;
     const uint32_t TJ = (uint32_t)d.tile_j;
-    const uint32_t NW = (uint32_t)(tile_nodes_of(d.kind) - L);
+    const uint32_t TN = (uint32_t)tile_nodes_of(d.kind);
     const int32_t per = (R + blockDim.x - 1) / blockDim.x;
     const int32_t j0 = min(R, (int32_t)threadIdx.x * per), j1 = min(R, j0 + per);
     uint32_t cnt = 0, nodes = 0;
@@ -160,19 +159,14 @@ __global__ __launch_bounds__(1024) void k_compact(const QueryDesc *__restrict__ 
     }
     if (threadIdx.x == 0) d.joff[R1] = total;
     __syncthreads();
-    uint32_t nbound = 0;
-    for (uint32_t e = kb; e < kb + cnt; ++e)
-        nbound += (e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW);
-    uint32_t n_tiles;
-    uint32_t tb = block_excl_sum(nbound, &n_tiles);
-    for (uint32_t e = kb; e < kb + cnt; ++e)
-        if ((e == 0) || (e % TJ == 0) || (d.joff[e] / NW != d.joff[e - 1] / NW))
-            d.tiles[tb++] = e;
-    if (threadIdx.x == 0) {
-        d.tiles[n_tiles] = R1;
-        d.meta[0] = R1;
-        d.meta[1] = total;
-        d.meta[2] = n_tiles;
+    if (threadIdx.x < 64) {
+        const uint32_t n_tiles = cut_tiles(d.joff, R1, TJ, TN, d.tiles, (int)threadIdx.x);
+        if (threadIdx.x == 0) {
+            d.tiles[n_tiles] = R1;
+            d.meta[0] = R1;
+            d.meta[1] = total;
+            d.meta[2] = n_tiles;
+        }
     }
 }
 
