@@ -197,6 +197,15 @@ extern "C" int simrank_index_load(simrank_graph *g, const char *path) {
     if (!(h.c > 0.0 && h.c < 1.0) || h.T != continue_threshold(h.c) || !(h.kappa > 0.0))
         return refuse("decay or pool scale");
     if (h.segments < 0 || h.segments >= (int64_t)NIL) return refuse("segment count");
+    {   // the file's size must be the header's arrays, checked before any allocation
+        const int64_t S = h.segments, L = (int64_t)1 << h.seg_log2;
+        const int64_t want = (int64_t)sizeof(h) + 8 * ((int64_t)h.n + 1) + 4 * S * L + S + 4 * S +
+                             4 * S * h.width;
+        if (std::fseek(f, 0, SEEK_END) != 0) return refuse("cannot seek");
+        const long size = std::ftell(f);
+        if (size < 0 || (int64_t)size != want) return refuse("size does not match its header");
+        if (std::fseek(f, (long)sizeof(h), SEEK_SET) != 0) return refuse("cannot seek");
+    }
     SRK_HIP(hipSetDevice(g->device));
     hipStream_t st = g->stream;
     SRK_HIP(hipStreamSynchronize(st));
