@@ -164,9 +164,8 @@ extern "C" int simrank_batch_plan_create_ex(simrank_graph *const *graphs, int32_
                 RL += (int64_t)ps[i].R * ps[i].L;
             }
             const Graph *g = graphs[qs[m[0]].graph];
-            int64_t vb = default_unit_nodes(g);
-            if (modes[m[0]] == SIMRANK_MODE_STRATIFIED && m.size() > 8)
-                vb = std::min<int64_t>(vb, GROUP_STRAT32_VB);   // as describe_group sets it
+            const int64_t vb = group_unit_nodes(g->n_active, (int32_t)m.size(),
+                                                walk_kind(modes[m[0]]));   // as describe_group sets it
             const int64_t ub = (int64_t)group_max_tiles(Rmax, RL, ps[m[0]].L, (int32_t)m.size(),
                                                         walk_kind(modes[m[0]])) *
                                ((g->n_active + vb - 1) / vb);

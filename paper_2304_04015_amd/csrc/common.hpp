@@ -281,6 +281,9 @@ inline size_t group_units_words(int32_t ng) { return GROUP_LISTS * ((size_t)ng +
 inline int64_t group_pos_words(int64_t Rmax, int64_t sum_RL, int32_t L) { return sum_RL + Rmax * L; }
 // Tiles of a group's compacted walks, at most.
 int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int32_t wk);
+// Nodes per work unit of a group of G members with walks wk on a graph with
+// n_active nodes that have in-edges (the lone queries' tuning does not apply).
+int32_t group_unit_nodes(int32_t n_active, int32_t G, int32_t wk);
 // Fills a group's descriptor (all but its compaction buffers jj .. meta) from
 // the descriptors of its G members (kinds K_GROUPED, K_GROUPED_STITCHED or
 // K_GROUPED_STRAT, buffers attached).

@@ -628,6 +628,21 @@ int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int3
     return (int32_t)(2 + Rmax / group_tile_j(GW, wk) + group_pos_words(Rmax, sum_RL, L) / NW);
 }
 
+// A unit's pairs are (its vb nodes) x (the tile's entries), and the block
+// waits at the unit's end for its longest pair.  A group's tile holds few
+// entries (every entry carries all members' positions) and its pairs walk
+// until the longest member walk ends, so small units spend much of their time
+// in that wait: on the n = 2^22 graph a 32-member group took 855 ms with 256
+// nodes per unit, 894 with 128, 971 with 64 and 1121 with 32 (stitched: 994 /
+// 1049 / 1161 / 1366).  Groups therefore take the largest unit that still
+// leaves 64 chunks of nodes, whatever the lone queries were tuned to.
+int32_t group_unit_nodes(int32_t n_active, int32_t G, int32_t wk) {
+    int32_t vb = MEET_VB;
+    while (vb > 32 && (n_active + vb - 1) / vb < 64) vb >>= 1;
+    if (wk == 2 && G > 8) vb = std::min(vb, GROUP_STRAT32_VB);   // the LDS sums' node limit
+    return vb;
+}
+
 void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
     const QueryDesc &d0 = *members[0];
     *gd = GroupDesc{};
@@ -635,15 +650,11 @@ void describe_group(const QueryDesc *const *members, int32_t G, GroupDesc *gd) {
     gd->E = d0.E;
     gd->active = d0.active;
     gd->n_active = d0.n_active;
-    gd->vb = d0.vb;
-    gd->n_chunks = d0.n_chunks;
     gd->G = G;
     gd->gw = (G + 3) / 4;
     gd->wk = d0.kind == K_GROUPED_STITCHED ? 1 : d0.kind == K_GROUPED_STRAT ? 2 : 0;
-    if (gd->wk == 2 && G > 8 && gd->vb > GROUP_STRAT32_VB) {   // the LDS sums' node limit
-        gd->vb = GROUP_STRAT32_VB;
-        gd->n_chunks = (gd->n_active + gd->vb - 1) / gd->vb;
-    }
+    gd->vb = group_unit_nodes(d0.n_active, G, gd->wk);
+    gd->n_chunks = (gd->n_active + gd->vb - 1) / gd->vb;
     gd->ix = d0.ix;
     gd->tab = d0.tab;
     gd->sa = d0.sa;
