@@ -222,8 +222,12 @@ inline size_t units_words(int32_t nq) { return (size_t)N_KINDS * ((size_t)nq + 1
 constexpr int GROUP_MAX = 32;
 constexpr int32_t K_GROUPED = N_KINDS, K_GROUPED_STITCHED = N_KINDS + 1, K_GROUPED_STRAT = N_KINDS + 2;
 // Groups of more than 8 stratified queries keep their 64-bit weighted sums for
-// at most this many nodes per work unit.
-constexpr int GROUP_STRAT32_VB = 64;
+// at most this many nodes per work unit (64 KB of LDS at 256 nodes; their tile
+// is the smaller for it).
+#ifndef SRK_GROUP_STRAT32_VB
+#define SRK_GROUP_STRAT32_VB 256
+#endif
+constexpr int GROUP_STRAT32_VB = SRK_GROUP_STRAT32_VB;
 // Kinds whose walks are the stratified estimator's (weighted sums, not counts).
 __host__ __device__ inline bool strat_kind(int32_t kind) { return kind == K_STRAT || kind == K_GROUPED_STRAT; }
 

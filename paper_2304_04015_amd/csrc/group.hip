@@ -41,7 +41,7 @@ namespace {
 #define SRK_GROUP32_TILE_NODES 28672
 #endif
 #ifndef SRK_GROUP32_STRAT_TILE_NODES
-#define SRK_GROUP32_STRAT_TILE_NODES 28672
+#define SRK_GROUP32_STRAT_TILE_NODES 20480
 #endif
 #ifndef SRK_GROUP_STRAT_TILE_J
 #define SRK_GROUP_STRAT_TILE_J 1024
