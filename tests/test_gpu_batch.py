@@ -385,8 +385,9 @@ def test_stratified_groups_equal_lone(graphs):
 def test_stratified_group_full_size(nq):
     """Stratified queries with Algorithm 2's z and Algorithm 1's cap on a
     2^16-node R-MAT graph (N = 14,825, phi = 43) and one seed: one group of 8
-    and one of 13 (whose sums are kept for 64 nodes per unit), each member's
-    weighted sums equal to its lone run's."""
+    and one of 13 (the instance for more than 8 members, its 64-bit sums in LDS
+    for 256 nodes per unit), each member's weighted sums equal to its lone
+    run's."""
     g = inputs.rmat_in(16, 16 << 16, seed=72)
     G = S.load_csr(g)
     srcs = [int(x) for x in inputs.sources_with_in_edges(g, nq, 75)]
