@@ -450,6 +450,10 @@ static void server_loop(simrank_server *S) {
                     if (o->mode != SIMRANK_MODE_STRATIFIED && same_walks(o, r)) return true;
                 return false;
             };
+            // set when a group could not get the memory of two members: the
+            // requests then go alone, so that a pool too small for two of
+            // them cannot keep them waiting for each other for ever
+            bool no_room = false;
             if (S->gmax >= 2 && !S->grp.busy) {
                 for (Request *head : S->queue) {
                     if (head->mode == SIMRANK_MODE_STRATIFIED || walks_running(head)) continue;
@@ -471,6 +475,7 @@ static void server_loop(simrank_server *S) {
                             --S->inflight;
                         }
                         group.clear();
+                        no_room = true;
                     } else {
                         group.resize(kept);
                         for (Request *r : group)
@@ -481,18 +486,19 @@ static void server_loop(simrank_server *S) {
             }
             // lone admission, oldest first; with groups, a request whose walks
             // a running request or a group just formed shares, or that has a
-            // partner waiting, waits
+            // partner waiting (unless a group found no room), waits
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request *r = *it;
                 bool wait = false;
                 if (S->gmax >= 2 && r->mode != SIMRANK_MODE_STRATIFIED) {
                     wait = walks_running(r);
                     for (const Request *o : group) wait |= same_walks(o, r);
-                    for (const Request *o : S->queue)
-                        if (o != r && same_walks(o, r)) {
-                            wait = true;
-                            break;
-                        }
+                    if (!no_room)
+                        for (const Request *o : S->queue)
+                            if (o != r && same_walks(o, r)) {
+                                wait = true;
+                                break;
+                            }
                 }
                 if (wait) {
                     ++it;

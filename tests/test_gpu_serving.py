@@ -414,6 +414,26 @@ def test_memory_admission_per_request(served):
     srv.destroy()
 
 
+def test_groups_in_a_pool_for_one_request(served):
+    """Group admission with a pool that holds one request of the largest R:
+    same-walk requests cannot start together, so they run one after another
+    instead of waiting for a group (each wait has a time limit), and each
+    equals its lone call."""
+    g, G = served
+    probe = S.Server(G, max_slots=1, max_R=9502, max_L=64)
+    big = probe.info()["slot_bytes"]
+    probe.destroy()
+    srv = S.Server(G, max_slots=4, max_R=9502, max_L=64, hbm_budget=big, group_max=8)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    qs = [S.make_query(int(act[i]), c=0.6, eps=0.02, seed=0x6400) for i in range(3)]
+    tickets = [srv.submit(q) for q in qs]
+    for t, q in zip(tickets, qs):
+        assert np.array_equal(srv.wait(t, timeout_s=120.0, want_out=False)[1],
+                              S.simrank_single_source_ex(G, q)[1])
+    assert srv.counts()["groups"] == 0 and srv.load()["inflight_peak"] == 1
+    srv.destroy()
+
+
 def test_entry_reuse_with_other_sizes(served):
     """Ring entries reused many times by requests of other sizes and kinds
     (plain and stitched with R = 1521 or 9502, stratified with N = 1,150;
