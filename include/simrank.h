@@ -443,16 +443,18 @@ typedef struct simrank_server_params {
     int32_t max_slots;    /* 1..64 requests in flight at once */
     int32_t max_R;        /* largest R (stratified: N) a request may need */
     int32_t max_L;        /* largest walk cap (stratified: phi) a request may use */
-    int32_t group_max;    /* 0 or 1: every request runs alone.  2..32: a plain
-                             or stitched request waits while a request with the
-                             same mode, seed, c and cap runs; those that then
-                             wait together are admitted as one query group of
-                             up to group_max, which takes each walk (v, j) once
-                             for all of them (Section 3's walk (v, j) does not
-                             depend on the source); one group runs at a time,
-                             beside the lone requests.  A grouped request's
-                             stats are its share (1/G) of its group's work and
-                             the group's device time. */
+    int32_t group_max;    /* 0 or 1: every request runs alone.  2..32: a
+                             request waits while a request with the same walks
+                             runs (mode, seed, c and cap; stratified also N and
+                             z); those that then wait together are admitted as
+                             one query group of up to group_max, which takes
+                             each walk (v, j) once for all of them (Section 3's
+                             walk (v, j) does not depend on the source); one
+                             group runs at a time, beside the lone requests.
+                             If the pool cannot hold two of them, they run one
+                             after another.  A grouped request's stats are its
+                             share (1/G) of its group's work and the group's
+                             device time. */
     int64_t hbm_budget;   /* device bytes for the requests in flight (the pool);
                              0: half the free memory.  At most max_slots requests
                              of (max_R, max_L) are reserved for. */

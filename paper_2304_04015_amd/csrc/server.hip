@@ -115,6 +115,7 @@ struct Request {
     bool grouped = false;
     int32_t group_size = 1;
     int32_t group_pos = 0;
+    uint64_t zbits = 0;     // stratified: the bits of Algorithm 2's z (part of its walks)
 };
 
 // Pinned host buffers for one request's results, with the copy's event.
@@ -136,13 +137,18 @@ struct GroupRun {
     uint32_t *units = nullptr, *gunits = nullptr;
     unsigned long long *counters = nullptr;
     char *buffers = nullptr;
+    StratTab *tabs_host = nullptr;       // pinned [GROUP_MAX] class tables of stratified members
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<Request *> members;
     bool busy = false;
 };
 
+// Requests whose walks are the same (a group walks them once for all): mode,
+// seed, continue threshold and cap; stratified also N and z, which fix the
+// length classes.
 bool same_walks(const Request *a, const Request *b) {
-    return a->mode == b->mode && a->q.seed == b->q.seed && a->p.T == b->p.T && a->p.L == b->p.L;
+    return a->mode == b->mode && a->q.seed == b->q.seed && a->p.T == b->p.T && a->p.L == b->p.L &&
+           (a->mode != SIMRANK_MODE_STRATIFIED || (a->p.R == b->p.R && a->zbits == b->zbits));
 }
 
 int kind_of(int mode) {
@@ -314,7 +320,21 @@ static int launch_group(simrank_server *S, const std::vector<Request *> &rs, hip
     for (int32_t i = 0; i < G; ++i) {
         QueryDesc &d = gr.desc_host[i];
         d = rs[i]->d;
-        d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED : K_GROUPED;
+        d.kind = d.kind == K_STITCHED ? K_GROUPED_STITCHED
+                 : d.kind == K_STRAT  ? K_GROUPED_STRAT
+                                      : K_GROUPED;
+        if (rs[i]->mode == SIMRANK_MODE_STRATIFIED) {
+            // the member's class table, staged in pinned memory that the next
+            // group rewrites only after this one has finished
+            StratParams sp;
+            const int rc = strat_params(&rs[i]->q, g->n, &sp, gr.tabs_host + i);
+            if (rc) return rc;
+            d.z = sp.z;
+            d.sa = sp.sa;
+            d.sb = sp.sb;
+            SRK_HIP(hipMemcpyAsync((void *)d.tab, gr.tabs_host + i, sizeof(StratTab),
+                                   hipMemcpyHostToDevice, st));
+        }
         mem[i] = &d;
         sum_RL += (int64_t)d.R * d.L;
     }
@@ -447,7 +467,7 @@ static void server_loop(simrank_server *S) {
             // device works on the previous ones.
             auto walks_running = [&](const Request *r) {
                 for (const Request *o : running)
-                    if (o->mode != SIMRANK_MODE_STRATIFIED && same_walks(o, r)) return true;
+                    if (same_walks(o, r)) return true;
                 return false;
             };
             // set when a group could not get the memory of two members: the
@@ -456,7 +476,7 @@ static void server_loop(simrank_server *S) {
             bool no_room = false;
             if (S->gmax >= 2 && !S->grp.busy) {
                 for (Request *head : S->queue) {
-                    if (head->mode == SIMRANK_MODE_STRATIFIED || walks_running(head)) continue;
+                    if (walks_running(head)) continue;
                     for (Request *r : S->queue)
                         if ((int32_t)group.size() < S->gmax && same_walks(head, r)) group.push_back(r);
                     if (group.size() < 2) {
@@ -490,7 +510,7 @@ static void server_loop(simrank_server *S) {
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request *r = *it;
                 bool wait = false;
-                if (S->gmax >= 2 && r->mode != SIMRANK_MODE_STRATIFIED) {
+                if (S->gmax >= 2) {
                     wait = walks_running(r);
                     for (const Request *o : group) wait |= same_walks(o, r);
                     if (!no_room)
@@ -610,6 +630,7 @@ static void server_release(simrank_server *S) {
     if (S->copy) (void)hipStreamSynchronize(S->copy);
     GroupRun &gr = S->grp;
     if (gr.desc_host) (void)hipHostFree(gr.desc_host);
+    if (gr.tabs_host) (void)hipHostFree(gr.tabs_host);
     if (gr.gdesc_host) (void)hipHostFree(gr.gdesc_host);
     device_free(gr.desc_dev);
     device_free(gr.gdesc_dev);
@@ -704,13 +725,19 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
     S->gmax = gmax;
     if (!rc && gmax >= 2) {   // the group's own buffers
         GroupRun &gr = S->grp;
-        GroupDesc gd{};
-        gd.Rmax = p->max_R;
-        gd.L = p->max_L;
-        gd.G = gmax;
-        gd.gw = (gmax + 3) / 4;
-        const int64_t sum_RL = (int64_t)gmax * p->max_R * p->max_L;
-        const size_t gb = group_buffers(&gd, sum_RL, nullptr);
+        // the buffers of the largest group of any walks and size (stratified
+        // groups have the smaller tiles, so the most of them)
+        size_t gb = 0;
+        for (int32_t wk = 0; wk < 3; ++wk)
+            for (int32_t G = 2; G <= gmax; ++G) {
+                GroupDesc gd{};
+                gd.Rmax = p->max_R;
+                gd.L = p->max_L;
+                gd.G = G;
+                gd.gw = (G + 3) / 4;
+                gd.wk = wk;
+                gb = std::max(gb, group_buffers(&gd, (int64_t)G * p->max_R * p->max_L, nullptr));
+            }
         rc = device_alloc((void **)&gr.buffers, gb, nullptr);
         if (!rc) rc = device_alloc((void **)&gr.desc_dev, sizeof(QueryDesc) * gmax, nullptr);
         if (!rc) rc = device_alloc((void **)&gr.gdesc_dev, sizeof(GroupDesc), nullptr);
@@ -719,6 +746,7 @@ extern "C" int simrank_server_create(simrank_graph *g, const simrank_server_para
         if (!rc) rc = device_alloc((void **)&gr.counters, 8 * 8, nullptr);
         hip(hipHostMalloc((void **)&gr.desc_host, sizeof(QueryDesc) * gmax, hipHostMallocDefault));
         hip(hipHostMalloc((void **)&gr.gdesc_host, sizeof(GroupDesc), hipHostMallocDefault));
+        hip(hipHostMalloc((void **)&gr.tabs_host, sizeof(StratTab) * gmax, hipHostMallocDefault));
         hip(hipEventCreate(&gr.ev0));
         hip(hipEventCreate(&gr.ev1));
     }
@@ -773,6 +801,11 @@ extern "C" int simrank_server_submit(simrank_server *S, const simrank_query *q, 
     if (!rc && (q->s < 0 || q->s >= S->g->n)) rc = fail(SIMRANK_EINVAL, "source out of range");
     if (!rc && (r->p.R > S->prm.max_R || r->p.L > S->prm.max_L))
         rc = fail(SIMRANK_EINVAL, "query needs R or L beyond the server's maximum");
+    if (!rc && r->mode == SIMRANK_MODE_STRATIFIED) {
+        StratParams sp;
+        rc = strat_params(q, S->g->n, &sp, nullptr);
+        if (!rc) std::memcpy(&r->zbits, &sp.z, sizeof(r->zbits));
+    }
     if (!rc && r->mode == SIMRANK_MODE_STITCHED && (!S->g->index || S->g->index->T != r->p.T))
         rc = fail(SIMRANK_ESTATE, "stitched query without a matching index");
     if (!rc) {

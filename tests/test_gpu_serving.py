@@ -346,6 +346,37 @@ def test_stratified_and_mixed_requests(served):
     srv.destroy()
 
 
+def test_stratified_requests_in_groups(served):
+    """group_max = 16: stratified requests that share the seed, z and phi are
+    admitted as query groups, which take walk j of v (its slot and class,
+    Algorithms 1-2) once for all members; a group of more than 8 runs on the
+    instance that keeps its 64-bit sums in LDS.  One request with another z
+    and one with another seed run alone beside them.  Every member's weighted sums and both estimates
+    equal its lone call's bit for bit, and one member's sums equal the
+    oracle's."""
+    g, G = served
+    rng = np.random.default_rng(53)
+    act = np.nonzero(g.in_degree() > 0)[0]
+    srcs = [int(x) for x in rng.choice(act, 15, replace=False)]
+    qs = [S.make_stratified_query(s, c=0.6, eps=0.05, seed=0x5F80, z=1200, phi=12) for s in srcs[:13]]
+    qs.append(S.make_stratified_query(srcs[13], c=0.6, eps=0.05, seed=0x5F80, z=900, phi=12))
+    qs.append(S.make_stratified_query(srcs[14], c=0.6, eps=0.05, seed=0x5F81, z=1200, phi=12))
+    srv = S.Server(G, max_slots=16, max_R=9502, max_L=64, group_max=16)
+    tickets = [srv.submit(q) for q in qs]
+    ws = []
+    for i, (t, q) in enumerate(zip(tickets, qs)):
+        o, on, w, info = srv.wait_stratified(t, timeout_s=120.0)
+        o1, on1, w1, _ = S.simrank_single_source_stratified(G, q)
+        assert np.array_equal(w, w1) and np.array_equal(o, o1) and np.array_equal(on, on1), i
+        ws.append(w)
+    P = O.strat_params(g.n, 0.6, 0.05, z=1200.0, phi=12)
+    assert np.array_equal(ws[3], OT.strat_sums(g, qs[3].s, qs[3].seed, P, np.arange(g.n)))
+    k = srv.counts()
+    assert k["done"] == len(qs) and k["failed"] == 0
+    assert k["groups"] >= 1 and k["grouped"] >= 2 * k["groups"], k
+    srv.destroy()
+
+
 def test_arrivals_join_running_work(served):
     """Continuous batching: requests that arrive while others run are admitted
     at once (ring entries and memory are free) rather than after the running
