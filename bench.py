@@ -136,9 +136,9 @@ def parse():
                     help="grouped: number of same-seed queries on the medium graph")
     ap.add_argument("--group-kind", default="plain", choices=["plain", "stratified"],
                     help="grouped: plain queries (groups of up to 32) or stratified ones (up to 8)")
-    ap.add_argument("--served-mode", default="stitched", choices=["stitched", "plain"],
+    ap.add_argument("--served-mode", default="stitched", choices=["stitched", "plain", "stratified"],
                     help="serving: walks of the requests (stitched through the resident index, "
-                         "or plain)")
+                         "plain, or Algorithms 1-2's stratified estimator with its own z and cap)")
     ap.add_argument("--shared-seed", action="store_true",
                     help="batching: one walk seed per graph instead of one per query, so that "
                          "the queries of a graph share their walks from every node (query groups)")
@@ -986,47 +986,74 @@ def bench_serving(args):
     rng = np.random.default_rng(31)
     deg = g.in_degree().astype(np.float64)
 
+    strat = args.served_mode == "stratified"
+
     def make(i):
         s = int(rng.choice(g.n, p=deg / deg.sum()))
         seed = 0x2304040150000500 + (0 if args.group_max >= 2 else i)
-        return S.make_query(s, c=cfg["c"], eps=float(rng.choice(cfg["eps_choices"])),
-                            delta=cfg["delta"], seed=seed, walk_cap=cfg["L"],
+        eps = float(rng.choice(cfg["eps_choices"]))
+        if strat:                       # Algorithm 2's z and Algorithm 1's cap
+            return S.make_stratified_query(s, c=cfg["c"], eps=eps, seed=seed)
+        return S.make_query(s, c=cfg["c"], eps=eps, delta=cfg["delta"], seed=seed,
+                            walk_cap=cfg["L"],
                             mode=S.MODE_STITCHED if args.served_mode == "stitched"
                             else S.MODE_PLAIN)
 
     # the index's segment length and the work partition, chosen by the tuners
     # on one request of the workload (the index left built is the fastest one)
-    tq = make(0)
-    tq.eps = 0.02                     # the larger R of the mix
-    tq.mode = S.MODE_STITCHED         # the index tuner times stitched queries
+    s0 = int(rng.choice(g.n, p=deg / deg.sum()))
+    _ = rng.choice(cfg["eps_choices"])        # the draws of one request, as make() takes them
+    tq = S.make_query(s0, c=cfg["c"], eps=0.02, delta=cfg["delta"], seed=0x2304040150000500,
+                      walk_cap=cfg["L"], mode=S.MODE_STITCHED)   # the larger R of the mix;
+                                                                  # stitched for the index tuner
     index_choice, index_ms = S.simrank_tune_index(G, tq, seg_log2=(2, 3, 4), kappa=1.0,
                                                   c=cfg["c"], seed=0x2304040150000023)
+    # the unit / tile tuner times plain or stitched queries (stratified
+    # requests keep the graph's default partition)
     tq.mode = S.MODE_STITCHED if args.served_mode == "stitched" else S.MODE_PLAIN
-    tuning = S.simrank_tune_ex(G, tq)
+    tuning = S.simrank_tune_ex(G, tq) if not strat else {}
+    # the largest R (stratified: N) and cap of the mix size the workspace and the server
+    if strat:
+        sps = [S.simrank_derive_stratified(S.make_stratified_query(0, c=cfg["c"], eps=e), g.n)
+               for e in cfg["eps_choices"]]
+        max_R, max_L = max(p.N for p in sps), max(p.phi for p in sps)
+    else:
+        max_R, max_L = 9502, cfg["L"]
     # the requests: one list, replayed one at a time (the plain capacity) and
     # into the server at every load, so that every rate covers the same work
     warm = [make(i) for i in range(2)]
     cap_q = [make(1000 + i) for i in range(args.requests)]
-    ws = S.simrank_workspace_create(G, 9502, cfg["L"])
+    ws = S.simrank_workspace_create(G, max_R, max_L)
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
     cnt = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    out_n = torch.empty(g.n, dtype=torch.float64, device="cuda") if strat else None
+    wsum = torch.empty(g.n, dtype=torch.int64, device="cuda") if strat else None
     stream = torch.cuda.Stream()
+
+    def run_lone(q):
+        if strat:
+            S.simrank_stratified_async(G, q, ws, out, out_n, wsum, stream)
+        else:
+            S.simrank_single_source_async(G, q, ws, out, cnt, stream)
+        return S.simrank_workspace_stats(ws)
+
     for q in warm:
-        S.simrank_single_source_async(G, q, ws, out, cnt, stream)
-        S.simrank_workspace_stats(ws)
+        run_lone(q)
     t1 = time.perf_counter()
     steps = 0
     kmoves, kms = 0, 0.0
     lone_counts = []
     for i, q in enumerate(cap_q):
-        S.simrank_single_source_async(G, q, ws, out, cnt, stream)
-        st = S.simrank_workspace_stats(ws)
+        st = run_lone(q)
         steps += st.moves + st.tail_steps + st.source_moves
         kmoves += st.moves + st.tail_steps
         kms += st.meet_ms
         _ = out.cpu()                       # results to host, as a served request has
+        if strat:
+            _ = out_n.cpu()
         if i < 4:
-            lone_counts.append(cnt.cpu().numpy().view(np.uint32).copy())
+            lone_counts.append(wsum.cpu().numpy().view(np.uint64).copy() if strat
+                               else cnt.cpu().numpy().view(np.uint32).copy())
     plain_s = time.perf_counter() - t1
     capacity = len(cap_q) / plain_s
     plain_steps_per_s = steps / plain_s
@@ -1036,7 +1063,7 @@ def bench_serving(args):
     gather = S.simrank_roofline_gather(footprint, 8, dependent=False)
     kernel_rate = kmoves / (kms / 1e3)
     grouped = args.group_max >= 2
-    srv = S.Server(G, max_slots=max(16, args.group_max), max_R=9502, max_L=cfg["L"],
+    srv = S.Server(G, max_slots=max(16, args.group_max), max_R=max_R, max_L=max_L,
                    group_max=args.group_max)
     levels = []
     served_equal = True
@@ -1057,7 +1084,11 @@ def bench_serving(args):
             tickets.append(srv.submit(q))
         lat, qwait, wsteps = [], [], 0
         for i, t in enumerate(tickets):
-            _, c, info = srv.wait(t, timeout_s=300.0, want_counts=i < len(lone_counts))
+            if strat:
+                _, _, c, info = srv.wait_stratified(t, timeout_s=300.0)
+                c = c if i < len(lone_counts) else None
+            else:
+                _, c, info = srv.wait(t, timeout_s=300.0, want_counts=i < len(lone_counts))
             if c is not None:
                 served_equal &= bool(np.array_equal(c, lone_counts[i]))
             lat.append(info.latency_s)
