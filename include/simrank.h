@@ -36,9 +36,9 @@
  *     "device" pointers are HIP device memory on the graph's device.
  *   - A graph (and its index, once built) is immutable and may be queried from
  *     several threads at once; a workspace is used by one call at a time.
- *     The calls that change a graph (simrank_build_index, the tuners,
- *     simrank_set_tuning, simrank_free_graph) must not overlap other calls on
- *     it.
+ *     The calls that change a graph (simrank_build_index,
+ *     simrank_index_load, the tuners, simrank_set_tuning, simrank_free_graph)
+ *     must not overlap other calls on it.
  */
 #ifndef SIMRANK_H
 #define SIMRANK_H
