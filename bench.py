@@ -70,15 +70,42 @@ STITCH_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stitching_rmat24.json")
 SEG_SLOTS = 2   # segments in flight per lane of the index build's walk kernel
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without its comments and blank-line and trailing-space
+    differences: what the compiler sees of the code (string and character
+    literals kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":                       # a literal: copy it whole
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_fingerprint() -> str:
-    """sha256 (16 hex digits) of the sources the walk kernels are built from
-    (the meet kernels and the index build)."""
+    """sha256 (16 hex digits) of the code, comments left out, of the sources the
+    walk kernels are built from (the meet kernels and the index build)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_04015_amd", "csrc")
-    h = b"".join(open(os.path.join(csrc, f), "rb").read()
-                 for f in ("query.hip", "group.hip", "index.hip", "device_common.hpp", "philox.hpp",
-                           "common.hpp"))
-    return hashlib.sha256(h).hexdigest()[:16]
+    h = "\n".join(strip_comments(open(os.path.join(csrc, f)).read())
+                  for f in ("query.hip", "group.hip", "index.hip", "device_common.hpp", "philox.hpp",
+                            "common.hpp"))
+    return hashlib.sha256(h.encode()).hexdigest()[:16]
 
 
 def measured_traffic(path: str, kernel: str = None):

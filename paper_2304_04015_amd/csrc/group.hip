@@ -628,11 +628,11 @@ int32_t group_max_tiles(int64_t Rmax, int64_t sum_RL, int32_t L, int32_t G, int3
     return (int32_t)(2 + Rmax / group_tile_j(GW, wk) + group_pos_words(Rmax, sum_RL, L) / NW);
 }
 
-// A unit's pairs are (its vb nodes) x (the tile's entries), and the block
-// waits at the unit's end for its longest pair.  A group's tile holds few
-// entries (every entry carries all members' positions) and its pairs walk
-// until the longest member walk ends, so small units spend much of their time
-// in that wait: on the n = 2^22 graph a 32-member group took 855 ms with 256
+// A unit's pairs are (its vb nodes) x (the tile's entries); each unit has
+// fixed work (the claim, three barriers, staging its nodes, flushing its
+// counters, the wait for its longest pair).  A group's tile holds few entries
+// (every entry carries all members' positions), so small units pay that work
+// over few pairs: on the n = 2^22 graph a 32-member group took 855 ms with 256
 // nodes per unit, 894 with 128, 971 with 64 and 1121 with 32 (stitched: 994 /
 // 1049 / 1161 / 1366).  Groups therefore take the largest unit that still
 // leaves 64 chunks of nodes, whatever the lone queries were tuned to.

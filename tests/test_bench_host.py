@@ -32,6 +32,18 @@ def test_traffic_only_for_the_current_kernel_sources(tmp_path):
     assert bench.measured_traffic(str(multi), "k_c") is None
 
 
+def test_fingerprint_ignores_comments_only():
+    """The counters stay valid across comment edits (the compiler sees the
+    same code) and not across code edits; literals keep their slashes."""
+    code = 'int f(int x) {\n    return x + 1;   // one more\n}\n/* a\n block */\nconst char *s = "a // b /* c */";\n'
+    same = '// header\nint f(int x) {\n\n    return x + 1;\n}\nconst char *s = "a // b /* c */";  \n'
+    other = code.replace("x + 1", "x + 2")
+    assert bench.strip_comments(code) == bench.strip_comments(same)
+    assert bench.strip_comments(code) != bench.strip_comments(other)
+    assert '"a // b /* c */"' in bench.strip_comments(code)
+    assert "one more" not in bench.strip_comments(code) and "block" not in bench.strip_comments(code)
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
